@@ -1,0 +1,177 @@
+"""Tetrahedral mesh generators (Kuhn split of structured boxes).
+
+Every generator returns positively oriented linear tetrahedra.  The paper
+runs on unstructured tetrahedral meshes (Introduction; Section 6); these
+synthetic stand-ins reproduce their structure: linear tets, about 24 tets
+per interior node and 15 node neighbours, and for the jittered cube a
+random perturbation of the interior nodes.
+
+Layouts (host numpy arrays):
+  xyz   float64 [n_nodes, 3]
+  tets  int32   [n_elems, 4]   vertex ids, det[x1-x0, x2-x0, x3-x0] > 0
+Node numbering is lexicographic over the lattice (i, j, k) with k fastest,
+restricted to the nodes that active cells touch.  Cells are enumerated in
+the same lexicographic order, six tets per cell.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from itertools import permutations
+
+import numpy as np
+
+
+@dataclass
+class Mesh:
+    xyz: np.ndarray           # float64 [n_nodes, 3]
+    tets: np.ndarray          # int32 [n_elems, 4]
+    name: str = "mesh"
+    h: float = 0.0            # nominal cell size (smallest lattice spacing)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_elems(self) -> int:
+        return int(self.tets.shape[0])
+
+
+def _kuhn_offsets():
+    """Six Kuhn tets of the unit cube: paths 0 -> e_p0 -> e_p0+e_p1 -> (1,1,1).
+
+    Odd permutations produce negatively oriented tets; their last two
+    vertices are swapped so that every tet is positively oriented.
+    """
+    tets = []
+    for perm in permutations(range(3)):
+        v = [np.zeros(3, dtype=np.int64)]
+        for ax in perm:
+            nxt = v[-1].copy()
+            nxt[ax] += 1
+            v.append(nxt)
+        m = np.stack([v[1] - v[0], v[2] - v[0], v[3] - v[0]], axis=1)
+        if np.linalg.det(m) < 0:
+            v[2], v[3] = v[3], v[2]
+        tets.append(np.stack(v))
+    return np.stack(tets)      # [6, 4, 3] integer corner offsets
+
+
+def kuhn_box(shape, lo, hi, cell_mask=None, name="box") -> Mesh:
+    """Kuhn split of an (nx, ny, nz) lattice of cells spanning [lo, hi].
+
+    cell_mask (bool [nx, ny, nz]) selects active cells; nodes not touched by
+    any active cell are dropped and the rest renumbered in lattice order.
+    """
+    nx, ny, nz = (int(s) for s in shape)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    if cell_mask is None:
+        cell_mask = np.ones((nx, ny, nz), dtype=bool)
+    offs = _kuhn_offsets()
+
+    ci, cj, ck = np.nonzero(cell_mask)          # lexicographic, k fastest
+    corner = np.stack([ci, cj, ck], axis=1)     # [n_cells, 3]
+    # lattice coordinates of the 6x4 vertices of each cell
+    lat = corner[:, None, None, :] + offs[None, :, :, :]          # [nc, 6, 4, 3]
+    lat = lat.reshape(-1, 4, 3)
+    lin = (lat[..., 0] * (ny + 1) + lat[..., 1]) * (nz + 1) + lat[..., 2]
+
+    used = np.zeros((nx + 1) * (ny + 1) * (nz + 1), dtype=bool)
+    used[lin.ravel()] = True
+    new_id = -np.ones(used.size, dtype=np.int64)
+    new_id[used] = np.arange(int(used.sum()))
+    tets = new_id[lin].astype(np.int32)
+
+    idx = np.nonzero(used)[0]
+    i = idx // ((ny + 1) * (nz + 1))
+    j = (idx // (nz + 1)) % (ny + 1)
+    k = idx % (nz + 1)
+    step = (hi - lo) / np.array([nx, ny, nz], dtype=np.float64)
+    xyz = np.stack([lo[0] + i * step[0], lo[1] + j * step[1], lo[2] + k * step[2]], axis=1)
+    mesh = Mesh(xyz=np.ascontiguousarray(xyz), tets=np.ascontiguousarray(tets),
+                name=name, h=float(step.min()),
+                meta={"lattice": (nx, ny, nz), "lattice_index": np.stack([i, j, k], axis=1)})
+    _assert_positive(mesh)
+    return mesh
+
+
+def tet_volumes6(xyz, tets):
+    """6 x signed volume of each tet (det of the edge matrix)."""
+    x0 = xyz[tets[:, 0]]
+    e1 = xyz[tets[:, 1]] - x0
+    e2 = xyz[tets[:, 2]] - x0
+    e3 = xyz[tets[:, 3]] - x0
+    return np.einsum("ei,ei->e", e1, np.cross(e2, e3))
+
+
+def _assert_positive(mesh: Mesh):
+    v6 = tet_volumes6(mesh.xyz, mesh.tets)
+    if not np.all(v6 > 0):
+        bad = int(np.argmin(v6))
+        raise ValueError(f"{mesh.name}: tet {bad} has det J = {v6[bad]:.3e} <= 0")
+
+
+def cavity_mesh(n: int) -> Mesh:
+    """Unit cube [0,1]^3, n^3 cells x 6 tets (lid-driven cavity)."""
+    return kuhn_box((n, n, n), (0, 0, 0), (1, 1, 1), name=f"cavity{n}")
+
+
+def jittered_cube(n: int, seed: int = 0, amp: float = 0.2) -> Mesh:
+    """Unit cube with every interior node displaced by U(-amp*h, amp*h) per coordinate.
+
+    The displacements are drawn for all lattice nodes in lexicographic order
+    (k fastest) from numpy.random.default_rng(seed) and applied only to
+    interior nodes, so the boundary stays planar.
+    """
+    m = kuhn_box((n, n, n), (0, 0, 0), (1, 1, 1), name=f"jitter{n}_s{seed}")
+    h = 1.0 / n
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-amp * h, amp * h, size=(m.n_nodes, 3))
+    lat = m.meta["lattice_index"]
+    interior = np.all((lat > 0) & (lat < n), axis=1)
+    m.xyz = m.xyz + d * interior[:, None]
+    m.meta["seed"] = seed
+    _assert_positive(m)
+    v6 = tet_volumes6(m.xyz, m.tets)
+    m.meta["min_6V_over_h3"] = float(v6.min() / h ** 3)
+    return m
+
+
+def backward_facing_step(cx: int, cy: int, cz: int) -> Mesh:
+    """Backward-facing-step channel: step height 1, expansion ratio 2.
+
+    Inlet channel x in [-5, 0], y in [1, 2]; outlet channel x in [0, 30],
+    y in [0, 2]; span z in [0, 4].  (cx, cy, cz) are cells per unit length.
+    """
+    nx, ny, nz = 35 * cx, 2 * cy, 4 * cz
+    i = np.arange(nx)[:, None, None]
+    j = np.arange(ny)[None, :, None]
+    mask = np.broadcast_to((i >= 5 * cx) | (j >= cy), (nx, ny, nz))
+    return kuhn_box((nx, ny, nz), (-5, 0, 0), (30, 2, 4), cell_mask=np.array(mask),
+                    name=f"bfs_{cx}_{cy}_{cz}")
+
+
+def boundary_nodes(tets: np.ndarray, n_nodes: int) -> np.ndarray:
+    """Bool mask of nodes lying on a boundary face (a face owned by one tet)."""
+    faces = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]],
+                            tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
+    faces = np.sort(faces, axis=1).astype(np.int64)
+    key = (faces[:, 0] * n_nodes + faces[:, 1]) * n_nodes + faces[:, 2]
+    uniq, cnt = np.unique(key, return_counts=True)
+    bkey = uniq[cnt == 1]
+    mask = np.zeros(n_nodes, dtype=bool)
+    a = bkey // (n_nodes * n_nodes)
+    b = (bkey // n_nodes) % n_nodes
+    c = bkey % n_nodes
+    mask[a] = True
+    mask[b] = True
+    mask[c] = True
+    return mask
+
+
+def count_edges(tets: np.ndarray, n_nodes: int) -> int:
+    pairs = np.concatenate([tets[:, [a, b]] for a in range(4) for b in range(a + 1, 4)])
+    pairs = np.sort(pairs, axis=1).astype(np.int64)
+    return int(np.unique(pairs[:, 0] * n_nodes + pairs[:, 1]).size)
