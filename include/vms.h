@@ -1,0 +1,224 @@
+/*
+ * vms.h -- C ABI of the MI355X (gfx950) variational multiscale Newton-Schur
+ * library (libvms.so).
+ *
+ * The method (Turner, Nakshatrala & Hjelmstad, "A variational multiscale
+ * Newton-Schur approach for the incompressible Navier-Stokes equations"):
+ * equal-order linear tetrahedra for velocity and pressure plus one bubble
+ * per element for the fine-scale velocity (Section 3.3); element residuals
+ * R_c, R_p, R_f (Section 4.1) and their consistent Newton tangent
+ * (Section 4.2, the 3x3-block update system); element-level block Gauss
+ * elimination of the fine scales, assembly of the condensed 2x2-block system
+ * and fine-scale recovery (Section 5); a Krylov solve of the condensed system
+ * (Section 6).
+ *
+ * Conventions shared by every call
+ *   - Arrays are DEVICE pointers owned by the caller unless stated; the
+ *     library never frees them.  Host-side structs are read during the call.
+ *   - Coarse unknowns per node are (vx, vy, vz, p); global coarse dof
+ *     4*node + c.  Element dof order: (v0x,v0y,v0z,p0, ..., v3x,v3y,v3z,p3,
+ *     beta_x, beta_y, beta_z).
+ *   - nu = 1/Re; the viscous term carries 2*nu as written in the paper's
+ *     momentum equation and weak form (Sections 2, 3.2).
+ *   - dt <= 0 means steady; otherwise backward Euler from u_prev (Section 4.1
+ *     Remark): the coarse rows get the consistent-mass term, the fine rows
+ *     the bubble-weighted term of the coarse velocity (quasi-static fine scales).
+ *   - Newton sign convention: K * Delta = -R.
+ *   - Every call enqueues on `stream` (NULL = default stream) and returns an
+ *     int status; calls documented as synchronising wait for the stream.
+ *   - No call allocates device memory except vms_create.
+ *   - Errors: negative status; vms_last_error() describes the last one.
+ *     Nothing aborts the process (the paper's code aborted on solver
+ *     failure, Section 6; this library returns VMS_ENOCONV_* instead).
+ */
+#ifndef VMS_H
+#define VMS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VMS_OK = 0,
+    VMS_EINVAL = -1,           /* bad argument (null pointer, size, option)         */
+    VMS_EDEGENERATE = -2,      /* an element with det J <= 0 (index in info)        */
+    VMS_ESINGULAR_KFF = -3,    /* fine-scale block K_ff numerically singular        */
+    VMS_ENOCONV_GMRES = -4,    /* Krylov solve hit max_iters before rtol            */
+    VMS_ENOCONV_NEWTON = -5,   /* reserved for drivers                              */
+    VMS_ENONFINITE = -6,       /* NaN/Inf in a residual or norm                     */
+    VMS_EHIP = -7,             /* HIP runtime error                                 */
+    VMS_ENOMEM = -8            /* device allocation failed in vms_create            */
+};
+
+typedef struct vms_ctx vms_ctx;
+
+typedef enum { VMS_FP64 = 0, VMS_MIXED = 1 } vms_precision;
+typedef enum { VMS_PC_BLOCK_JACOBI = 0, VMS_PC_LEARNED = 1 } vms_pc_kind;
+
+/* Mesh, read once by vms_create (the library keeps its own copies).
+ *   xyz   device double [n_nodes][3]
+ *   tets  device int32  [n_elems][4], positively oriented linear tets
+ *   dirichlet_dofs  device int32 [n_dirichlet], dof = 4*node + c; the
+ *         increment of these dofs is zero (their values live in u).       */
+typedef struct {
+    int32_t n_nodes;
+    int32_t n_elems;
+    const double* xyz;
+    const int32_t* tets;
+    int32_t n_dirichlet;
+    const int32_t* dirichlet_dofs;
+} vms_mesh_desc;
+
+typedef struct {
+    vms_precision precision;   /* VMS_FP64: FP64 everywhere.  VMS_MIXED: FP32
+                                  tangent blocks, block-CSR values and inner
+                                  GMRES; FP64 K_ff^-1, residuals, refinement. */
+    int32_t max_restart;       /* Krylov basis allocated (<= 0: 50)          */
+} vms_create_opts;
+
+/* Builds the 4x4 block-CSR pattern of the condensed system (one block per
+ * node pair sharing an element), the element-to-block map and every
+ * workspace.  Synchronising.  opts may be NULL (FP64, restart 50). */
+int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts, hipStream_t stream,
+               vms_ctx** out);
+int vms_destroy(vms_ctx* ctx);
+const char* vms_last_error(const vms_ctx* ctx);   /* ctx may be NULL */
+
+/* Read-only device views of the block pattern: rowptr [n_nodes+1],
+ * colidx [nb] (sorted per row), diagpos [n_nodes] (block index of (i,i)).
+ * Any pointer argument may be NULL. */
+int vms_bsr_info(const vms_ctx* ctx, int64_t* nb, const int32_t** rowptr,
+                 const int32_t** colidx, const int32_t** diagpos, int32_t* precision);
+
+/* Uncondensed element residual and tangent (Sections 4.1-4.2).
+ *   u      double [n_nodes][4];  u_prev double [n_nodes][4] or NULL (steady)
+ *   beta   double [n_elems][3] fine-scale coefficients
+ *   body   double [n_nodes][3] P1 nodal body force, or NULL
+ *   Ke     double [n_elems][19][19] row-major (mixed ctx: computed in FP32
+ *          for the tangent blocks, FP64 for K_ff, widened on output)
+ *   Rvec   double [n_elems][19]
+ * Ke or Rvec may be NULL.  Not synchronising. */
+int vms_element_tangents(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta,
+                         double Re, double dt, const double* body, double* Ke, double* Rvec,
+                         hipStream_t stream);
+
+/* Condensed tangent and residual, assembled (Section 5):
+ *   K* = K_cc - K_cf K_ff^-1 K_fc,  R* = R_cp - K_cf K_ff^-1 R_f  per element,
+ *   summed into bsr_vals (FP64 ctx: double, mixed ctx: float) [nb][16]
+ *   (4x4 blocks row-major) and rhs = -R* (double [n_nodes][4]).
+ * Rows and columns of Dirichlet dofs are replaced by the identity and their
+ * rhs by 0.  rnorm (device double[1], may be NULL) receives the FP64 Newton
+ * residual norm ||[R_c; R_p] (assembled, free dofs), R_f (all elements)||_2
+ * at the input state.  Not synchronising. */
+int vms_condense_assemble(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta,
+                          double Re, double dt, const double* body, void* bsr_vals, double* rhs,
+                          double* rnorm, hipStream_t stream);
+
+/* FP64 Newton residual norm only (same definition as above); rglob
+ * (double [n_nodes][4], may be NULL) receives the assembled [R_c; R_p].
+ * Not synchronising. */
+int vms_residual(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta,
+                 double Re, double dt, const double* body, double* rglob, double* rnorm,
+                 hipStream_t stream);
+
+/* Fine-scale recovery and Newton update (Section 5; Section 4.2 update):
+ *   dbeta_e = K_ff^-1 (-R_f - K_fc du_e)  at the input state, then
+ *   beta += dbeta, u += du (du is zeroed on Dirichlet dofs first).
+ * du double [n_nodes][4].  u and beta are updated in place.  Not synchronising. */
+int vms_recover_update(vms_ctx* ctx, double* u, double* beta, const double* u_prev, double Re,
+                       double dt, const double* body, const double* du, hipStream_t stream);
+
+/* y = A x with the context's block pattern.  FP64 ctx: double A, x, y.
+ * Mixed ctx: float A, x, y with FP32 accumulation.  Not synchronising. */
+int vms_bsr_spmv(vms_ctx* ctx, const void* bsr_vals, const void* x, void* y, hipStream_t stream);
+
+typedef struct {
+    int32_t restart;           /* Krylov dimension m (<= max_restart)                    */
+    int32_t max_iters;         /* total Arnoldi steps over all cycles and refinements    */
+    double rtol;               /* success iff ||b - A x||_2 <= rtol ||b||_2 (true residual) */
+    vms_pc_kind pc;
+    const float* pc_weights;   /* device, VMS_PC_LEARNED only (layout in vms_pc_*)       */
+    int32_t refine_max;        /* mixed ctx: FP64 iterative-refinement sweeps (<= 0: 30) */
+    double inner_rtol;         /* mixed ctx: FP32 GMRES tolerance per sweep (<= 0: 1e-5) */
+    int32_t cgs2;              /* 1: re-orthogonalise (classical Gram-Schmidt twice)     */
+} vms_solve_opts;
+
+typedef struct {
+    int32_t iters;             /* Arnoldi steps                                          */
+    int32_t restarts;          /* cycles                                                 */
+    int32_t refinements;       /* outer FP64 sweeps (mixed)                              */
+    int32_t fell_back_to_bj;   /* learned preconditioner rejected (non-finite / failure) */
+    double true_rel_res;       /* final ||b - A x|| / ||b|| recomputed in FP64           */
+} vms_solve_info;
+
+/* Right-preconditioned restarted GMRES(m) on A x = b (Section 6 names a
+ * Krylov solver with tolerance and iteration cap; the method and the
+ * preconditioner are this library's: 4x4 block-Jacobi or its learned
+ * correction).  bsr_vals as in vms_condense_assemble; b, x double [n_nodes][4]
+ * (x is the initial guess on entry).  Mixed ctx: FP64 iterative refinement
+ * around FP32 GMRES.  Synchronising.  Returns VMS_ENOCONV_GMRES when the true
+ * residual misses rtol within max_iters (x then holds the best iterate). */
+int vms_gmres_solve(vms_ctx* ctx, const void* bsr_vals, const double* b, double* x,
+                    const vms_solve_opts* opts, vms_solve_info* info, hipStream_t stream);
+
+typedef struct {
+    vms_solve_opts lin;
+} vms_newton_opts;
+
+typedef struct {
+    double rnorm_before;       /* FP64 residual norm at the input state                  */
+    double rnorm_after;        /* FP64 residual norm after the update                    */
+    vms_solve_info lin;
+    int32_t bad_elem;          /* first degenerate element, or -1                         */
+} vms_newton_info;
+
+/* One Newton-Schur iteration (Sections 4.2 and 5): condense and assemble
+ * into the context's own matrix, set up the preconditioner, solve, recover
+ * the fine scales, update u and beta in place, evaluate the new residual.
+ * Synchronising. */
+int vms_newton_step(vms_ctx* ctx, double* u, double* beta, const double* u_prev, double Re,
+                    double dt, const double* body, const vms_newton_opts* opts,
+                    vms_newton_info* info, hipStream_t stream);
+
+/* ---- learned block-Jacobi correction ------------------------------------
+ * Per node i: features x_i (25 floats) from the condensed tangent,
+ *   [ D_i/||D_i||_F (16), log||D_i||_F, log(1 + sum_{j!=i} ||A_ij[r,:]||_1/|D_i[r,r]|) (4),
+ *     Dirichlet flags of the node's 4 dofs (4) ];
+ * MLP h = tanh(W1 x + b1) (64), y = W2 h + b2 (16) = Delta_i (4x4 row-major),
+ * Delta_i zeroed on the rows and columns of Dirichlet dofs,
+ * P_i = D_i^-1 (I + Delta_i).  Weights (float, VMS_PC_NWEIGHTS) packed as
+ * [W1 64x25 row-major, b1 64, W2 16x64, b2 16]. */
+#define VMS_PC_NIN 25
+#define VMS_PC_NHID 64
+#define VMS_PC_NOUT 16
+#define VMS_PC_NWEIGHTS (VMS_PC_NHID * VMS_PC_NIN + VMS_PC_NHID + VMS_PC_NOUT * VMS_PC_NHID + VMS_PC_NOUT)
+
+/* feats float [n_nodes][25].  Not synchronising. */
+int vms_pc_features(vms_ctx* ctx, const void* bsr_vals, float* feats, hipStream_t stream);
+
+/* Preconditioner blocks P float [n_nodes][16] (weights NULL: plain
+ * block-Jacobi D_i^-1).  Not synchronising. */
+int vms_pc_blocks(vms_ctx* ctx, const void* bsr_vals, const float* weights, float* P,
+                  hipStream_t stream);
+
+/* One training step on a batch of residual samples r_batch float
+ * [nbatch][n_nodes][4]:
+ *   loss = mean_s ||r_s - A P r_s||^2 / ||r_s||^2, gradient by the library's
+ *   backward kernels, then Adam (beta1 0.9, beta2 0.999, eps 1e-8) on
+ *   weights in place.  adam_state float [2][VMS_PC_NWEIGHTS] (m, v; zero
+ *   before the first step); step = 1, 2, ... (bias correction).
+ *   grad_out (float [VMS_PC_NWEIGHTS], may be NULL) receives the gradient;
+ *   loss_out (device float[1], may be NULL) the loss before the update.
+ *   lr <= 0 computes loss and gradient without updating.
+ * Not synchronising. */
+int vms_pc_train_step(vms_ctx* ctx, const void* bsr_vals, const float* r_batch, int32_t nbatch,
+                      float* weights, float* adam_state, int32_t step, float lr,
+                      float* grad_out, float* loss_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VMS_H */

@@ -139,6 +139,18 @@ def jittered_cube(n: int, seed: int = 0, amp: float = 0.2) -> Mesh:
     return m
 
 
+def jitter_interior(mesh: Mesh, amp: float, seed: int) -> Mesh:
+    """Displace every node off the boundary by U(-amp*h, amp*h) per coordinate
+    (numpy.random.default_rng(seed), drawn for all nodes in node order)."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-amp * mesh.h, amp * mesh.h, size=(mesh.n_nodes, 3))
+    inner = ~boundary_nodes(mesh.tets, mesh.n_nodes)
+    out = Mesh(xyz=mesh.xyz + d * inner[:, None], tets=mesh.tets, name=mesh.name + f"_j{seed}",
+               h=mesh.h, meta=dict(mesh.meta))
+    _assert_positive(out)
+    return out
+
+
 def backward_facing_step(cx: int, cy: int, cz: int) -> Mesh:
     """Backward-facing-step channel: step height 1, expansion ratio 2.
 
