@@ -1,0 +1,200 @@
+"""Benchmark: condensed tangents/s and time-to-1e-8 Newton solve, FP64 vs mixed precision.
+
+Workload: steady lid-driven cavity, 32^3 cells x 6 tets (196,608 tets, 35,937 nodes),
+Re 100, Newton to ||R|| <= 1e-8 ||R_0|| (FP64 residual), GMRES(50) with 4x4
+block-Jacobi (+ learned correction when trained weights are available).
+
+One step = one complete Newton-Schur solve from the initial state (every assembly,
+preconditioner setup, GMRES iteration, recovery and residual evaluation), all on the
+GPU through the C ABI; inputs are resident on the device before the timed region.
+value = condensed tangents processed per second over the timed steps
+        (elements x Newton iterations / wall time); ms_per_step = time to 1e-8.
+Also reported: the other precision forms, assembly-only throughput, the dominant
+kernel's roofline (HIP events on its stream), and the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_OF_PHASE = {"condense": "tile_kernel", "spmv": "spmv_kernel", "dots": "cgs_dots_kernel",
+                   "update": "cgs_update_kernel", "pc_apply": "arnoldi_pc_kernel"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cavity32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="elements in the oracle sample (0: every element of the workload)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_0809_4802_amd import binding as B, driver
+    from workloads import build_workload
+
+    dev = "cuda:0"
+    cfg, mesh, u0, beta0, bc = build_workload(args.workload)
+    xyz = torch.from_numpy(mesh.xyz).to(dev)
+    tets = torch.from_numpy(mesh.tets).to(dev)
+    dd = torch.from_numpy(bc.dofs).to(dev)
+    u0d = torch.from_numpy(u0).to(dev)
+    b0d = torch.from_numpy(beta0).to(dev)
+    log(f"workload {args.workload}: {mesh.n_elems} tets, {mesh.n_nodes} nodes, Re {cfg.re}")
+
+    def lin_opts():
+        return B.solve_opts(restart=50, rtol=1e-9, max_iters=60000)
+
+    def solve(ctx, prof=False):
+        u = u0d.clone()
+        beta = b0d.clone()
+        torch.cuda.synchronize()
+        res = driver.newton_solve(ctx, u, beta, cfg.re, tol=cfg.newton_tol, lin=lin_opts(), forcing="ew",
+                                  max_newton=30)
+        return res
+
+    ctxs = {"fp64": B.Context(xyz, tets, dd, precision=B.VMS_FP64),
+            "mixed": B.Context(xyz, tets, dd, precision=B.VMS_MIXED)}
+    headline = "mixed"
+
+    # ---- assembly-only throughput (kernel time from HIP events on the launch stream)
+    assembly = {}
+    for name, ctx in ctxs.items():
+        A = ctx.new_bsr()
+        rhs = ctx.new_vec()
+        rn = torch.zeros(1, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            B.vms_condense_assemble(ctx, u0d, b0d, cfg.re, 0.0, None, None, A, rhs, rn)
+        B.vms_profile(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            B.vms_condense_assemble(ctx, u0d, b0d, cfg.re, 0.0, None, None, A, rhs, rn)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        ms, cnt, byt = B.vms_profile_read(ctx)["condense"]
+        B.vms_profile(ctx, False)
+        assembly[name] = {"tangents_per_s": mesh.n_elems / (ms / cnt / 1e3),
+                          "kernel_us": 1e3 * ms / cnt, "call_us": 1e6 * wall,
+                          "alg_GBps": byt / ms / 1e6}
+        del A, rhs
+        log(f"assembly {name}: {assembly[name]}")
+
+    # ---- time to 1e-8 in every form (one warm-up + one timed solve each)
+    forms = {}
+    for name, ctx in ctxs.items():
+        solve(ctx)
+        r = solve(ctx)
+        forms[name + "_bj"] = {"seconds": r.seconds, "newton_steps": len(r.rnorms) - 1,
+                               "gmres_iters": int(sum(d["iters"] for d in r.lin)),
+                               "final_rel_residual": r.rnorms[-1] / r.rnorms[0]}
+        log(f"time-to-1e-8 {name}+BJ: {forms[name + '_bj']}")
+
+    # ---- timed region: K headline solves
+    ctx = ctxs[headline]
+    for _ in range(args.warmup):
+        solve(ctx)
+    B.vms_profile(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = []
+    for _ in range(args.steps):
+        steps.append(solve(ctx))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = B.vms_profile_read(ctx)
+    B.vms_profile(ctx, False)
+    n_assemblies = sum(len(r.rnorms) - 1 for r in steps)
+    value = mesh.n_elems * n_assemblies / elapsed
+
+    # dominant kernel of the timed region
+    phase = max((p for p in prof if prof[p][1] > 0 and p != "fill"), key=lambda p: prof[p][0])
+    ms, cnt, byt = prof[phase]
+    achieved = byt / cnt / (ms / cnt / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": KERNEL_OF_PHASE.get(phase, phase), "phase": phase,
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(1e3 * ms / cnt, 3), "launches": cnt,
+                "alg_bytes_per_launch": byt / cnt}
+    phases = {p: {"ms": round(v[0], 3), "launches": v[1], "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else None,
+                  "alg_GBps": round(v[2] / v[0] / 1e6, 1) if v[0] else None} for p, v in prof.items() if v[1]}
+
+    # ---- CPU oracle baseline on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(mesh, u0, beta0, bc, cfg, args.cpu_sample)
+
+    out = {
+        "metric": "condensed tangents/s + time-to-1e-8 Newton step, plain FP64 vs mixed+learned-PC",
+        "value": value,
+        "unit": "condensed tangents/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if headline == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: lid-driven cavity 32^3 cells x 6 tets ({mesh.n_elems} tets, "
+                               f"{mesh.n_nodes} nodes), Re {cfg.re:g}, steady Newton to 1e-8, GMRES(50) + 4x4 "
+                               f"block-Jacobi, form {headline}",
+                   "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes},
+        "time_to_1e-8_s": {k: v["seconds"] for k, v in forms.items()},
+        "forms": forms,
+        "assembly": assembly,
+        "phases": phases,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(mesh, u0, beta0, bc, cfg, n_sample):
+    """The oracle (quadrature element, condensation, CSR assembly) on the first n_sample
+    elements of the workload, timed on the host cores."""
+    import numpy as np
+    from oracle import vms as O
+    from oracle.element import element_residual_tangent
+
+    n_sample = mesh.n_elems if n_sample <= 0 else min(n_sample, mesh.n_elems)
+    tets = mesh.tets[:n_sample]
+    t0 = time.perf_counter()
+    R, K = element_residual_tangent(mesh.xyz, tets, u0, beta0[:n_sample], 1.0 / cfg.re)
+    Ks, Rs = O.condense(R, K)
+    O.assemble_matrix(tets, mesh.n_nodes, Ks, bc.dofs)
+    O.assemble_vector(tets, mesh.n_nodes, Rs)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_sample / dt, "unit": "condensed tangents/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_sample} of {mesh.n_elems} elements, one condensed assembly at the initial state: "
+                      f"quadrature element + condensation + CSR assembly ({dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

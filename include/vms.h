@@ -144,6 +144,10 @@ typedef struct {
     int32_t refine_max;        /* mixed ctx: FP64 iterative-refinement sweeps (<= 0: 30) */
     double inner_rtol;         /* mixed ctx: FP32 GMRES tolerance per sweep (<= 0: 1e-5) */
     int32_t cgs2;              /* 1: re-orthogonalise (classical Gram-Schmidt twice)     */
+    int32_t coarse_pressure;   /* 1: add the coarse correction on the constant pressure
+                                  mode, P v = M v + z (z^T v) / (z^T A z), z = 1 on every
+                                  free pressure dof.  With one pinned pressure dof that mode
+                                  is nearly singular and restarted GMRES stalls on it.     */
 } vms_solve_opts;
 
 typedef struct {
@@ -217,6 +221,28 @@ int vms_pc_blocks(vms_ctx* ctx, const void* bsr_vals, const float* weights, floa
 int vms_pc_train_step(vms_ctx* ctx, const void* bsr_vals, const float* r_batch, int32_t nbatch,
                       float* weights, float* adam_state, int32_t step, float lr,
                       float* grad_out, float* loss_out, hipStream_t stream);
+
+/* ---- phase timers ----------------------------------------------------------
+ * While enabled, every launch of a hot kernel is bracketed by two hipEvents
+ * on its stream, and the algorithmic bytes the launch must move (inputs read
+ * once, outputs written once; no credit for scratch, atomics or re-reads)
+ * are added to its phase.  vms_profile clears the accumulators; enabling adds
+ * a small host cost per launch. */
+enum {
+    VMS_PH_CONDENSE = 0,       /* element residual + tangent + condensation + scatter kernel */
+    VMS_PH_RESIDUAL = 1,       /* residual-only element kernel                            */
+    VMS_PH_RECOVER = 2,        /* fine-scale recovery kernel                              */
+    VMS_PH_PCSETUP = 3,        /* preconditioner block setup                              */
+    VMS_PH_PCAPPLY = 4,        /* normalisation + preconditioner apply in the Arnoldi step */
+    VMS_PH_SPMV = 5,           /* block-CSR SpMV in the Arnoldi step                      */
+    VMS_PH_DOTS = 6,           /* Gram-Schmidt dot products                               */
+    VMS_PH_UPDATE = 7,         /* Gram-Schmidt update + norm + Givens                     */
+    VMS_PH_FILL = 8,           /* zero fill of the assembled outputs                      */
+    VMS_NPHASES = 9
+};
+int vms_profile(vms_ctx* ctx, int enable);
+/* Synchronising.  Each array has VMS_NPHASES entries; any may be NULL. */
+int vms_profile_read(vms_ctx* ctx, double* ms, int64_t* launches, double* alg_bytes);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,8 @@ import os
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libvms.so")
+# VMS_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("VMS_LIBRARY", os.path.join(_PKG, "libvms.so"))
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_0809_4802_amd/build.py`")
@@ -32,7 +33,8 @@ PC_NWEIGHTS = PC_NHID * PC_NIN + PC_NHID + PC_NOUT * PC_NHID + PC_NOUT
 EXPORTED = ["vms_create", "vms_destroy", "vms_last_error", "vms_bsr_info", "vms_element_tangents",
             "vms_condense_assemble", "vms_residual", "vms_recover_update", "vms_bsr_spmv",
             "vms_gmres_solve", "vms_newton_step", "vms_pc_features", "vms_pc_blocks",
-            "vms_pc_train_step"]
+            "vms_pc_train_step", "vms_profile", "vms_profile_read"]
+PHASES = ["condense", "residual", "recover", "pc_setup", "pc_apply", "spmv", "dots", "update", "fill"]
 
 
 class VmsError(RuntimeError):
@@ -54,7 +56,8 @@ class CreateOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("pc", ctypes.c_int), ("pc_weights", ctypes.c_void_p), ("refine_max", ctypes.c_int32),
-                ("inner_rtol", ctypes.c_double), ("cgs2", ctypes.c_int32)]
+                ("inner_rtol", ctypes.c_double), ("cgs2", ctypes.c_int32),
+                ("coarse_pressure", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -94,6 +97,8 @@ _sig = {
     "vms_pc_features": [_vp, _vp, _vp, _vp],
     "vms_pc_blocks": [_vp, _vp, _vp, _vp, _vp],
     "vms_pc_train_step": [_vp, _vp, _vp, _i32, _vp, _vp, _i32, ctypes.c_float, _vp, _vp, _vp],
+    "vms_profile": [_vp, ctypes.c_int],
+    "vms_profile_read": [_vp, _vp, _vp, _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -202,10 +207,10 @@ def _copy_device(dst, src_ptr, nbytes):
 
 
 def solve_opts(restart=50, max_iters=100000, rtol=1e-8, pc=VMS_PC_BLOCK_JACOBI, pc_weights=None,
-               refine_max=30, inner_rtol=1e-5, cgs2=0):
+               refine_max=30, inner_rtol=1e-5, cgs2=1, coarse_pressure=1):
     return SolveOpts(restart, max_iters, rtol, pc,
                      pc_weights.data_ptr() if pc_weights is not None else None,
-                     refine_max, inner_rtol, cgs2)
+                     refine_max, inner_rtol, cgs2, coarse_pressure)
 
 
 # ---- entry points (same names as the C ABI) ------------------------------------------
@@ -287,3 +292,17 @@ def vms_pc_train_step(ctx: Context, bsr_vals, r_batch, weights, adam_state, step
     _check(_lib.vms_pc_train_step(ctx.handle, _ptr(bsr_vals), _ptr(r_batch), nbatch, _ptr(weights),
                                   _ptr(adam_state), int(step), float(lr), _ptr(grad_out), _ptr(loss_out),
                                   _stream(stream)), ctx.handle)
+
+
+def vms_profile(ctx: Context, enable=True):
+    _check(_lib.vms_profile(ctx.handle, 1 if enable else 0), ctx.handle)
+
+
+def vms_profile_read(ctx: Context):
+    """{phase: (ms, launches, algorithmic bytes)} accumulated since vms_profile."""
+    n = len(PHASES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    byt = (ctypes.c_double * n)()
+    _check(_lib.vms_profile_read(ctx.handle, ms, cnt, byt), ctx.handle)
+    return {PHASES[i]: (ms[i], int(cnt[i]), byt[i]) for i in range(n)}

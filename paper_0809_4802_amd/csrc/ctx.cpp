@@ -41,13 +41,77 @@ extern "C" const char* vms_last_error(const vms_ctx* ctx) {
     return g_last_error.c_str();
 }
 
+namespace vms {
+
+static constexpr int kProfPool = 4096;
+
+static int prof_flush(vms_ctx* c) {
+    for (int i = 0; i < c->prof_used; ++i) {
+        hipEvent_t e0 = c->prof_ev[2 * i], e1 = c->prof_ev[2 * i + 1];
+        if (hipEventSynchronize(e1) != hipSuccess) return VMS_EHIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return VMS_EHIP;
+        const int ph = c->prof_phase[i];
+        c->prof_ms[ph] += ms;
+        c->prof_acc_bytes[ph] += c->prof_bytes[i];
+        c->prof_count[ph] += 1;
+    }
+    c->prof_used = 0;
+    return VMS_OK;
+}
+
+int prof_begin(vms_ctx* c, int phase, double bytes, hipStream_t s) {
+    if (c->prof_used == kProfPool && prof_flush(c) != VMS_OK) return -1;
+    const int slot = c->prof_used++;
+    c->prof_phase[slot] = phase;
+    c->prof_bytes[slot] = bytes;
+    (void)hipEventRecord(c->prof_ev[2 * slot], s);
+    return slot;
+}
+
+void prof_end(vms_ctx* c, int slot, hipStream_t s) { (void)hipEventRecord(c->prof_ev[2 * slot + 1], s); }
+
+}  // namespace vms
+
+extern "C" int vms_profile(vms_ctx* c, int enable) {
+    if (!c) return set_error(nullptr, VMS_EINVAL, "vms_profile: NULL ctx");
+    if (c->prof_ev.empty() && enable) {
+        c->prof_ev.resize(2 * kProfPool);
+        for (auto& e : c->prof_ev)
+            if (hipEventCreate(&e) != hipSuccess) return set_error(c, VMS_EHIP, "vms_profile: hipEventCreate");
+        c->prof_phase.resize(kProfPool);
+        c->prof_bytes.resize(kProfPool);
+    }
+    if (c->prof_used && prof_flush(c) != VMS_OK) return set_error(c, VMS_EHIP, "vms_profile: event sync");
+    for (int i = 0; i < VMS_NPHASES; ++i) {
+        c->prof_ms[i] = 0.0;
+        c->prof_acc_bytes[i] = 0.0;
+        c->prof_count[i] = 0;
+    }
+    c->prof_on = enable != 0;
+    return VMS_OK;
+}
+
+extern "C" int vms_profile_read(vms_ctx* c, double* ms, int64_t* launches, double* alg_bytes) {
+    if (!c) return set_error(nullptr, VMS_EINVAL, "vms_profile_read: NULL ctx");
+    if (c->prof_used && prof_flush(c) != VMS_OK) return set_error(c, VMS_EHIP, "vms_profile_read: event sync");
+    for (int i = 0; i < VMS_NPHASES; ++i) {
+        if (ms) ms[i] = c->prof_ms[i];
+        if (launches) launches[i] = c->prof_count[i];
+        if (alg_bytes) alg_bytes[i] = c->prof_acc_bytes[i];
+    }
+    return VMS_OK;
+}
+
 static void free_all(vms_ctx* c) {
     void* ptrs[] = {c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
-                    c->tpos, c->epos, c->A, c->rhs, c->du, c->rglob, c->rnorm, c->flags,
+                    c->tpos, c->tile_node0, c->tile_iptr, c->item_ea, c->item_pos, c->A, c->rhs, c->du, c->rglob, c->rnorm, c->flags,
                     c->V, c->w, c->z, c->d, c->r, c->Minv, c->x64, c->r64, c->gs, c->red,
                     c->feats, c->hid, c->pblk, c->gblk, c->tvec, c->wgrad, c->fscal};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto e : c->prof_ev)
+        if (e) (void)hipEventDestroy(e);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
 }
@@ -192,15 +256,57 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
         const int32_t* p = std::lower_bound(b, e, col);
         return (int32_t)(p - colidx.data());
     };
-    std::vector<int32_t> diagpos(nn), tpos(c->nb), epos(16 * ne);
+    std::vector<int32_t> diagpos(nn), tpos(c->nb);
     for (int64_t i = 0; i < nn; ++i) {
         diagpos[i] = find((int32_t)i, (int32_t)i);
         for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) tpos[k] = find(colidx[k], (int32_t)i);
     }
-    for (int64_t e = 0; e < ne; ++e)
-        for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b)
-                epos[(a * 4 + b) * ne + e] = find(tets[4 * e + a], tets[4 * e + b]);
+
+    // Assembly tiles: contiguous node ranges whose block rows fit the LDS budget.
+    const size_t acc_size = c->prec == VMS_FP64 ? sizeof(double) : kMixedAccSize;
+    const int64_t max_blocks = acc_size == sizeof(double) ? kTileBlocksFP64 : kTileBlocksFP32;
+    std::vector<int32_t> tnode0{0}, tiptr{0}, iea;
+    std::vector<uint2> ipos;
+    iea.reserve(4 * ne);
+    ipos.reserve(4 * ne);
+    size_t lds_max = 0;
+    {
+        int64_t r0 = 0;
+        std::vector<std::pair<int32_t, int32_t>> list;   // (element, local vertex)
+        while (r0 < nn) {
+            if (rowptr[r0 + 1] - rowptr[r0] > max_blocks) {
+                free_all(c);
+                delete c;
+                return set_error(nullptr, VMS_EINVAL, "vms_create: node " + std::to_string(r0) +
+                                                          " has more block neighbours than an assembly tile holds");
+            }
+            int64_t r1 = r0 + 1;
+            while (r1 < nn && r1 - r0 < kTileNodes && rowptr[r1 + 1] - rowptr[r0] <= max_blocks) ++r1;
+            list.clear();
+            for (int64_t i = r0; i < r1; ++i)
+                for (int32_t k = n2e_ptr[i]; k < n2e_ptr[i + 1]; ++k) {
+                    const int32_t e = n2e[k];
+                    for (int a = 0; a < 4; ++a)
+                        if (tets[4 * (int64_t)e + a] == i) list.emplace_back(e, a);
+                }
+            std::sort(list.begin(), list.end());   // element order: neighbouring lanes hit different rows
+            const int32_t b0 = rowptr[r0];
+            for (auto& it : list) {
+                const int32_t e = it.first, a = it.second;
+                const int32_t row = tets[4 * (int64_t)e + a];
+                uint32_t p[4];
+                for (int b = 0; b < 4; ++b) p[b] = (uint32_t)(find(row, tets[4 * (int64_t)e + b]) - b0);
+                iea.push_back(4 * e + a);
+                ipos.push_back(make_uint2(p[0] | (p[1] << 16), p[2] | (p[3] << 16)));
+            }
+            tnode0.push_back((int32_t)r1);
+            tiptr.push_back((int32_t)iea.size());
+            lds_max = std::max(lds_max, tile_lds_bytes(rowptr[r1] - rowptr[r0], r1 - r0, acc_size));
+            r0 = r1;
+        }
+    }
+    c->n_tiles = (int32_t)(tnode0.size() - 1);
+    c->tile_lds = lds_max;
 
     std::vector<double> xyz4(4 * nn);
     for (int64_t i = 0; i < nn; ++i) {
@@ -220,7 +326,10 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->colidx, c->nb * sizeof(int32_t), "alloc colidx"));
     TRY(dev_alloc(c, &c->diagpos, nn * sizeof(int32_t), "alloc diagpos"));
     TRY(dev_alloc(c, &c->tpos, c->nb * sizeof(int32_t), "alloc tpos"));
-    TRY(dev_alloc(c, &c->epos, 16 * ne * sizeof(int32_t), "alloc epos"));
+    TRY(dev_alloc(c, &c->tile_node0, tnode0.size() * sizeof(int32_t), "alloc tiles"));
+    TRY(dev_alloc(c, &c->tile_iptr, tiptr.size() * sizeof(int32_t), "alloc tiles"));
+    TRY(dev_alloc(c, &c->item_ea, iea.size() * sizeof(int32_t), "alloc tile items"));
+    TRY(dev_alloc(c, &c->item_pos, ipos.size() * sizeof(uint2), "alloc tile items"));
     TRY(dev_alloc(c, &c->A, c->nb * 16 * es, "alloc A"));
     TRY(dev_alloc(c, &c->rhs, N * sizeof(double), "alloc rhs"));
     TRY(dev_alloc(c, &c->du, N * sizeof(double), "alloc du"));
@@ -259,7 +368,11 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(check_hip(c, hipMemcpy(c->colidx, colidx.data(), c->nb * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     TRY(check_hip(c, hipMemcpy(c->diagpos, diagpos.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     TRY(check_hip(c, hipMemcpy(c->tpos, tpos.data(), c->nb * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
-    TRY(check_hip(c, hipMemcpy(c->epos, epos.data(), 16 * ne * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    TRY(check_hip(c, hipMemcpy(c->tile_node0, tnode0.data(), tnode0.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    TRY(check_hip(c, hipMemcpy(c->tile_iptr, tiptr.data(), tiptr.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    TRY(check_hip(c, hipMemcpy(c->item_ea, iea.data(), iea.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    TRY(check_hip(c, hipMemcpy(c->item_pos, ipos.data(), ipos.size() * sizeof(uint2), hipMemcpyHostToDevice), "upload"));
+    TRY(check_hip(c, tile_kernels_configure(c), "configure tile kernels"));
     TRY(check_hip(c, hipMemset(c->red, 0, sizeof(RedScratch)), "clear"));
     TRY(check_hip(c, hipMemset(c->gs, 0, sizeof(GmresState)), "clear"));
     TRY(check_hip(c, hipMemset(c->flags, 0, 8 * sizeof(int32_t)), "clear"));

@@ -310,133 +310,294 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // -------------------------------------------------------------------------------------------
-// Condense and assemble: K* into the block-CSR values, -R* into rhs, [R_c; R_p] into rglob
-// (free dofs only), sum |R_f|^2 into red_slots.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void condense_kernel(ElemArgs args, const int32_t* __restrict__ epos,
-                                                          T* __restrict__ Aval, double* __restrict__ rhs,
-                                                          double* __restrict__ rglob,
-                                                          double* __restrict__ red_slots) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+// Tiled assembly.  Workgroup t owns the block rows of nodes [n0, n1) (a contiguous range, so
+// its rows are the contiguous block range [rowptr[n0], rowptr[n1])) and stages them, with the
+// rhs and residual rows, in LDS.  Its work items are the pairs (element e, local vertex a)
+// with vertex a owned by the tile; an item evaluates the element's shared quantities
+// (geometry, fields, R_f, K_ff^-1), its rows a:
+//   R*_a = R_cp,a - K_cf(a) K_ff^-1 R_f,   Y(a) = K_cf(a) K_ff^-1,
+//   K*(a,b) = K_cc(a,b) - Y(a) K_fc(b)   for b = 0..3 (column by column),
+// and adds them to the staged rows with LDS atomics.  The tile then sets the Dirichlet unit
+// diagonals and writes its rows once with coalesced stores: no global atomics, no zero fill,
+// every condensed block computed exactly once.  Item slots (tile-local block index of (a, b))
+// come precomputed from the host.
+//   CONDENSE = true : K* into Aval, -R* into rhs, R_cp into rglob, |R_f|^2 into slots
+//   CONDENSE = false: R_cp into rglob, |R_f|^2 into slots (residual only)
+constexpr int kTileThreads = 512;
+
+struct TileArgs {
+    const int32_t* __restrict__ node0;
+    const int32_t* __restrict__ iptr;
+    const int32_t* __restrict__ ea;
+    const uint2* __restrict__ pos;
+    const int32_t* __restrict__ rowptr;
+    const int32_t* __restrict__ diagpos;
+};
+
+template <typename T, typename TACC, bool CONDENSE>
+__global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, TileArgs ta, T* __restrict__ Aval,
+                                                               double* __restrict__ rhs, double* __restrict__ rglob,
+                                                               double* __restrict__ red_slots) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = blockIdx.x;
+    const int n0 = ta.node0[t], n1 = ta.node0[t + 1], nn = n1 - n0;
+    const int b0 = ta.rowptr[n0], nbk = ta.rowptr[n1] - b0;
+    TACC* blk = reinterpret_cast<TACC*>(smem);
+    const size_t off = CONDENSE ? align16((size_t)nbk * kLdsBlockStride * sizeof(TACC)) : 0;
+    double* rr = reinterpret_cast<double*>(smem + off);
+    double* rg = rr + (size_t)nn * 4;
+
+    if (CONDENSE)
+        for (int i = threadIdx.x; i < nbk * kLdsBlockStride; i += blockDim.x) blk[i] = TACC(0);
+    for (int i = threadIdx.x; i < nn * 4; i += blockDim.x) {
+        rr[i] = 0.0;
+        rg[i] = 0.0;
+    }
+    __syncthreads();
+
+    const double nu = args.nu;
+    const bool transient = args.u_prev != nullptr && args.inv_dt != 0.0;
+    const double inv_dt = transient ? args.inv_dt : 0.0;
     double rf2 = 0.0;
-    if (e < args.n_elems) {
-        Elem E;
-        if (!load_element(args, e, E)) {
+    const int k_end = ta.iptr[t + 1];
+    for (int k = ta.iptr[t] + threadIdx.x; k < k_end; k += blockDim.x) {
+        const int ea = ta.ea[k];
+        const int e = ea >> 2, a = ea & 3;
+        const int4 tv = args.tets[e];
+        const int nid[4] = {tv.x, tv.y, tv.z, tv.w};
+        // geometry
+        double X[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double4 x = args.xyz4[nid[q]];
+            X[q][0] = x.x;
+            X[q][1] = x.y;
+            X[q][2] = x.z;
+        }
+        double J[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) J[i][c] = X[c + 1][i] - X[0][i];
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        if (!(det > 0.0)) {
             atomicMin(&args.flags[0], e);
-        } else {
-            const double nu = args.nu, inv_dt = E.transient ? args.inv_dt : 0.0;
-            double Rf[3];
-            fine_residual(E, nu, inv_dt, Rf);
-            rf2 = Rf[0] * Rf[0] + Rf[1] * Rf[1] + Rf[2] * Rf[2];
-            double Ki[3][3], Kff[3][3];
-            if (!fine_block_inverse(E, nu, Ki, Kff)) atomicMin(&args.flags[1], e);
-            double z[3];
+            continue;
+        }
+        const double id = 1.0 / det;
+        double g[4][3];
+        g[1][0] = c00 * id;
+        g[1][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+        g[1][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+        g[2][0] = c01 * id;
+        g[2][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+        g[2][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+        g[3][0] = c02 * id;
+        g[3][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+        g[3][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) z[i] = Ki[i][0] * Rf[0] + Ki[i][1] * Rf[1] + Ki[i][2] * Rf[2];
-            // W(b) = K_ff^-1 K_fc(b): FP64 product, stored in T
-            T Wb[4][3][4];
+        for (int i = 0; i < 3; ++i) g[0][i] = -(g[1][i] + g[2][i] + g[3][i]);
+        const double vol = det * (1.0 / 6.0);
+        double gg = 0.0;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                double Kfc[3][4];
-                fine_coarse_block<double>(E, b, inv_dt, Kfc);
+        for (int q = 0; q < 4; ++q) gg += g[q][0] * g[q][0] + g[q][1] * g[q][1] + g[q][2] * g[q][2];
+        const double B1 = kB1 * vol, Bm = kB * vol, Cm = kC * vol, Kb = kKb * vol * gg;
+        const double m0 = vol * (1.0 / 20.0);
+
+        // fields: G = grad vbar, grad p, sums over vertices; quantities of vertex a
+        double G[3][3] = {}, gp[3] = {}, vs[3] = {}, ps = 0.0, va[3] = {}, ga[3] = {};
+        double dvs[3] = {}, dva[3] = {}, fs[3] = {}, fa[3] = {};
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        Wb[b][i][c] = T(Ki[i][0] * Kfc[0][c] + Ki[i][1] * Kfc[1][c] + Ki[i][2] * Kfc[2][c]);
-            }
-            T Gt[3][3], gt[4][3], bt[3];
+        for (int q = 0; q < 4; ++q) {
+            const double4 uu = reinterpret_cast<const double4*>(args.u)[nid[q]];
+            const double vq[3] = {uu.x, uu.y, uu.z};
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
 #pragma unroll
-                for (int j = 0; j < 3; ++j) Gt[i][j] = T(E.G[i][j]);
-                bt[i] = T(E.be[i]);
+                for (int j = 0; j < 3; ++j) G[i][j] += vq[i] * g[q][j];
+                gp[i] += uu.w * g[q][i];
+                vs[i] += vq[i];
+                va[i] = (q == a) ? vq[i] : va[i];
+                ga[i] = (q == a) ? g[q][i] : ga[i];
             }
+            ps += uu.w;
+            if (transient) {
+                const double4 up = reinterpret_cast<const double4*>(args.u_prev)[nid[q]];
+                const double d[3] = {vq[0] - up.x, vq[1] - up.y, vq[2] - up.z};
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) {
+                    dvs[i] += d[i];
+                    dva[i] = (q == a) ? d[i] : dva[i];
+                }
+            }
+            if (args.body) {
 #pragma unroll
-                for (int i = 0; i < 3; ++i) gt[a][i] = T(E.g[a][i]);
-            const T volt = T(E.vol), B1t = T(E.B1), tnv = T(2.0 * nu * E.vol), idt = T(inv_dt);
-            const int nid[4] = {E.t.x, E.t.y, E.t.z, E.t.w};
-            uint32_t dm[4];
+                for (int i = 0; i < 3; ++i) {
+                    const double f = args.body[3 * (size_t)nid[q] + i];
+                    fs[i] += f;
+                    fa[i] = (q == a) ? f : fa[i];
+                }
+            }
+        }
+        const double th = G[0][0] + G[1][1] + G[2][2];
+        const double* bp = args.beta + 3 * (size_t)e;
+        const double be[3] = {bp[0], bp[1], bp[2]};
+        double Wv[3], Va[3];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) dm[a] = args.dmask[nid[a]];
-            const size_t ne = (size_t)args.n_elems;
+        for (int i = 0; i < 3; ++i) {
+            Wv[i] = B1 * vs[i];
+            Va[i] = m0 * (vs[i] + va[i]);
+        }
+        // fine-scale residual and block
+        double Rf[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            Rf[i] = G[i][0] * Wv[0] + G[i][1] * Wv[1] + G[i][2] * Wv[2] +
+                    Cm * (G[i][0] * be[0] + G[i][1] * be[1] + G[i][2] * be[2] - 0.5 * th * be[i]) +
+                    2.0 * nu * Kb * be[i] + Bm * gp[i] - B1 * fs[i] + inv_dt * B1 * dvs[i];
+        if (a == 0) rf2 += Rf[0] * Rf[0] + Rf[1] * Rf[1] + Rf[2] * Rf[2];
+        // coarse residual rows of vertex a
+        const double gaW = ga[0] * Wv[0] + ga[1] * Wv[1] + ga[2] * Wv[2];
+        const double bga = be[0] * ga[0] + be[1] * ga[1] + be[2] * ga[2];
+        double Rc[4];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            Rc[i] = G[i][0] * (Va[0] + B1 * be[0]) + G[i][1] * (Va[1] + B1 * be[1]) + G[i][2] * (Va[2] + B1 * be[2]) -
+                    (gaW + th * B1 + 0.5 * Cm * bga) * be[i] +
+                    2.0 * nu * vol * (G[i][0] * ga[0] + G[i][1] * ga[1] + G[i][2] * ga[2]) - 0.25 * vol * ps * ga[i] -
+                    m0 * (fs[i] + fa[i]) + inv_dt * m0 * (dvs[i] + dva[i]);
+        Rc[3] = -th * vol * 0.25 + Bm * bga;
+        const uint32_t dma = args.dmask[nid[a]];
+        const int la = nid[a] - n0;
+        double Kcf[4][3];
+        double Ki[3][3];
+        if (CONDENSE) {
+            const double dk = 2.0 * nu * Kb - 0.5 * Cm * th;
+            double Kff[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) Kff[i][j] = Cm * G[i][j] + (i == j ? dk : 0.0);
+            const double k00 = Kff[1][1] * Kff[2][2] - Kff[1][2] * Kff[2][1];
+            const double k01 = Kff[1][2] * Kff[2][0] - Kff[1][0] * Kff[2][2];
+            const double k02 = Kff[1][0] * Kff[2][1] - Kff[1][1] * Kff[2][0];
+            const double kdet = Kff[0][0] * k00 + Kff[0][1] * k01 + Kff[0][2] * k02;
+            double knrm = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) knrm = fmax(knrm, fabs(Kff[i][0]) + fabs(Kff[i][1]) + fabs(Kff[i][2]));
+            if (!(fabs(kdet) > 1e-14 * knrm * knrm * knrm)) atomicMin(&args.flags[1], e);
+            const double kid = 1.0 / kdet;
+            Ki[0][0] = k00 * kid;
+            Ki[0][1] = (Kff[0][2] * Kff[2][1] - Kff[0][1] * Kff[2][2]) * kid;
+            Ki[0][2] = (Kff[0][1] * Kff[1][2] - Kff[0][2] * Kff[1][1]) * kid;
+            Ki[1][0] = k01 * kid;
+            Ki[1][1] = (Kff[0][0] * Kff[2][2] - Kff[0][2] * Kff[2][0]) * kid;
+            Ki[1][2] = (Kff[0][2] * Kff[1][0] - Kff[0][0] * Kff[1][2]) * kid;
+            Ki[2][0] = k02 * kid;
+            Ki[2][1] = (Kff[0][1] * Kff[2][0] - Kff[0][0] * Kff[2][1]) * kid;
+            Ki[2][2] = (Kff[0][0] * Kff[1][1] - Kff[0][1] * Kff[1][0]) * kid;
+            // K_cf(a): velocity rows, then the pressure row
+            const double dg = -(gaW + th * B1) - 0.5 * Cm * bga;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    Kcf[i][j] = B1 * G[i][j] - 0.5 * Cm * be[i] * ga[j] + (i == j ? dg : 0.0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Kcf[3][j] = Bm * ga[j];
+            double zf[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) zf[i] = Ki[i][0] * Rf[0] + Ki[i][1] * Rf[1] + Ki[i][2] * Rf[2];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double rs = Rc[r] - (Kcf[r][0] * zf[0] + Kcf[r][1] * zf[1] + Kcf[r][2] * zf[2]);
+                if (!(dma & (1u << r))) atomic_add(&rr[4 * la + r], -rs);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (!(dma & (1u << r))) atomic_add(&rg[4 * la + r], Rc[r]);
+        if (!CONDENSE) continue;
 
+        // Y(a) = K_cf(a) K_ff^-1 (FP64 product, kept in T)
+        T Y[4][3];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                double Rc[4];
-                coarse_residual(E, a, nu, inv_dt, Rc);
-                double Kcf[4][3];
-                coarse_fine_block<double>(E, a, Kcf);
-                const size_t row = 4 * (size_t)nid[a];
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Y[r][j] = T(Kcf[r][0] * Ki[0][j] + Kcf[r][1] * Ki[1][j] + Kcf[r][2] * Ki[2][j]);
+        T keep_r[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) keep_r[r] = (dma & (1u << r)) ? T(0) : T(1);
+        const T Gt[3][3] = {{T(G[0][0]), T(G[0][1]), T(G[0][2])},
+                            {T(G[1][0]), T(G[1][1]), T(G[1][2])},
+                            {T(G[2][0]), T(G[2][1]), T(G[2][2])}};
+        const T bt[3] = {T(be[0]), T(be[1]), T(be[2])};
+        const T gat[3] = {T(ga[0]), T(ga[1]), T(ga[2])};
+        const T B1t = T(B1), hCt = T(0.5 * Cm), qv = T(-0.25 * vol);
+        const uint2 pp = ta.pos[k];
+        const uint32_t slot[4] = {pp.x & 0xffffu, pp.x >> 16, pp.y & 0xffffu, pp.y >> 16};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const T gb[3] = {T(g[b][0]), T(g[b][1]), T(g[b][2])};
+            const uint32_t dmb = args.dmask[nid[b]];
+            const double mab = (b == a) ? 2.0 * m0 : m0;
+            // scalar of the K_vv identity part and of the K_fv identity part
+            const T s_ab = T(g[b][0] * Va[0] + g[b][1] * Va[1] + g[b][2] * Va[2] + mab * inv_dt +
+                             2.0 * nu * vol * (ga[0] * g[b][0] + ga[1] * g[b][1] + ga[2] * g[b][2]) +
+                             B1 * (g[b][0] * be[0] + g[b][1] * be[1] + g[b][2] * be[2]));
+            const T d_b = T(g[b][0] * Wv[0] + g[b][1] * Wv[1] + g[b][2] * Wv[2] +
+                            Cm * (g[b][0] * be[0] + g[b][1] * be[1] + g[b][2] * be[2]) + B1 * inv_dt);
+            const T mabt = T(mab);
+            TACC* dst = blk + (size_t)slot[b] * kLdsBlockStride;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                T kfc[3], kcc[4];
+                if (c < 3) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        kfc[i] = B1t * Gt[i][c] - hCt * bt[i] * gb[c] + (i == c ? d_b : T(0));
+                        kcc[i] = mabt * Gt[i][c] - B1t * bt[i] * (gat[c] + gb[c]) + (i == c ? s_ab : T(0));
+                    }
+                    kcc[3] = qv * gb[c];
+                } else {
+                    const T Bt = T(Bm);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        kfc[i] = Bt * gb[i];
+                        kcc[i] = qv * gat[i];
+                    }
+                    kcc[3] = T(0);
+                }
+                const T keep_c = (dmb & (1u << c)) ? T(0) : T(1);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    if (dm[a] & (1u << r)) continue;
-                    const double rs = Rc[r] - (Kcf[r][0] * z[0] + Kcf[r][1] * z[1] + Kcf[r][2] * z[2]);
-                    atomic_add(&rhs[row + r], -rs);
-                    atomic_add(&rglob[row + r], Rc[r]);
-                }
-                T Kc[4][3];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) Kc[r][k] = T(Kcf[r][k]);
-                const double m0 = E.vol * (1.0 / 20.0);
-                T Va[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) Va[i] = T(m0 * (E.vs[i] + E.v[a][i]));
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    T K[4][4];
-                    coarse_block<T>(Gt, gt, Va, bt, volt, B1t, tnv, idt, a, b, K);
-                    const int blk = epos[(a * 4 + b) * ne + e];
-                    T* dst = Aval + (size_t)blk * 16;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        if (dm[a] & (1u << r)) continue;
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            if (dm[b] & (1u << c)) continue;
-                            const T val = K[r][c] - (Kc[r][0] * Wb[b][0][c] + Kc[r][1] * Wb[b][1][c] +
-                                                     Kc[r][2] * Wb[b][2][c]);
-                            atomic_add(&dst[r * 4 + c], val);
-                        }
-                    }
+                    const T val = kcc[r] - (Y[r][0] * kfc[0] + Y[r][1] * kfc[1] + Y[r][2] * kfc[2]);
+                    atomic_add(&dst[r * 4 + c], TACC(val * keep_r[r] * keep_c));
                 }
             }
         }
     }
-    rf2 = wave_sum(rf2);
-    if ((threadIdx.x & 63) == 0 && rf2 != 0.0) atomic_add(&red_slots[(blockIdx.x & 63) * 8], rf2);
-}
-
-// Residual only: [R_c; R_p] into rglob (free dofs), |R_f|^2 into red_slots.
-__global__ __launch_bounds__(kBlock) void residual_kernel(ElemArgs args, double* __restrict__ rglob,
-                                                          double* __restrict__ red_slots) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    double rf2 = 0.0;
-    if (e < args.n_elems) {
-        Elem E;
-        if (!load_element(args, e, E)) {
-            atomicMin(&args.flags[0], e);
-        } else {
-            const double inv_dt = E.transient ? args.inv_dt : 0.0;
-            double Rf[3];
-            fine_residual(E, args.nu, inv_dt, Rf);
-            rf2 = Rf[0] * Rf[0] + Rf[1] * Rf[1] + Rf[2] * Rf[2];
-            const int nid[4] = {E.t.x, E.t.y, E.t.z, E.t.w};
+    __syncthreads();
+    if (CONDENSE) {
+        // unit diagonal on the Dirichlet dofs of owned nodes
+        for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+            const uint32_t d = args.dmask[n0 + i];
+            if (!d) continue;
+            const int p = ta.diagpos[n0 + i] - b0;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const uint32_t dm = args.dmask[nid[a]];
-                double Rc[4];
-                coarse_residual(E, a, args.nu, inv_dt, Rc);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (!(dm & (1u << r))) atomic_add(&rglob[4 * (size_t)nid[a] + r], Rc[r]);
-            }
+            for (int r = 0; r < 4; ++r)
+                if (d & (1u << r)) blk[(size_t)p * kLdsBlockStride + r * 5] = TACC(1);
         }
+        __syncthreads();
+        T* gdst = Aval + (size_t)b0 * 16;
+        for (int i = threadIdx.x; i < nbk * 16; i += blockDim.x) gdst[i] = T(blk[(i >> 4) * kLdsBlockStride + (i & 15)]);
+        for (int i = threadIdx.x; i < nn * 4; i += blockDim.x) rhs[4 * (size_t)n0 + i] = rr[i];
     }
+    for (int i = threadIdx.x; i < nn * 4; i += blockDim.x) rglob[4 * (size_t)n0 + i] = rg[i];
     rf2 = wave_sum(rf2);
     if ((threadIdx.x & 63) == 0 && rf2 != 0.0) atomic_add(&red_slots[(blockIdx.x & 63) * 8], rf2);
 }
@@ -542,17 +703,6 @@ __global__ void update_kernel(int n_nodes, const uint8_t* __restrict__ dmask, co
     u[i] += du[i];
 }
 
-// Unit diagonal on Dirichlet dofs (their rows and columns were skipped by the scatter).
-template <typename T>
-__global__ void dirichlet_diag_kernel(int n_dir, const int32_t* __restrict__ dlist,
-                                      const int32_t* __restrict__ diagpos, T* __restrict__ Aval) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_dir) return;
-    const int d = dlist[k];
-    const int c = d & 3;
-    Aval[(size_t)diagpos[d >> 2] * 16 + c * 4 + c] = T(1);
-}
-
 // Newton residual norm: free-dof sum of rglob^2 plus the |R_f|^2 slots.
 __global__ __launch_bounds__(kBlock) void norm_finalize_kernel(int n, const double* __restrict__ rglob,
                                                                const double* __restrict__ slots,
@@ -574,14 +724,22 @@ __global__ __launch_bounds__(kBlock) void norm_finalize_kernel(int n, const doub
         last = prev == gridDim.x - 1;
     }
     __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        double t = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k)
-            t += __hip_atomic_load(&red->partial[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int k = 0; k < 64; ++k)
-            t += __hip_atomic_load(&slots[k * 8], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        out[0] = sqrt(t);
+    if (!last) return;
+    __threadfence();
+    // all lanes of the last workgroup sum a strided share of the partials (fixed order)
+    double t = 0.0;
+    for (unsigned k = threadIdx.x; k < gridDim.x; k += blockDim.x)
+        t += __hip_atomic_load(&red->partial[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 64) t += __hip_atomic_load(&slots[threadIdx.x * 8], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double v[1] = {t};
+    v[0] = wave_sum(v[0]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v[0];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) tot += ws[w];
+        out[0] = sqrt(tot);
         red->counter = 0u;
     }
 }
@@ -612,42 +770,71 @@ ElemArgs make_args(vms_ctx* c, const double* u, const double* u_prev, const doub
 
 double* slots_of(vms_ctx* c) { return c->red->acc_slots; }
 
+TileArgs tile_args(vms_ctx* c) {
+    TileArgs t;
+    t.node0 = c->tile_node0;
+    t.iptr = c->tile_iptr;
+    t.ea = c->item_ea;
+    t.pos = c->item_pos;
+    t.rowptr = c->rowptr;
+    t.diagpos = c->diagpos;
+    return t;
+}
+
 }  // namespace
+
+hipError_t tile_kernels_configure(vms_ctx* c) {
+    const int lds = (int)c->tile_lds;
+    hipError_t e = hipFuncSetAttribute((const void*)tile_kernel<double, double, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)tile_kernel<float, MixedAcc, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)tile_kernel<double, double, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return e;
+}
 
 int launch_condense(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
                     double inv_dt, const double* body, void* A, double* rhs, double* rglob,
                     double* /*red_acc*/, hipStream_t s) {
     const size_t es = elt_size(c);
+    const double nn = c->n_nodes, ne = c->n_elems;
     int rc;
-    if ((rc = launch_fill(A, (size_t)c->nb * 16 * es, s))) return rc;
-    if ((rc = launch_fill(rhs, 4 * (size_t)c->n_nodes * sizeof(double), s))) return rc;
-    if ((rc = launch_fill(rglob, 4 * (size_t)c->n_nodes * sizeof(double), s))) return rc;
-    if ((rc = launch_fill(slots_of(c), 64 * 8 * sizeof(double), s))) return rc;
-    flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
-    ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
-    const int g = grid_for(c->n_elems);
-    if (c->prec == VMS_FP64) {
-        condense_kernel<double><<<g, kBlock, 0, s>>>(a, c->epos, (double*)A, rhs, rglob, slots_of(c));
-        if (c->n_dir)
-            dirichlet_diag_kernel<double><<<grid_for(c->n_dir), kBlock, 0, s>>>(c->n_dir, c->dlist, c->diagpos,
-                                                                               (double*)A);
-    } else {
-        condense_kernel<float><<<g, kBlock, 0, s>>>(a, c->epos, (float*)A, rhs, rglob, slots_of(c));
-        if (c->n_dir)
-            dirichlet_diag_kernel<float><<<grid_for(c->n_dir), kBlock, 0, s>>>(c->n_dir, c->dlist, c->diagpos,
-                                                                              (float*)A);
+    {
+        PhaseScope ph(c, VMS_PH_FILL, 64.0 * 8, s);
+        if ((rc = launch_fill(slots_of(c), 64 * 8 * sizeof(double), s))) return rc;
+        flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
     }
+    ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
+    // algorithmic bytes: connectivity + beta per element; coordinates, state (and previous
+    // velocity, body force) per node; block-CSR values, rhs and residual written once
+    const double alg = ne * (16.0 + 24.0) + nn * (24.0 + 32.0 + (a.u_prev ? 24.0 : 0.0) + (body ? 24.0 : 0.0)) +
+                       (double)c->nb * 16 * es + 2 * 32.0 * nn;
+    PhaseScope ph(c, VMS_PH_CONDENSE, alg, s);
+    if (c->prec == VMS_FP64)
+        tile_kernel<double, double, true><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (double*)A, rhs, rglob,
+                                                                         slots_of(c));
+    else
+        tile_kernel<float, MixedAcc, true><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (float*)A, rhs, rglob,
+                                                                        slots_of(c));
     return check_hip(c, hipGetLastError(), "condense launch");
 }
 
 int launch_residual(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
                     double inv_dt, const double* body, double* rglob, double* /*red_acc*/, hipStream_t s) {
     int rc;
-    if ((rc = launch_fill(rglob, 4 * (size_t)c->n_nodes * sizeof(double), s))) return rc;
     if ((rc = launch_fill(slots_of(c), 64 * 8 * sizeof(double), s))) return rc;
     flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
     ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
-    residual_kernel<<<grid_for(c->n_elems), kBlock, 0, s>>>(a, rglob, slots_of(c));
+    {
+        const double nn = c->n_nodes, ne = c->n_elems;
+        PhaseScope ph(c, VMS_PH_RESIDUAL,
+                      ne * 40.0 + nn * (56.0 + (a.u_prev ? 24.0 : 0.0) + (body ? 24.0 : 0.0)) + 32.0 * nn, s);
+        tile_kernel<double, double, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (double*)nullptr,
+                                                                          nullptr, rglob, slots_of(c));
+    }
     return check_hip(c, hipGetLastError(), "residual launch");
 }
 
@@ -731,7 +918,12 @@ extern "C" int vms_recover_update(vms_ctx* c, double* u, double* beta, const dou
     flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
     ElemArgs a = make_args(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body);
     // beta is read and written by the same lane only, so the update is in place.
-    recover_kernel<<<grid_for(c->n_elems), kBlock, 0, s>>>(a, du, beta);
+    {
+        const double nn = c->n_nodes, ne = c->n_elems;
+        PhaseScope ph(c, VMS_PH_RECOVER,
+                      ne * (16.0 + 48.0) + nn * (56.0 + 32.0 + (a.u_prev ? 24.0 : 0.0) + (body ? 24.0 : 0.0)), s);
+        recover_kernel<<<grid_for(c->n_elems), kBlock, 0, s>>>(a, du, beta);
+    }
     update_kernel<<<grid_for(4 * (int64_t)c->n_nodes), kBlock, 0, s>>>(c->n_nodes, c->dmask, du, u);
     return check_hip(c, hipGetLastError(), "recover launch");
 }

@@ -176,23 +176,90 @@ __device__ __forceinline__ bool arrive_last(unsigned* counter) {
     return last;
 }
 
-// norm of a vector -> gs->beta, initialises the cycle (g = beta e_1, k = 0, done flag).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __restrict__ r, RedScratch* red,
-                                                             GmresState* gs, double tol_abs) {
+// Inside the last-arriving workgroup: out[i] = sum_k part[i * ld + k], k < nk, for i < nvec.
+// Threads form groups of P lanes (P a power of two, P <= 64) per vector; each lane sums a
+// fixed stride of partials and the group combines them with shuffles (fixed order).
+__device__ void reduce_partials(const double* part, int ld, int nvec, int nk, double* out) {
+    int P = 64;
+    while (P > 1 && P * nvec > (int)blockDim.x) P >>= 1;
+    const int i = threadIdx.x / P, lane = threadIdx.x % P;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (i < nvec) {
+        const double* pi = part + (size_t)i * ld;
+        int k = lane;
+        for (; k + 3 * P < nk; k += 4 * P) {
+            s0 += ld_agent(pi + k);
+            s1 += ld_agent(pi + k + P);
+            s2 += ld_agent(pi + k + 2 * P);
+            s3 += ld_agent(pi + k + 3 * P);
+        }
+        for (; k < nk; k += P) s0 += ld_agent(pi + k);
+    }
+    double sum = (s0 + s1) + (s2 + s3);
+    for (int off = P / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if (i < nvec && lane == 0) out[i] = sum;
+}
+
+// dof idx is a pressure dof without a Dirichlet condition
+__device__ __forceinline__ bool free_pressure(const uint8_t* __restrict__ dmask, int idx) {
+    return (idx & 3) == 3 && !(dmask[idx >> 2] & 8u);
+}
+
+// Coarse correction on the constant pressure mode: kappa = 1 / sum of the entries of A
+// that couple two free pressure dofs (= 1 / (z^T A z) for z = 1 on the free pressure dofs).
+template <typename TA>
+__global__ __launch_bounds__(kBlock) void coarse_setup_kernel(int n_nodes, const int32_t* __restrict__ rowptr,
+                                                              const int32_t* __restrict__ colidx,
+                                                              const TA* __restrict__ A,
+                                                              const uint8_t* __restrict__ dmask, int enabled,
+                                                              RedScratch* red, GmresState* gs) {
     __shared__ double lds[kBlock / 64];
     double v[1] = {0.0};
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const double x = double(r[i]);
-        v[0] += x * x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes; i += gridDim.x * blockDim.x) {
+        if (dmask[i] & 8u) continue;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (!(dmask[colidx[k]] & 8u)) v[0] += double(A[(size_t)k * 16 + 15]);
     }
     block_sum<1>(v, lds);
     if (threadIdx.x == 0) red->partial[blockIdx.x] = v[0];
-    if (arrive_last(&red->counter) && threadIdx.x == 0) {
+    if (!arrive_last(&red->counter)) return;
+    __threadfence();
+    __shared__ double tot;
+    reduce_partials(red->partial, kRedBlocks, 1, gridDim.x, &tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        gs->kappa = (enabled && tot != 0.0 && isfinite(tot)) ? 1.0 / tot : 0.0;
+        red->counter = 0u;
+    }
+}
+
+// norm of a vector -> gs->beta, initialises the cycle (g = beta e_1, k = 0, done flag).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __restrict__ r,
+                                                             const uint8_t* __restrict__ dmask, RedScratch* red,
+                                                             GmresState* gs, double tol_abs) {
+    __shared__ double lds[(kBlock / 64) * 2];
+    double v[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double x = double(r[i]);
+        v[0] += x * x;
+        if (free_pressure(dmask, i)) v[1] += x;
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        red->partial[blockIdx.x] = v[0];
+        red->partial[kRedBlocks + blockIdx.x] = v[1];
+    }
+    __shared__ double tot[2];
+    const bool last = arrive_last(&red->counter);
+    if (last) {
         __threadfence();
-        double t = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) t += ld_agent(&red->partial[k]);
-        const double nrm = sqrt(t);
+        reduce_partials(red->partial, kRedBlocks, 2, gridDim.x, tot);
+        __syncthreads();
+    }
+    if (last && threadIdx.x == 0) {
+        const double nrm = sqrt(tot[0]);
+        gs->sv = nrm > 0.0 ? tot[1] / nrm : 0.0;
         gs->beta = nrm;
         gs->g[0] = nrm;
         gs->k = 0;
@@ -215,7 +282,8 @@ __global__ void cycle_v0_kernel(int n, const T* __restrict__ r, T* __restrict__ 
 // Arnoldi step j, part 1: v_j = w / h(j, j-1) (j > 0), z = Minv v_j.
 template <typename T>
 __global__ void arnoldi_pc_kernel(int n_nodes, int j, T* __restrict__ V, const T* __restrict__ w,
-                                  const T* __restrict__ Minv, T* __restrict__ z, const GmresState* gs) {
+                                  const T* __restrict__ Minv, const uint8_t* __restrict__ dmask, T* __restrict__ z,
+                                  const GmresState* gs) {
     if (gs->done) return;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = tid >> 2, r = tid & 3;
@@ -238,42 +306,67 @@ __global__ void arnoldi_pc_kernel(int n_nodes, int j, T* __restrict__ V, const T
         v4 = *reinterpret_cast<const V4*>(vj + 4 * (size_t)node);
     }
     const V4 m = *reinterpret_cast<const V4*>(Minv + (size_t)node * 16 + r * 4);
-    z[4 * (size_t)node + r] = m.x * v4.x + m.y * v4.y + m.z * v4.z + m.w * v4.w;
+    T zz = m.x * v4.x + m.y * v4.y + m.z * v4.z + m.w * v4.w;
+    if (r == 3 && !(dmask[node] & 8u)) zz += T(gs->kappa * gs->sv);
+    z[4 * (size_t)node + r] = zz;
 }
 
-// Classical Gram-Schmidt dots: partial[i][blk] = sum over the block's range of V_i . w, i <= j.
-// The last workgroup sums the partials (fixed order) into gs->hcol.
+// Classical Gram-Schmidt dots: h_i = V_i . w for i <= j.  Grid (chunks, groups of 8
+// vectors); each workgroup writes 8 partial sums, the last one to arrive sums all partials in
+// a fixed order into gs->hcol.
+constexpr int kDotVecs = 8;
+constexpr int kDotItems = 4;     // elements per thread per pass
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T* __restrict__ V,
                                                           const T* __restrict__ w, RedScratch* red,
                                                           GmresState* gs) {
     if (gs->done) return;
-    __shared__ double lds[(kBlock / 64) * 8];
+    __shared__ double lds[(kBlock / 64) * kDotVecs];
     const size_t N = (size_t)n;
-    for (int i0 = 0; i0 <= j; i0 += 8) {
-        double acc[8];
+    const int i0 = blockIdx.y * kDotVecs;
+    const int nv = min(kDotVecs, j + 1 - i0);
+    double acc[kDotVecs];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-        for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
-            const double wv = double(w[idx]);
+    for (int q = 0; q < kDotVecs; ++q) acc[q] = 0.0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x + threadIdx.x; base < n; base += stride * kDotItems) {
+        double wv[kDotItems];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (i0 + q <= j) acc[q] += double(V[(size_t)(i0 + q) * N + idx]) * wv;
+        for (int it = 0; it < kDotItems; ++it) {
+            const int idx = base + it * stride;
+            wv[it] = idx < n ? double(w[idx]) : 0.0;
         }
-        block_sum<8>(acc, lds);
-        if (threadIdx.x == 0)
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (i0 + q <= j) red->partial[(size_t)(i0 + q) * kRedBlocks + blockIdx.x] = acc[q];
-        __syncthreads();
+        for (int q = 0; q < kDotVecs; ++q) {
+            if (q < nv) {
+                const T* vq = V + (size_t)(i0 + q) * N;
+#pragma unroll
+                for (int it = 0; it < kDotItems; ++it) {
+                    const int idx = base + it * stride;
+                    if (idx < n) acc[q] += double(vq[idx]) * wv[it];
+                }
+            }
+        }
     }
-    if (arrive_last(&red->counter)) {
+    block_sum<kDotVecs>(acc, lds);
+    const int nblk = gridDim.x * gridDim.y;
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < kDotVecs; ++q)
+            if (q < nv) red->partial[(size_t)(i0 + q) * kRedBlocks + blockIdx.x] = acc[q];
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
         __threadfence();
-        for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-            double t = 0.0;
-            for (unsigned k = 0; k < gridDim.x; ++k) t += ld_agent(&red->partial[(size_t)i * kRedBlocks + k]);
-            gs->hcol[i] = t;
-        }
+        const unsigned prev = atomicAdd(&red->counter, 1u);
+        last = prev == (unsigned)nblk - 1;
+    }
+    __syncthreads();
+    (void)bid;
+    if (last) {
+        __threadfence();
+        reduce_partials(red->partial, kRedBlocks, j + 1, gridDim.x, gs->hcol);
         __syncthreads();
         if (threadIdx.x == 0) red->counter = 0u;
     }
@@ -284,46 +377,73 @@ __global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T*
 // rotations and updates the residual estimate and the done flag.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const T* __restrict__ V,
-                                                            T* __restrict__ w, RedScratch* red, GmresState* gs,
-                                                            int first_pass, int final_pass) {
+                                                            T* __restrict__ w, const uint8_t* __restrict__ dmask,
+                                                            RedScratch* red, GmresState* gs, int first_pass,
+                                                            int final_pass) {
     if (gs->done) return;
     __shared__ double hs[kMaxRestart + 1];
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[(kBlock / 64) * 2];
     for (int i = threadIdx.x; i <= j; i += blockDim.x) hs[i] = gs->hcol[i];
     __syncthreads();
     const size_t N = (size_t)n;
-    double v[1] = {0.0};
+    double v[2] = {0.0, 0.0};
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
         double s = double(w[idx]);
-        for (int i = 0; i <= j; ++i) s -= hs[i] * double(V[(size_t)i * N + idx]);
+        int i = 0;
+        // groups of 8 independent loads keep several memory requests in flight per lane
+        for (; i + 8 <= j + 1; i += 8) {
+            double vv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) vv[q] = double(V[(size_t)(i + q) * N + idx]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s -= hs[i + q] * vv[q];
+        }
+        for (; i <= j; ++i) s -= hs[i] * double(V[(size_t)i * N + idx]);
         const T sv = T(s);
         w[idx] = sv;
         v[0] += double(sv) * double(sv);
+        if (free_pressure(dmask, idx)) v[1] += double(sv);
     }
-    block_sum<1>(v, lds);
-    if (threadIdx.x == 0) red->partial[blockIdx.x] = v[0];
-    if (arrive_last(&red->counter) && threadIdx.x == 0) {
-        __threadfence();
-        constexpr int ld = kMaxRestart + 1;
-        double* Hj = gs->H + (size_t)j * ld;
-        for (int i = 0; i <= j; ++i) Hj[i] = first_pass ? hs[i] : Hj[i] + hs[i];
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        red->partial[blockIdx.x] = v[0];
+        red->partial[kRedBlocks + blockIdx.x] = v[1];
+    }
+    if (!arrive_last(&red->counter)) return;
+    __threadfence();
+    constexpr int ld = kMaxRestart + 1;
+    __shared__ double col[kMaxRestart + 2], csl[kMaxRestart], snl[kMaxRestart];
+    __shared__ double tot[2];
+    double* Hj = gs->H + (size_t)j * ld;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        const double h = first_pass ? hs[i] : Hj[i] + hs[i];
+        Hj[i] = h;
+        col[i] = h;
+    }
+    if (final_pass) {
+        for (int i = threadIdx.x; i < j; i += blockDim.x) {
+            csl[i] = gs->cs[i];
+            snl[i] = gs->sn[i];
+        }
+        reduce_partials(red->partial, kRedBlocks, 2, gridDim.x, tot);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         if (final_pass) {
-            double t = 0.0;
-            for (unsigned k = 0; k < gridDim.x; ++k) t += ld_agent(&red->partial[k]);
-            const double hn = sqrt(t);
+            const double hn = sqrt(tot[0]);
             Hj[j + 1] = hn;
-            // apply the previous rotations to the new column, then a new rotation
+            gs->sv = hn > 0.0 ? tot[1] / hn : 0.0;   // free-pressure sum of the next basis vector
+            // previous rotations on the new column: the running entry is carried in a register
             double* Rj = gs->R + (size_t)j * ld;
-            double below = hn;
-            for (int i = 0; i <= j; ++i) Rj[i] = Hj[i];
+            double x = col[0];
             for (int i = 0; i < j; ++i) {
-                const double a = gs->cs[i] * Rj[i] + gs->sn[i] * Rj[i + 1];
-                Rj[i + 1] = -gs->sn[i] * Rj[i] + gs->cs[i] * Rj[i + 1];
-                Rj[i] = a;
+                const double y = col[i + 1];
+                Rj[i] = csl[i] * x + snl[i] * y;
+                x = -snl[i] * x + csl[i] * y;
             }
-            const double d = hypot(Rj[j], below);
-            const double cs = d > 0.0 ? Rj[j] / d : 1.0;
-            const double sn = d > 0.0 ? below / d : 0.0;
+            const double d = hypot(x, hn);
+            const double cs = d > 0.0 ? x / d : 1.0;
+            const double sn = d > 0.0 ? hn / d : 0.0;
             gs->cs[j] = cs;
             gs->sn[j] = sn;
             Rj[j] = d;
@@ -339,19 +459,6 @@ __global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const 
     }
 }
 
-// Back substitution R y = g over the k completed steps (one lane).
-__global__ void solve_y_kernel(GmresState* gs) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double* Rtri = gs->R;
-    const int k = gs->k;
-    constexpr int ld = kMaxRestart + 1;
-    for (int i = k - 1; i >= 0; --i) {
-        double s = gs->g[i];
-        for (int c = i + 1; c < k; ++c) s -= Rtri[(size_t)c * ld + i] * gs->y[c];
-        gs->y[i] = s / Rtri[(size_t)i * ld + i];
-    }
-}
-
 // t = sum_{i<k} y_i V_i
 template <typename T>
 __global__ void combine_kernel(int n, const T* __restrict__ V, const GmresState* gs, T* __restrict__ t) {
@@ -364,9 +471,32 @@ __global__ void combine_kernel(int n, const T* __restrict__ V, const GmresState*
     t[idx] = T(s);
 }
 
-// x += Minv t (x in TX: double for the FP64 solution, float for an inner correction)
+// gs->st = sum of the free pressure entries of t (for the coarse term of P t)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void free_pressure_sum_kernel(int n_nodes, const T* __restrict__ t,
+                                                                   const uint8_t* __restrict__ dmask,
+                                                                   RedScratch* red, GmresState* gs) {
+    __shared__ double lds[kBlock / 64];
+    double v[1] = {0.0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes; i += gridDim.x * blockDim.x)
+        if (!(dmask[i] & 8u)) v[0] += double(t[4 * (size_t)i + 3]);
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) red->partial[blockIdx.x] = v[0];
+    if (!arrive_last(&red->counter)) return;
+    __threadfence();
+    __shared__ double tot;
+    reduce_partials(red->partial, kRedBlocks, 1, gridDim.x, &tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        gs->st = tot;
+        red->counter = 0u;
+    }
+}
+
+// x += P t = Minv t + z kappa (z^T t)  (x in TX: double for the FP64 solution, float for an inner correction)
 template <typename T, typename TX>
 __global__ void precond_accumulate_kernel(int n_nodes, const T* __restrict__ Minv, const T* __restrict__ t,
+                                          const uint8_t* __restrict__ dmask, const GmresState* gs,
                                           TX* __restrict__ x) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = tid >> 2, r = tid & 3;
@@ -374,8 +504,9 @@ __global__ void precond_accumulate_kernel(int n_nodes, const T* __restrict__ Min
     using V4 = typename Vec4<T>::type;
     const V4 m = *reinterpret_cast<const V4*>(Minv + (size_t)node * 16 + r * 4);
     const V4 v = *reinterpret_cast<const V4*>(t + 4 * (size_t)node);
-    const double s = double(m.x) * double(v.x) + double(m.y) * double(v.y) + double(m.z) * double(v.z) +
-                     double(m.w) * double(v.w);
+    double s = double(m.x) * double(v.x) + double(m.y) * double(v.y) + double(m.z) * double(v.z) +
+               double(m.w) * double(v.w);
+    if (r == 3 && !(dmask[node] & 8u)) s += gs->kappa * gs->st;
     x[4 * (size_t)node + r] = TX(double(x[4 * (size_t)node + r]) + s);
 }
 
@@ -391,11 +522,13 @@ __global__ __launch_bounds__(kBlock) void norm_kernel(int n, const T* __restrict
     }
     block_sum<1>(v, lds);
     if (threadIdx.x == 0) red->partial[blockIdx.x] = v[0];
-    if (arrive_last(&red->counter) && threadIdx.x == 0) {
-        __threadfence();
-        double t = 0.0;
-        for (unsigned k = 0; k < gridDim.x; ++k) t += ld_agent(&red->partial[k]);
-        out[0] = sqrt(t);
+    if (!arrive_last(&red->counter)) return;
+    __threadfence();
+    __shared__ double tot;
+    reduce_partials(red->partial, kRedBlocks, 1, gridDim.x, &tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = sqrt(tot);
         red->counter = 0u;
     }
 }
@@ -436,19 +569,37 @@ int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double 
     T* V = (T*)c->V;
     T* w = (T*)c->w;
     T* z = (T*)c->z;
-    cycle_start_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, r0, c->red, c->gs, tol_abs);
+    cycle_start_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, r0, c->dmask, c->red, c->gs, tol_abs);
     cycle_v0_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, r0, V, c->gs);
     const int steps = std::min(m, budget);
     const int check_every = 5;
+    const double vb = (double)n * sizeof(T);      // bytes of one Krylov vector
+    const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 2.0 * vb;
     for (int j = 0; j < steps; ++j) {
-        arnoldi_pc_kernel<T><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, j, V, w, Minv, z, c->gs);
-        spmv_kernel<T, T, T, T, 0><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, c->rowptr, c->colidx, A, z,
-                                                                  (const double*)nullptr, w, &c->gs->done);
+        {
+            PhaseScope ph(c, VMS_PH_PCAPPLY, 3.0 * vb + 4.0 * vb, s);
+            arnoldi_pc_kernel<T><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, j, V, w, Minv, c->dmask, z, c->gs);
+        }
+        {
+            PhaseScope ph(c, VMS_PH_SPMV, spmv_bytes, s);
+            spmv_kernel<T, T, T, T, 0><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, c->rowptr, c->colidx, A, z,
+                                                                      (const double*)nullptr, w, &c->gs->done);
+        }
         const int passes = cgs2 ? 2 : 1;
         for (int p = 0; p < passes; ++p) {
-            cgs_dots_kernel<T><<<red_grid(n / 4), kBlock, 0, s>>>(n, j, V, w, c->red, c->gs);
-            cgs_update_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, j, V, w, c->red, c->gs, p == 0,
-                                                                p == passes - 1);
+            {
+                PhaseScope ph(c, VMS_PH_DOTS, (j + 2) * vb, s);
+                const int groups = (j + kDotVecs) / kDotVecs;
+                const int gx = std::max(1, std::min(kRedBlocks, std::min(grid_for(n, kBlock * kDotItems),
+                                                                         std::max(1, 2048 / groups))));
+                cgs_dots_kernel<T><<<dim3(gx, groups), kBlock, 0, s>>>(n, j, V, w, c->red, c->gs);
+            }
+            {
+                PhaseScope ph(c, VMS_PH_UPDATE, (j + 3) * vb, s);
+                cgs_update_kernel<T><<<std::min(kRedBlocks, grid_for(n)), kBlock, 0, s>>>(n, j, V, w, c->dmask, c->red,
+                                                                                           c->gs, p == 0,
+                                                                    p == passes - 1);
+            }
         }
         if ((j + 1) % check_every == 0 || j + 1 == steps) {
             int h[2];
@@ -461,9 +612,26 @@ int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double 
         }
     }
     if (st->k > 0) {
-        solve_y_kernel<<<1, 64, 0, s>>>(c->gs);
+        // back substitution R y = g on the host (R is at most kMaxRestart square)
+        const int k = st->k;
+        constexpr int ld = kMaxRestart + 1;
+        std::vector<double> R((size_t)k * ld), g(k), y(k);
+        if (check_hip(c, hipMemcpyAsync(R.data(), c->gs->R, R.size() * sizeof(double), hipMemcpyDeviceToHost, s),
+                      "read R") ||
+            check_hip(c, hipMemcpyAsync(g.data(), c->gs->g, k * sizeof(double), hipMemcpyDeviceToHost, s), "read g") ||
+            check_hip(c, hipStreamSynchronize(s), "sync"))
+            return -1;
+        for (int i = k - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int cc = i + 1; cc < k; ++cc) acc -= R[(size_t)cc * ld + i] * y[cc];
+            y[i] = acc / R[(size_t)i * ld + i];
+        }
+        if (check_hip(c, hipMemcpyAsync(c->gs->y, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s), "write y") ||
+            check_hip(c, hipStreamSynchronize(s), "sync"))
+            return -1;
         combine_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, V, c->gs, z);
-        precond_accumulate_kernel<T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, x);
+        free_pressure_sum_kernel<T><<<red_grid(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, z, c->dmask, c->red, c->gs);
+        precond_accumulate_kernel<T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, c->dmask, c->gs, x);
     }
     return st->k;
 }
@@ -494,6 +662,7 @@ int launch_spmv(vms_ctx* c, const void* A, const void* x, void* y, hipStream_t s
 }
 
 int launch_bj_setup(vms_ctx* c, const void* A, void* Minv, hipStream_t s) {
+    PhaseScope ph(c, VMS_PH_PCSETUP, (double)c->n_nodes * (32.0 * elt_size(c) + 4.0), s);
     if (c->prec == VMS_FP64)
         bj_setup_kernel<double, double><<<grid_for(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, c->diagpos,
                                                                               (const double*)A, (double*)Minv,
@@ -541,6 +710,12 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     } else {
         if ((rc = launch_bj_setup(c, A, c->Minv, s))) return rc;
     }
+    if (c->prec == VMS_FP64)
+        coarse_setup_kernel<double><<<red_grid(c->n_nodes), kBlock, 0, s>>>(
+            c->n_nodes, c->rowptr, c->colidx, (const double*)A, c->dmask, o->coarse_pressure, c->red, c->gs);
+    else
+        coarse_setup_kernel<float><<<red_grid(c->n_nodes), kBlock, 0, s>>>(
+            c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, o->coarse_pressure, c->red, c->gs);
     norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, b, c->red, c->rnorm + 3);
     double bn = 0.0;
     if ((rc = read_scalar(c, c->rnorm + 3, &bn, s))) return rc;

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <type_traits>
+#include <vector>
 
 #include "vms.h"
 
@@ -15,6 +17,33 @@ namespace vms {
 constexpr int kBlock = 256;          // threads per workgroup for streaming kernels
 constexpr int kRedBlocks = 1024;     // workgroups of the grid-wide reductions
 constexpr int kMaxRestart = 128;
+constexpr int kTileNodes = 64;           // max nodes owned by one assembly tile
+#ifndef VMS_TILE_BLOCKS_FP64
+#define VMS_TILE_BLOCKS_FP64 420
+#endif
+#ifndef VMS_TILE_BLOCKS_FP32
+#define VMS_TILE_BLOCKS_FP32 870
+#endif
+#ifndef VMS_LDS_BLOCK_STRIDE
+#define VMS_LDS_BLOCK_STRIDE 17
+#endif
+#ifndef VMS_MIXED_LDS_FP64
+#define VMS_MIXED_LDS_FP64 1
+#endif
+// accumulator type of the staged blocks in the mixed-precision assembly
+using MixedAcc = std::conditional_t<VMS_MIXED_LDS_FP64 != 0, double, float>;
+constexpr size_t kMixedAccSize = sizeof(MixedAcc);
+constexpr int kTileBlocksFP64 = VMS_TILE_BLOCKS_FP64;   // max 4x4 blocks staged in LDS per tile (FP64 values)
+constexpr int kTileBlocksFP32 = VMS_TILE_BLOCKS_FP32;   // same for FP32 values (LDS per tile stays under 64 KB)
+
+// Dynamic LDS of a tile: block values (each 4x4 block padded to 17 entries so that the
+// lanes of a wave, which update the same entry of different blocks, spread over the LDS
+// banks), rhs rows and residual rows.
+constexpr int kLdsBlockStride = VMS_LDS_BLOCK_STRIDE;
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+__host__ __device__ inline size_t tile_lds_bytes(int64_t nblocks, int64_t nnodes, size_t elt) {
+    return align16(nblocks * kLdsBlockStride * elt) + 2 * nnodes * 4 * 8;
+}
 
 // Device-resident state of one GMRES cycle (Hessenberg matrix, Givens
 // rotations, residual estimate).  Updated by single-lane finalisers so that
@@ -30,6 +59,9 @@ struct GmresState {
     double tol_abs;                // stop when |g[k]| <= tol_abs
     double beta;                   // norm of the cycle's initial residual
     double norm;                   // scratch: a finished reduction
+    double kappa;                  // coarse pressure correction: 1 / (sum of free p-p entries), 0 = off
+    double sv;                     // sum of the free pressure entries of the current v_j
+    double st;                     // sum of the free pressure entries of the correction V y
     int k;                         // Arnoldi steps completed in this cycle
     int done;                      // 1: converged or breakdown, later kernels idle
     unsigned counter;              // arrival counter of last-block reductions
@@ -64,7 +96,15 @@ struct vms_ctx {
     int32_t* colidx = nullptr;       // [nb]
     int32_t* diagpos = nullptr;      // [n_nodes]
     int32_t* tpos = nullptr;         // [nb] position of the transposed block
-    int32_t* epos = nullptr;         // [16][n_elems] block of local pair (a, b), SoA
+    // assembly tiles: tile t owns block rows [tile_node0[t], tile_node0[t+1]) and works
+    // through work items (element e, owned vertex a): item_ea = 4 e + a, item_pos = the four
+    // tile-local block slots of row a (16 bits each)
+    int32_t n_tiles = 0;
+    int32_t* tile_node0 = nullptr;   // [n_tiles + 1]
+    int32_t* tile_iptr = nullptr;    // [n_tiles + 1]
+    int32_t* item_ea = nullptr;      // [4 n_elems]
+    uint2* item_pos = nullptr;       // [4 n_elems]
+    size_t tile_lds = 0;             // dynamic LDS bytes of the largest tile
 
     // Newton workspaces (device)
     void* A = nullptr;               // [nb][16] of the ctx precision
@@ -97,6 +137,16 @@ struct vms_ctx {
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::string err;
+
+    // phase timers
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;       // pairs
+    std::vector<int> prof_phase;           // pending slot -> phase
+    std::vector<double> prof_bytes;        // pending slot -> algorithmic bytes
+    int prof_used = 0;
+    double prof_ms[VMS_NPHASES] = {};
+    double prof_acc_bytes[VMS_NPHASES] = {};
+    int64_t prof_count[VMS_NPHASES] = {};
 };
 
 namespace vms {
@@ -105,7 +155,23 @@ int set_error(vms_ctx* ctx, int code, const std::string& msg);
 int check_hip(vms_ctx* ctx, hipError_t e, const char* what);
 inline size_t elt_size(const vms_ctx* c) { return c->prec == VMS_FP64 ? 8 : 4; }
 
+// phase timers (ctx.cpp): a scope records an event pair around the launches it encloses
+int prof_begin(vms_ctx* c, int phase, double bytes, hipStream_t s);
+void prof_end(vms_ctx* c, int slot, hipStream_t s);
+struct PhaseScope {
+    vms_ctx* c;
+    int slot;
+    hipStream_t s;
+    PhaseScope(vms_ctx* c_, int phase, double bytes, hipStream_t s_) : c(c_), slot(-1), s(s_) {
+        if (c->prof_on) slot = prof_begin(c, phase, bytes, s);
+    }
+    ~PhaseScope() {
+        if (slot >= 0) prof_end(c, slot, s);
+    }
+};
+
 // element kernels (element.hip)
+hipError_t tile_kernels_configure(vms_ctx* ctx);
 int launch_condense(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta,
                     double nu, double inv_dt, const double* body, void* A, double* rhs,
                     double* rglob, double* red_acc, hipStream_t s);

@@ -29,21 +29,57 @@ def set_dirichlet(u, dofs_dev, values_dev):
     u.view(-1).index_copy_(0, dofs_dev.long(), values_dev)
 
 
+def forcing_term(k, rn, rn_prev, eta_prev, tol, r0, eta_max=0.1, gamma=0.9):
+    """Linear tolerance of Newton step k (Eisenstat-Walker, second choice, with
+    the usual safeguards).  Never asks for more than what brings ||R|| to tol ||R_0||."""
+    if k == 0:
+        eta = eta_max
+    else:
+        eta = gamma * (rn / rn_prev) ** 2
+        if gamma * eta_prev ** 2 > 0.1:
+            eta = max(eta, gamma * eta_prev ** 2)
+        eta = min(eta, eta_max)
+    return max(eta, 0.5 * tol * r0 / rn)
+
+
 def newton_solve(ctx: B.Context, u, beta, Re, dt=0.0, u_prev=None, body=None, tol=1e-8, max_newton=25,
-                 lin: B.SolveOpts | None = None, stream=None, raise_on_fail=True) -> NewtonResult:
-    """Newton-Schur iterations until ||R_k|| <= tol ||R_0|| (FP64 residual)."""
+                 lin: B.SolveOpts | None = None, stream=None, raise_on_fail=True,
+                 forcing: str = "fixed") -> NewtonResult:
+    """Newton-Schur iterations until ||R_k|| <= tol ||R_0|| (FP64 residual).
+
+    forcing="fixed": every linear solve to lin.rtol.  forcing="ew": inexact
+    Newton, linear tolerance from forcing_term() (never below lin.rtol)."""
     lin = lin if lin is not None else B.solve_opts()
     res = NewtonResult(converged=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r0 = None
-    for _ in range(max_newton):
-        info = B.vms_newton_step(ctx, u, beta, Re, dt, u_prev, body, lin, stream)
+    rn_prev = None
+    eta = None
+    rn = None
+    for k in range(max_newton):
+        if forcing == "ew" and rn is not None:
+            eta = max(lin.rtol, forcing_term(k, rn, rn_prev, eta, tol, r0))
+            lin.rtol, saved = eta, lin.rtol
+        elif forcing == "ew":
+            saved = lin.rtol
+            eta = max(lin.rtol, 0.1)
+            lin.rtol = eta
+        else:
+            saved = lin.rtol
+        try:
+            info = B.vms_newton_step(ctx, u, beta, Re, dt, u_prev, body, lin, stream)
+        finally:
+            lin.rtol = saved
+        rn_prev = info.rnorm_before
+        rn = info.rnorm_after
         if r0 is None:
             r0 = info.rnorm_before
             res.rnorms.append(r0)
         res.rnorms.append(info.rnorm_after)
-        res.lin.append(info.lin.as_dict())
+        d = info.lin.as_dict()
+        d["rtol"] = eta if eta is not None else lin.rtol
+        res.lin.append(d)
         if info.rnorm_after <= tol * r0 or info.rnorm_after == 0.0:
             res.converged = True
             break

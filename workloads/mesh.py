@@ -9,9 +9,12 @@ random perturbation of the interior nodes.
 Layouts (host numpy arrays):
   xyz   float64 [n_nodes, 3]
   tets  int32   [n_elems, 4]   vertex ids, det[x1-x0, x2-x0, x3-x0] > 0
-Node numbering is lexicographic over the lattice (i, j, k) with k fastest,
-restricted to the nodes that active cells touch.  Cells are enumerated in
-the same lexicographic order, six tets per cell.
+Numbering: nodes and cells are numbered brick by brick (bricks of 4x4x4
+lattice points, bricks in lexicographic order, points inside a brick
+lexicographic with k fastest), restricted to the nodes that active cells
+touch; six tets per cell.  Contiguous ranges of node ids are then compact
+groups of nodes, which the GPU library's tiled assembly and SpMV exploit.
+order="lex" gives plain lexicographic numbering instead.
 """
 from __future__ import annotations
 
@@ -58,11 +61,21 @@ def _kuhn_offsets():
     return np.stack(tets)      # [6, 4, 3] integer corner offsets
 
 
-def kuhn_box(shape, lo, hi, cell_mask=None, name="box") -> Mesh:
+BRICK = 4
+
+
+def _brick_key(i, j, k, brick=BRICK):
+    """Sort key: brick index (lexicographic), then position inside the brick."""
+    bi, bj, bk = i // brick, j // brick, k // brick
+    big = 1 << 20
+    return (((bi * big + bj) * big + bk) * brick + i % brick) * brick * brick + (j % brick) * brick + k % brick
+
+
+def kuhn_box(shape, lo, hi, cell_mask=None, name="box", order="brick") -> Mesh:
     """Kuhn split of an (nx, ny, nz) lattice of cells spanning [lo, hi].
 
     cell_mask (bool [nx, ny, nz]) selects active cells; nodes not touched by
-    any active cell are dropped and the rest renumbered in lattice order.
+    any active cell are dropped and the rest numbered in `order`.
     """
     nx, ny, nz = (int(s) for s in shape)
     lo = np.asarray(lo, dtype=np.float64)
@@ -72,6 +85,9 @@ def kuhn_box(shape, lo, hi, cell_mask=None, name="box") -> Mesh:
     offs = _kuhn_offsets()
 
     ci, cj, ck = np.nonzero(cell_mask)          # lexicographic, k fastest
+    if order == "brick":
+        perm = np.argsort(_brick_key(ci, cj, ck), kind="stable")
+        ci, cj, ck = ci[perm], cj[perm], ck[perm]
     corner = np.stack([ci, cj, ck], axis=1)     # [n_cells, 3]
     # lattice coordinates of the 6x4 vertices of each cell
     lat = corner[:, None, None, :] + offs[None, :, :, :]          # [nc, 6, 4, 3]
@@ -80,14 +96,16 @@ def kuhn_box(shape, lo, hi, cell_mask=None, name="box") -> Mesh:
 
     used = np.zeros((nx + 1) * (ny + 1) * (nz + 1), dtype=bool)
     used[lin.ravel()] = True
-    new_id = -np.ones(used.size, dtype=np.int64)
-    new_id[used] = np.arange(int(used.sum()))
-    tets = new_id[lin].astype(np.int32)
-
-    idx = np.nonzero(used)[0]
+    idx = np.nonzero(used)[0]                   # lexicographic lattice ids of the nodes
     i = idx // ((ny + 1) * (nz + 1))
     j = (idx // (nz + 1)) % (ny + 1)
     k = idx % (nz + 1)
+    if order == "brick":
+        perm = np.argsort(_brick_key(i, j, k), kind="stable")
+        idx, i, j, k = idx[perm], i[perm], j[perm], k[perm]
+    new_id = -np.ones(used.size, dtype=np.int64)
+    new_id[idx] = np.arange(idx.size)
+    tets = new_id[lin].astype(np.int32)
     step = (hi - lo) / np.array([nx, ny, nz], dtype=np.float64)
     xyz = np.stack([lo[0] + i * step[0], lo[1] + j * step[1], lo[2] + k * step[2]], axis=1)
     mesh = Mesh(xyz=np.ascontiguousarray(xyz), tets=np.ascontiguousarray(tets),
@@ -121,15 +139,16 @@ def cavity_mesh(n: int) -> Mesh:
 def jittered_cube(n: int, seed: int = 0, amp: float = 0.2) -> Mesh:
     """Unit cube with every interior node displaced by U(-amp*h, amp*h) per coordinate.
 
-    The displacements are drawn for all lattice nodes in lexicographic order
-    (k fastest) from numpy.random.default_rng(seed) and applied only to
-    interior nodes, so the boundary stays planar.
+    The displacements are drawn for all lattice nodes in lexicographic lattice
+    order (k fastest) from numpy.random.default_rng(seed), whatever the node
+    numbering, and applied only to interior nodes, so the boundary stays planar.
     """
     m = kuhn_box((n, n, n), (0, 0, 0), (1, 1, 1), name=f"jitter{n}_s{seed}")
     h = 1.0 / n
     rng = np.random.default_rng(seed)
-    d = rng.uniform(-amp * h, amp * h, size=(m.n_nodes, 3))
     lat = m.meta["lattice_index"]
+    d_lex = rng.uniform(-amp * h, amp * h, size=((n + 1) ** 3, 3))
+    d = d_lex[(lat[:, 0] * (n + 1) + lat[:, 1]) * (n + 1) + lat[:, 2]]
     interior = np.all((lat > 0) & (lat < n), axis=1)
     m.xyz = m.xyz + d * interior[:, None]
     m.meta["seed"] = seed
