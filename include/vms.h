@@ -148,6 +148,11 @@ typedef struct {
                                   mode, P v = M v + z (z^T v) / (z^T A z), z = 1 on every
                                   free pressure dof.  With one pinned pressure dof that mode
                                   is nearly singular and restarted GMRES stalls on it.     */
+    float* log_residuals;      /* device float [log_max][n_nodes][4] or NULL: the true
+                                  residual b - A x at the start of every restart cycle
+                                  (refinement sweep in the mixed ctx) is copied here, as
+                                  training samples for the learned preconditioner          */
+    int32_t log_max;
 } vms_solve_opts;
 
 typedef struct {
@@ -156,6 +161,7 @@ typedef struct {
     int32_t refinements;       /* outer FP64 sweeps (mixed)                              */
     int32_t fell_back_to_bj;   /* learned preconditioner rejected (non-finite / failure) */
     double true_rel_res;       /* final ||b - A x|| / ||b|| recomputed in FP64           */
+    int32_t logged;            /* residuals written to log_residuals                      */
 } vms_solve_info;
 
 /* Right-preconditioned restarted GMRES(m) on A x = b (Section 6 names a

@@ -732,6 +732,11 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     int status = VMS_OK;
     for (;;) {
         if ((rc = true_residual(c, A, b, x, &rn, s))) return rc;
+        if (o->log_residuals && inf.logged < o->log_max) {
+            convert_kernel<double, float><<<grid_for(n), kBlock, 0, s>>>(
+                n, c->r64, o->log_residuals + (size_t)inf.logged * n, 1.0);
+            inf.logged++;
+        }
         if (!std::isfinite(rn)) {
             status = set_error(c, VMS_ENONFINITE, "gmres: non-finite residual");
             break;
