@@ -53,7 +53,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_0809_4802_amd import binding as B, driver
+    from paper_0809_4802_amd import binding as B, driver, learned
     from workloads import build_workload
 
     dev = "cuda:0"
@@ -65,16 +65,17 @@ def main():
     b0d = torch.from_numpy(beta0).to(dev)
     log(f"workload {args.workload}: {mesh.n_elems} tets, {mesh.n_nodes} nodes, Re {cfg.re}")
 
-    def lin_opts():
-        return B.solve_opts(restart=50, rtol=1e-9, max_iters=60000)
+    def lin_opts(weights=None):
+        return B.solve_opts(restart=50, rtol=1e-9, max_iters=60000,
+                            pc=B.VMS_PC_LEARNED if weights is not None else B.VMS_PC_BLOCK_JACOBI,
+                            pc_weights=weights)
 
-    def solve(ctx, prof=False):
+    def solve(ctx, weights=None):
         u = u0d.clone()
         beta = b0d.clone()
         torch.cuda.synchronize()
-        res = driver.newton_solve(ctx, u, beta, cfg.re, tol=cfg.newton_tol, lin=lin_opts(), forcing="ew",
-                                  max_newton=30)
-        return res
+        return driver.newton_solve(ctx, u, beta, cfg.re, tol=cfg.newton_tol, lin=lin_opts(weights), forcing="ew",
+                                   max_newton=30)
 
     ctxs = {"fp64": B.Context(xyz, tets, dd, precision=B.VMS_FP64),
             "mixed": B.Context(xyz, tets, dd, precision=B.VMS_MIXED)}
@@ -104,26 +105,43 @@ def main():
         del A, rhs
         log(f"assembly {name}: {assembly[name]}")
 
+    # ---- learned block-Jacobi correction: trained on the method's own condensed tangents and
+    # GMRES restart residuals (a mixed-precision Newton solve of this workload), checkpoints
+    # selected by GMRES iterations on the held-out last Newton system
+    t0 = time.perf_counter()
+    ctx = ctxs["mixed"]
+    data, _ = learned.collect_newton_data(ctx, u0d.clone(), b0d.clone(), cfg.re,
+                                          lin=B.solve_opts(restart=50, rtol=1e-4, max_iters=60000), per_step=48)
+    val = [(A, S[0].contiguous()) for A, S in data[-1:]]      # first logged residual = the rhs
+    weights, train_report = learned.train_validated(ctx, data[:-1] or data, val, steps=200, lr=3e-4)
+    train_report["seconds"] = time.perf_counter() - t0
+    log(f"learned PC: {train_report}")
+
     # ---- time to 1e-8 in every form (one warm-up + one timed solve each)
     forms = {}
-    for name, ctx in ctxs.items():
-        solve(ctx)
-        r = solve(ctx)
-        forms[name + "_bj"] = {"seconds": r.seconds, "newton_steps": len(r.rnorms) - 1,
-                               "gmres_iters": int(sum(d["iters"] for d in r.lin)),
-                               "final_rel_residual": r.rnorms[-1] / r.rnorms[0]}
-        log(f"time-to-1e-8 {name}+BJ: {forms[name + '_bj']}")
+    for name, ctx_name, w in (("fp64_bj", "fp64", None), ("mixed_bj", "mixed", None),
+                              ("mixed_learned", "mixed", weights)):
+        if name == "mixed_learned" and w is None:
+            forms[name] = dict(forms["mixed_bj"], note="validation selected plain block-Jacobi")
+            continue
+        solve(ctxs[ctx_name], w)
+        r = solve(ctxs[ctx_name], w)
+        forms[name] = {"seconds": r.seconds, "newton_steps": len(r.rnorms) - 1,
+                       "gmres_iters": int(sum(d["iters"] for d in r.lin)),
+                       "fell_back_to_bj": int(sum(d["fell_back_to_bj"] for d in r.lin)),
+                       "final_rel_residual": r.rnorms[-1] / r.rnorms[0]}
+        log(f"time-to-1e-8 {name}: {forms[name]}")
 
-    # ---- timed region: K headline solves
+    # ---- timed region: K headline solves (mixed precision + learned correction)
     ctx = ctxs[headline]
     for _ in range(args.warmup):
-        solve(ctx)
+        solve(ctx, weights)
     B.vms_profile(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps = []
     for _ in range(args.steps):
-        steps.append(solve(ctx))
+        steps.append(solve(ctx, weights))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = B.vms_profile_read(ctx)
@@ -163,10 +181,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: lid-driven cavity 32^3 cells x 6 tets ({mesh.n_elems} tets, "
                                f"{mesh.n_nodes} nodes), Re {cfg.re:g}, steady Newton to 1e-8, GMRES(50) + 4x4 "
-                               f"block-Jacobi, form {headline}",
+                               f"block-Jacobi (+ learned correction), form mixed_learned",
                    "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes},
         "time_to_1e-8_s": {k: v["seconds"] for k, v in forms.items()},
         "forms": forms,
+        "learned_pc": train_report,
         "assembly": assembly,
         "phases": phases,
         "roofline": roofline,

@@ -159,7 +159,9 @@ typedef struct {
     int32_t iters;             /* Arnoldi steps                                          */
     int32_t restarts;          /* cycles                                                 */
     int32_t refinements;       /* outer FP64 sweeps (mixed)                              */
-    int32_t fell_back_to_bj;   /* learned preconditioner rejected (non-finite / failure) */
+    int32_t fell_back_to_bj;   /* learned preconditioner rejected: non-finite blocks, or
+                                  no convergence within half of max_iters (the solve then
+                                  continues from its iterate with plain block-Jacobi)     */
     double true_rel_res;       /* final ||b - A x|| / ||b|| recomputed in FP64           */
     int32_t logged;            /* residuals written to log_residuals                      */
 } vms_solve_info;

@@ -730,7 +730,17 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     double rn = 0.0;
     int iters = 0;
     int status = VMS_OK;
+    const bool learned = o->pc == VMS_PC_LEARNED && o->pc_weights && !inf.fell_back_to_bj;
+    const int learned_budget = learned ? max_iters / 2 : max_iters;
+    bool using_learned = learned;
     for (;;) {
+        if (using_learned && iters >= learned_budget) {
+            // the learned blocks did not deliver within half the budget: continue from the
+            // current iterate with plain block-Jacobi
+            if ((rc = launch_bj_setup(c, A, c->Minv, s))) return rc;
+            using_learned = false;
+            inf.fell_back_to_bj = 1;
+        }
         if ((rc = true_residual(c, A, b, x, &rn, s))) return rc;
         if (o->log_residuals && inf.logged < o->log_max) {
             convert_kernel<double, float><<<grid_for(n), kBlock, 0, s>>>(
@@ -785,6 +795,11 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
                 spmv_kernel<float, float, float, float, 1, float><<<grid_for(n), kBlock, 0, s>>>(
                     c->n_nodes, c->rowptr, c->colidx, (const float*)A, d, rr, q, nullptr);
                 (void)Ad;
+                if (o->log_residuals && inf.logged < o->log_max) {
+                    convert_kernel<float, float><<<grid_for(n), kBlock, 0, s>>>(
+                        n, q, o->log_residuals + (size_t)inf.logged * n, 1.0);
+                    inf.logged++;
+                }
                 norm_kernel<float><<<red_grid(n), kBlock, 0, s>>>(n, q, c->red, c->rnorm + 2);
                 double qn = 0.0;
                 if ((rc = read_scalar(c, c->rnorm + 2, &qn, s))) return rc;

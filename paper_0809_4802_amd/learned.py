@@ -79,3 +79,46 @@ def collect_newton_data(ctx: B.Context, u, beta, Re, dt=0.0, u_prev=None, body=N
         data.append((A, log[:max(1, info.logged)].contiguous()))
         B.vms_recover_update(ctx, u, beta, du, Re, dt, u_prev, body)
     return data, hist
+
+
+def gmres_iterations(ctx: B.Context, A, b, weights, rtol=1e-4, max_iters=20000, restart=50):
+    """Arnoldi steps GMRES(restart) needs on A x = b with the learned blocks (None: block-Jacobi)."""
+    x = ctx.new_vec()
+    opts = B.solve_opts(restart=restart, rtol=rtol, max_iters=max_iters,
+                        pc=B.VMS_PC_LEARNED if weights is not None else B.VMS_PC_BLOCK_JACOBI,
+                        pc_weights=weights)
+    rc, info = B.vms_gmres_solve(ctx, A, b, x, opts, allow_noconv=True)
+    if rc != B.VMS_OK or info.fell_back_to_bj:
+        return max_iters
+    return int(info.iters)
+
+
+def train_validated(ctx: B.Context, data, val, steps=200, lr=3e-4, batch=8, seed=1, check_every=20,
+                    val_rtol=1e-4):
+    """Trains on `data` and keeps the checkpoint with the fewest GMRES iterations on the
+    held-out systems `val` (list of (bsr_vals, rhs)); plain block-Jacobi (the zero output
+    layer) is one of the candidates, so the result is never worse on the validation set.
+    Returns (weights or None for block-Jacobi, report)."""
+    def score(w):
+        return sum(gmres_iterations(ctx, A, b, w, rtol=val_rtol) for A, b in val)
+
+    base = score(None)
+    best_w, best = None, base
+    report = {"val_iters_bj": base, "checkpoints": []}
+    rng = np.random.default_rng(seed)
+    w = init_weights(seed, ctx.device)
+    state = torch.zeros(2 * B.PC_NWEIGHTS, dtype=torch.float32, device=ctx.device)
+    loss = torch.zeros(1, dtype=torch.float32, device=ctx.device)
+    for step in range(1, steps + 1):
+        A, S = data[rng.integers(len(data))]
+        k = min(batch, S.shape[0])
+        idx = torch.from_numpy(rng.choice(S.shape[0], size=k, replace=False)).to(ctx.device)
+        B.vms_pc_train_step(ctx, A, S.index_select(0, idx).contiguous(), w, state, step, lr, None, loss)
+        if step % check_every == 0:
+            s = score(w)
+            report["checkpoints"].append({"step": step, "loss": float(loss.item()), "val_iters": s})
+            if s < best:
+                best, best_w = s, w.clone()
+    report["selected"] = "bj" if best_w is None else "learned"
+    report["val_iters_selected"] = best
+    return best_w, report
