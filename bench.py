@@ -24,8 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_OF_PHASE = {"condense": "tile_kernel", "spmv": "spmv_kernel", "dots": "cgs_dots_kernel",
-                   "update": "cgs_update_kernel", "pc_apply": "arnoldi_pc_kernel"}
+KERNEL_OF_PHASE = {"condense": "tile_kernel", "spmv": "spmv_kernel", "dots": "dots2d_kernel",
+                   "update": "update_kernel", "pc_apply": "arnoldi_pc_kernel"}
 
 
 def parse():

@@ -12,7 +12,7 @@
 // (vx, vy, vz, p) of a node adjacent) so that a 4x4 block multiplies one
 // 32-byte (FP64) or 16-byte (FP32) segment.  The Hessenberg matrix, the Givens
 // rotations and the residual estimate live in device memory and are updated
-// by the last workgroup of each reduction, so an Arnoldi step is a fixed
+// by single-workgroup reduction kernels, so an Arnoldi step is a fixed
 // sequence of launches with no host round trip; the host looks at the
 // convergence flag only every few steps.
 #include <cstdio>
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void coarse_setup_kernel(int n_nodes, const
 template <typename T>
 __global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __restrict__ r,
                                                              const uint8_t* __restrict__ dmask, RedScratch* red,
-                                                             GmresState* gs, double tol_abs) {
+                                                             GmresState* gs, double tol_abs, int reorth) {
     __shared__ double lds[(kBlock / 64) * 2];
     double v[2] = {0.0, 0.0};
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -260,12 +260,16 @@ __global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __r
     if (last && threadIdx.x == 0) {
         const double nrm = sqrt(tot[0]);
         gs->sv = nrm > 0.0 ? tot[1] / nrm : 0.0;
+        gs->svs[0] = gs->sv;
         gs->beta = nrm;
         gs->g[0] = nrm;
+        gs->gin[0] = nrm;
         gs->k = 0;
         gs->tol_abs = tol_abs;
         gs->done = (nrm <= tol_abs || !(nrm > 0.0)) ? 1 : 0;
         gs->norm = nrm;
+        gs->reorth = reorth;
+        gs->redo = 0;
         red->counter = 0u;
     }
 }
@@ -279,7 +283,171 @@ __global__ void cycle_v0_kernel(int n, const T* __restrict__ r, T* __restrict__ 
     V0[i] = b > 0.0 ? T(double(r[i]) / b) : T(0);
 }
 
-// Arnoldi step j, part 1: v_j = w / h(j, j-1) (j > 0), z = Minv v_j.
+// ------------------------------------------------------------------- Arnoldi step kernels
+// Step j is a chain of small kernels; partial sums travel through plain-store slots and are
+// reduced by single-workgroup kernels, so no workgroup ever issues a device-scope fence (an
+// L2 write-back across the XCDs of this part) and every reduction has one level:
+//   arnoldi_pc     v_j = (w - V c) / h(j, j-1) (c = 0 unless step j-1 took a second pass),
+//                  z = P v_j (+ coarse pressure term)
+//   spmv           w = A z
+//   dots2d         slots: V_i . w (i <= j), w . w                        -> part
+//   reduce_h       h = slots, H(:, j) = h, ||w||^2                          (1 workgroup)
+//   update         w -= V h
+//   dots2d         slots: c = V^T w, w . w, free-pressure sum of w         -> part
+//   reduce_c       DGKS test: a second pass is taken when ||w|| < ||w_before|| / sqrt(2).
+//                  Its results need no further reduction: for orthonormal V,
+//                  ||w - V c||^2 = ||w||^2 - ||c||^2, and the free-pressure sum of w - V c is
+//                  S(w) - sum_i c_i S(v_i); H(:, j) += c.  Then h(j+1, j), Givens rotation,
+//                  residual estimate, done flag.  The subtraction w -= V c itself is folded
+//                  into the next arnoldi_pc.                               (1 workgroup)
+constexpr int kDotChunks = 64;            // workgroups per dot product
+constexpr int kDotThreads = 256;
+static_assert((kMaxRestart + 3) * kDotChunks <= kRedBlocks * (kMaxRestart + 1), "dot slots exceed scratch");
+
+// Slot y of a 2-D dot grid: y <= j -> V_y . w;  y == j+1 -> w . w;  y == j+2 -> free-pressure
+// sum of w.  One node (4 dofs) per vector load; one block reduction per workgroup.
+template <typename T>
+__global__ __launch_bounds__(kDotThreads) void dots2d_kernel(int n_nodes, int j, const T* __restrict__ V,
+                                                             const T* __restrict__ w,
+                                                             const uint8_t* __restrict__ dmask,
+                                                             double* __restrict__ part, const GmresState* gs) {
+    if (gs->done) return;
+    using V4 = typename Vec4<T>::type;
+    const int y = blockIdx.y;
+    const int kind = y <= j ? 0 : (y == j + 1 ? 1 : 2);
+    const V4* w4 = reinterpret_cast<const V4*>(w);
+    const V4* v4 = reinterpret_cast<const V4*>(V + (size_t)(kind == 0 ? y : 0) * 4 * (size_t)n_nodes);
+    const int per = (n_nodes + gridDim.x - 1) / gridDim.x;
+    const int i0 = blockIdx.x * per, i1 = min(n_nodes, i0 + per);
+    double acc = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const V4 b = w4[i];
+        if (kind == 0) {
+            const V4 a = v4[i];
+            acc += double(a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w);
+        } else if (kind == 1) {
+            acc += double(b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w);
+        } else if (!(dmask[i] & 8u)) {
+            acc += double(b.w);
+        }
+    }
+    acc = wave_sum(acc);
+    __shared__ double lds[kDotThreads / 64];
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kDotThreads / 64; ++k) t += lds[k];
+        part[(size_t)y * kDotChunks + blockIdx.x] = t;
+    }
+}
+
+// Sums the slots of a dot grid into LDS (one slot per thread group, fixed order).
+__device__ void sum_slots(const double* __restrict__ part, int ns, int nchunks, double* out) {
+    for (int sl = threadIdx.x; sl < ns; sl += blockDim.x) {
+        const double* p = part + (size_t)sl * kDotChunks;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int k = 0;
+        for (; k + 4 <= nchunks; k += 4) {
+            a0 += p[k];
+            a1 += p[k + 1];
+            a2 += p[k + 2];
+            a3 += p[k + 3];
+        }
+        for (; k < nchunks; ++k) a0 += p[k];
+        out[sl] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+}
+
+// Completes column jc with h(jc+1, jc) = hn (one workgroup): rotations from LDS, residual
+// estimate, done flag; sv = free-pressure sum of the next basis vector.
+__device__ void complete_column(int jc, double hn, double psum, GmresState* gs) {
+    constexpr int ld = kMaxRestart + 1;
+    __shared__ double col[kMaxRestart + 1], csl[kMaxRestart], snl[kMaxRestart];
+    const double* Hj = gs->H + (size_t)jc * ld;
+    for (int i = threadIdx.x; i <= jc; i += blockDim.x) col[i] = Hj[i];
+    for (int i = threadIdx.x; i < jc; i += blockDim.x) {
+        csl[i] = gs->cs[i];
+        snl[i] = gs->sn[i];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double* Rj = gs->R + (size_t)jc * ld;
+    double x = col[0];
+    for (int i = 0; i < jc; ++i) {
+        const double y = col[i + 1];
+        Rj[i] = csl[i] * x + snl[i] * y;
+        x = -snl[i] * x + csl[i] * y;
+    }
+    const double d = hypot(x, hn);
+    const double cs = d > 0.0 ? x / d : 1.0;
+    const double sn = d > 0.0 ? hn / d : 0.0;
+    const double gj = gs->gin[jc];
+    const double gnext = -sn * gj;
+    const bool conv = fabs(gnext) <= gs->tol_abs;
+    const bool breakdown = !(hn > 1e-300 * (fabs(d) + 1e-300)) || !isfinite(hn) || !isfinite(gnext);
+    Rj[jc] = d;
+    gs->cs[jc] = cs;
+    gs->sn[jc] = sn;
+    gs->g[jc] = cs * gj;
+    gs->gin[jc + 1] = gnext;
+    gs->H[(size_t)jc * ld + jc + 1] = hn;
+    gs->hn = hn;
+    gs->sv = hn > 0.0 ? psum / hn : 0.0;
+    gs->svs[jc + 1] = gs->sv;
+    gs->k = jc + 1;
+    if (conv || breakdown) gs->done = 1;
+}
+
+// reduce_h: h = V^T w, H(:, j) = h, ||w||^2 before orthogonalisation.
+__global__ __launch_bounds__(kBlock) void reduce_h_kernel(int j, int nchunks, const double* __restrict__ part,
+                                                          GmresState* gs) {
+    if (gs->done) return;
+    __shared__ double v[kMaxRestart + 3];
+    sum_slots(part, j + 2, nchunks, v);
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        gs->hcol[i] = v[i];
+        gs->H[(size_t)j * (kMaxRestart + 1) + i] = v[i];
+    }
+    if (threadIdx.x == 0) gs->wn2 = v[j + 1];
+}
+
+// reduce_c: c = V^T w after the first pass; DGKS test; completes column j.
+__global__ __launch_bounds__(kBlock) void reduce_c_kernel(int j, int nchunks, const double* __restrict__ part,
+                                                          GmresState* gs) {
+    if (gs->done) return;
+    __shared__ double v[kMaxRestart + 3];
+    __shared__ double fin[2];
+    __shared__ int redo;
+    sum_slots(part, j + 3, nchunks, v);
+    if (threadIdx.x == 0) {
+        const double after = v[j + 1], before = gs->wn2;
+        const int r = (gs->reorth == 2 || (gs->reorth == 1 && after < 0.5 * before)) ? 1 : 0;
+        double n2 = after, ps = v[j + 2];
+        if (r) {
+            for (int i = 0; i <= j; ++i) {
+                n2 -= v[i] * v[i];
+                ps -= v[i] * gs->svs[i];
+            }
+        }
+        redo = r;
+        gs->redo = r;
+        fin[0] = sqrt(fmax(n2, 0.0));
+        fin[1] = ps;
+    }
+    __syncthreads();
+    if (redo)
+        for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+            gs->ccol[i] = v[i];
+            gs->H[(size_t)j * (kMaxRestart + 1) + i] += v[i];
+        }
+    __syncthreads();
+    complete_column(j, fin[0], fin[1], gs);
+}
+
+// arnoldi_pc: v_j = (w - V c) / h(j, j-1) (j > 0; c only after a step with a second pass),
+// z = P v_j + coarse pressure term.  The four lanes of a node exchange their entries of v_j.
 template <typename T>
 __global__ void arnoldi_pc_kernel(int n_nodes, int j, T* __restrict__ V, const T* __restrict__ w,
                                   const T* __restrict__ Minv, const uint8_t* __restrict__ dmask, T* __restrict__ z,
@@ -287,110 +455,49 @@ __global__ void arnoldi_pc_kernel(int n_nodes, int j, T* __restrict__ V, const T
     if (gs->done) return;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = tid >> 2, r = tid & 3;
-    if (node >= n_nodes) return;
+    const bool active = node < n_nodes;
     const size_t N = 4 * (size_t)n_nodes;
-    using V4 = typename Vec4<T>::type;
+    const size_t idx = 4 * (size_t)node + r;
     T* vj = V + (size_t)j * N;
-    V4 v4;
-    if (j > 0) {
-        const double h = gs->H[j + (j - 1) * (kMaxRestart + 1)];
-        const double ih = 1.0 / h;
-        const V4 w4 = *reinterpret_cast<const V4*>(w + 4 * (size_t)node);
-        v4.x = T(double(w4.x) * ih);
-        v4.y = T(double(w4.y) * ih);
-        v4.z = T(double(w4.z) * ih);
-        v4.w = T(double(w4.w) * ih);
-        const T mine = r == 0 ? v4.x : r == 1 ? v4.y : r == 2 ? v4.z : v4.w;
-        vj[4 * (size_t)node + r] = mine;
-    } else {
-        v4 = *reinterpret_cast<const V4*>(vj + 4 * (size_t)node);
-    }
-    const V4 m = *reinterpret_cast<const V4*>(Minv + (size_t)node * 16 + r * 4);
-    T zz = m.x * v4.x + m.y * v4.y + m.z * v4.z + m.w * v4.w;
-    if (r == 3 && !(dmask[node] & 8u)) zz += T(gs->kappa * gs->sv);
-    z[4 * (size_t)node + r] = zz;
-}
-
-// Classical Gram-Schmidt dots: h_i = V_i . w for i <= j.  Grid (chunks, groups of 8
-// vectors); each workgroup writes 8 partial sums, the last one to arrive sums all partials in
-// a fixed order into gs->hcol.
-constexpr int kDotVecs = 8;
-constexpr int kDotItems = 4;     // elements per thread per pass
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T* __restrict__ V,
-                                                          const T* __restrict__ w, RedScratch* red,
-                                                          GmresState* gs) {
-    if (gs->done) return;
-    __shared__ double lds[(kBlock / 64) * kDotVecs];
-    const size_t N = (size_t)n;
-    const int i0 = blockIdx.y * kDotVecs;
-    const int nv = min(kDotVecs, j + 1 - i0);
-    double acc[kDotVecs];
-#pragma unroll
-    for (int q = 0; q < kDotVecs; ++q) acc[q] = 0.0;
-    const int stride = gridDim.x * blockDim.x;
-    for (int base = blockIdx.x * blockDim.x + threadIdx.x; base < n; base += stride * kDotItems) {
-        double wv[kDotItems];
-#pragma unroll
-        for (int it = 0; it < kDotItems; ++it) {
-            const int idx = base + it * stride;
-            wv[it] = idx < n ? double(w[idx]) : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < kDotVecs; ++q) {
-            if (q < nv) {
-                const T* vq = V + (size_t)(i0 + q) * N;
-#pragma unroll
-                for (int it = 0; it < kDotItems; ++it) {
-                    const int idx = base + it * stride;
-                    if (idx < n) acc[q] += double(vq[idx]) * wv[it];
-                }
+    T mine = T(0);
+    if (active) {
+        if (j > 0) {
+            double sacc = double(w[idx]);
+            if (gs->redo) {
+                const double* cc = gs->ccol;
+                for (int i = 0; i < j; ++i) sacc -= cc[i] * double(V[(size_t)i * N + idx]);
             }
+            mine = T(sacc / gs->hn);
+            vj[idx] = mine;
+        } else {
+            mine = vj[idx];
         }
     }
-    block_sum<kDotVecs>(acc, lds);
-    const int nblk = gridDim.x * gridDim.y;
-    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int q = 0; q < kDotVecs; ++q)
-            if (q < nv) red->partial[(size_t)(i0 + q) * kRedBlocks + blockIdx.x] = acc[q];
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&red->counter, 1u);
-        last = prev == (unsigned)nblk - 1;
-    }
-    __syncthreads();
-    (void)bid;
-    if (last) {
-        __threadfence();
-        reduce_partials(red->partial, kRedBlocks, j + 1, gridDim.x, gs->hcol);
-        __syncthreads();
-        if (threadIdx.x == 0) red->counter = 0u;
-    }
+    // lanes 4q .. 4q+3 of a wave hold one node; every lane takes part in the exchange
+    const int base = (threadIdx.x & 63) & ~3;
+    const T v0 = __shfl(mine, base, 64), v1 = __shfl(mine, base + 1, 64);
+    const T v2 = __shfl(mine, base + 2, 64), v3 = __shfl(mine, base + 3, 64);
+    if (!active) return;
+    using V4 = typename Vec4<T>::type;
+    const V4 m = *reinterpret_cast<const V4*>(Minv + (size_t)node * 16 + r * 4);
+    T zz = m.x * v0 + m.y * v1 + m.z * v2 + m.w * v3;
+    if (r == 3 && !(dmask[node] & 8u)) zz += T(gs->kappa * gs->sv);
+    z[idx] = zz;
 }
 
-// w -= sum_i hcol_i V_i; ||w||^2 partials; the last workgroup adds hcol into
-// column j of H and, on the final pass, sets h(j+1, j), applies the Givens
-// rotations and updates the residual estimate and the done flag.
+// w -= V h (h = gs->hcol, column j of the Hessenberg matrix from the first pass).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const T* __restrict__ V,
-                                                            T* __restrict__ w, const uint8_t* __restrict__ dmask,
-                                                            RedScratch* red, GmresState* gs, int first_pass,
-                                                            int final_pass) {
+__global__ __launch_bounds__(kBlock) void update_kernel(int n, int j, const T* __restrict__ V, T* __restrict__ w,
+                                                        const GmresState* gs) {
     if (gs->done) return;
     __shared__ double hs[kMaxRestart + 1];
-    __shared__ double lds[(kBlock / 64) * 2];
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) hs[i] = gs->hcol[i];
+    const double* coef = gs->hcol;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) hs[i] = coef[i];
     __syncthreads();
     const size_t N = (size_t)n;
-    double v[2] = {0.0, 0.0};
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
         double s = double(w[idx]);
         int i = 0;
-        // groups of 8 independent loads keep several memory requests in flight per lane
         for (; i + 8 <= j + 1; i += 8) {
             double vv[8];
 #pragma unroll
@@ -399,63 +506,7 @@ __global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const 
             for (int q = 0; q < 8; ++q) s -= hs[i + q] * vv[q];
         }
         for (; i <= j; ++i) s -= hs[i] * double(V[(size_t)i * N + idx]);
-        const T sv = T(s);
-        w[idx] = sv;
-        v[0] += double(sv) * double(sv);
-        if (free_pressure(dmask, idx)) v[1] += double(sv);
-    }
-    block_sum<2>(v, lds);
-    if (threadIdx.x == 0) {
-        red->partial[blockIdx.x] = v[0];
-        red->partial[kRedBlocks + blockIdx.x] = v[1];
-    }
-    if (!arrive_last(&red->counter)) return;
-    __threadfence();
-    constexpr int ld = kMaxRestart + 1;
-    __shared__ double col[kMaxRestart + 2], csl[kMaxRestart], snl[kMaxRestart];
-    __shared__ double tot[2];
-    double* Hj = gs->H + (size_t)j * ld;
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-        const double h = first_pass ? hs[i] : Hj[i] + hs[i];
-        Hj[i] = h;
-        col[i] = h;
-    }
-    if (final_pass) {
-        for (int i = threadIdx.x; i < j; i += blockDim.x) {
-            csl[i] = gs->cs[i];
-            snl[i] = gs->sn[i];
-        }
-        reduce_partials(red->partial, kRedBlocks, 2, gridDim.x, tot);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (final_pass) {
-            const double hn = sqrt(tot[0]);
-            Hj[j + 1] = hn;
-            gs->sv = hn > 0.0 ? tot[1] / hn : 0.0;   // free-pressure sum of the next basis vector
-            // previous rotations on the new column: the running entry is carried in a register
-            double* Rj = gs->R + (size_t)j * ld;
-            double x = col[0];
-            for (int i = 0; i < j; ++i) {
-                const double y = col[i + 1];
-                Rj[i] = csl[i] * x + snl[i] * y;
-                x = -snl[i] * x + csl[i] * y;
-            }
-            const double d = hypot(x, hn);
-            const double cs = d > 0.0 ? x / d : 1.0;
-            const double sn = d > 0.0 ? hn / d : 0.0;
-            gs->cs[j] = cs;
-            gs->sn[j] = sn;
-            Rj[j] = d;
-            const double gj = gs->g[j];
-            gs->g[j + 1] = -sn * gj;
-            gs->g[j] = cs * gj;
-            gs->k = j + 1;
-            const bool conv = fabs(gs->g[j + 1]) <= gs->tol_abs;
-            const bool breakdown = !(hn > 1e-300 * (fabs(d) + 1e-300)) || !isfinite(hn);
-            if (conv || breakdown || !isfinite(gs->g[j + 1])) gs->done = 1;
-        }
-        red->counter = 0u;
+        w[idx] = T(s);
     }
 }
 
@@ -569,15 +620,18 @@ int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double 
     T* V = (T*)c->V;
     T* w = (T*)c->w;
     T* z = (T*)c->z;
-    cycle_start_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, r0, c->dmask, c->red, c->gs, tol_abs);
+    cycle_start_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, r0, c->dmask, c->red, c->gs, tol_abs, cgs2);
     cycle_v0_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, r0, V, c->gs);
     const int steps = std::min(m, budget);
-    const int check_every = 5;
+    const int check_every = 8;
     const double vb = (double)n * sizeof(T);      // bytes of one Krylov vector
     const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 2.0 * vb;
-    for (int j = 0; j < steps; ++j) {
+    const int nch = std::max(1, std::min(kDotChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
+    double* part = c->red->partial;
+    int j = 0;
+    for (; j < steps; ++j) {
         {
-            PhaseScope ph(c, VMS_PH_PCAPPLY, 3.0 * vb + 4.0 * vb, s);
+            PhaseScope ph(c, VMS_PH_PCAPPLY, 7.0 * vb, s);
             arnoldi_pc_kernel<T><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, j, V, w, Minv, c->dmask, z, c->gs);
         }
         {
@@ -585,31 +639,36 @@ int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double 
             spmv_kernel<T, T, T, T, 0><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, c->rowptr, c->colidx, A, z,
                                                                       (const double*)nullptr, w, &c->gs->done);
         }
-        const int passes = cgs2 ? 2 : 1;
-        for (int p = 0; p < passes; ++p) {
-            {
-                PhaseScope ph(c, VMS_PH_DOTS, (j + 2) * vb, s);
-                const int groups = (j + kDotVecs) / kDotVecs;
-                const int gx = std::max(1, std::min(kRedBlocks, std::min(grid_for(n, kBlock * kDotItems),
-                                                                         std::max(1, 2048 / groups))));
-                cgs_dots_kernel<T><<<dim3(gx, groups), kBlock, 0, s>>>(n, j, V, w, c->red, c->gs);
-            }
-            {
-                PhaseScope ph(c, VMS_PH_UPDATE, (j + 3) * vb, s);
-                cgs_update_kernel<T><<<std::min(kRedBlocks, grid_for(n)), kBlock, 0, s>>>(n, j, V, w, c->dmask, c->red,
-                                                                                           c->gs, p == 0,
-                                                                    p == passes - 1);
-            }
+        {
+            PhaseScope ph(c, VMS_PH_DOTS, (j + 2) * vb, s);
+            dots2d_kernel<T><<<dim3(nch, j + 2), kDotThreads, 0, s>>>(c->n_nodes, j, V, w, c->dmask, part, c->gs);
         }
-        if ((j + 1) % check_every == 0 || j + 1 == steps) {
+        reduce_h_kernel<<<1, kBlock, 0, s>>>(j, nch, part, c->gs);
+        {
+            PhaseScope ph(c, VMS_PH_UPDATE, (j + 3) * vb, s);
+            update_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, j, V, w, c->gs);
+        }
+        dots2d_kernel<T><<<dim3(nch, j + 3), kDotThreads, 0, s>>>(c->n_nodes, j, V, w, c->dmask, part, c->gs);
+        reduce_c_kernel<<<1, kBlock, 0, s>>>(j, nch, part, c->gs);
+        if ((j + 1) % check_every == 0 && j + 1 < steps) {
             int h[2];
             if (check_hip(c, hipMemcpyAsync(h, &c->gs->k, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read k"))
                 return -1;
             if (check_hip(c, hipStreamSynchronize(s), "sync")) return -1;
-            st->k = h[0];
-            st->done = h[1];
-            if (h[1]) break;
+            if (h[1]) {
+                ++j;
+                break;
+            }
         }
+    }
+    // every column completes in its own step (reduce_c)
+    {
+        int h[2];
+        if (check_hip(c, hipMemcpyAsync(h, &c->gs->k, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read k"))
+            return -1;
+        if (check_hip(c, hipStreamSynchronize(s), "sync")) return -1;
+        st->k = h[0];
+        st->done = h[1];
     }
     if (st->k > 0) {
         // back substitution R y = g on the host (R is at most kMaxRestart square)

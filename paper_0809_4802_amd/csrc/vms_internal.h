@@ -53,7 +53,8 @@ struct GmresState {
     double R[(kMaxRestart + 1) * kMaxRestart];   // its Givens-rotated triangle, same layout
     double cs[kMaxRestart];
     double sn[kMaxRestart];
-    double g[kMaxRestart + 1];
+    double g[kMaxRestart + 1];     // rotated right-hand side (final entries)
+    double gin[kMaxRestart + 1];   // entry i before rotation i (gin[k] = residual estimate)
     double y[kMaxRestart];
     double hcol[kMaxRestart + 1];  // CGS coefficients of the current step
     double tol_abs;                // stop when |g[k]| <= tol_abs
@@ -62,6 +63,13 @@ struct GmresState {
     double kappa;                  // coarse pressure correction: 1 / (sum of free p-p entries), 0 = off
     double sv;                     // sum of the free pressure entries of the current v_j
     double st;                     // sum of the free pressure entries of the correction V y
+    double wn2;                    // ||w||^2 of the current step before orthogonalisation
+    double hn;                     // h(j+1, j) of the last completed column
+    double ccol[kMaxRestart + 1];  // reorthogonalisation coefficients of the current step
+    double svs[kMaxRestart + 1];   // free-pressure sum of every basis vector
+    int redo;                      // 1: the current step is being reorthogonalised
+    int nbc;                       // partial sums of the step's final norm (1 when not reorthogonalised)
+    int reorth;                    // reorthogonalisation mode: 0 never, 1 when cancellation (DGKS), 2 always
     int k;                         // Arnoldi steps completed in this cycle
     int done;                      // 1: converged or breakdown, later kernels idle
     unsigned counter;              // arrival counter of last-block reductions
