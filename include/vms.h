@@ -235,8 +235,8 @@ int vms_pc_train_step(vms_ctx* ctx, const void* bsr_vals, const float* r_batch, 
  * While enabled, every launch of a hot kernel is bracketed by two hipEvents
  * on its stream, and the algorithmic bytes the launch must move (inputs read
  * once, outputs written once; no credit for scratch, atomics or re-reads)
- * are added to its phase.  vms_profile clears the accumulators; enabling adds
- * a small host cost per launch. */
+ * are added to its phase.  Each timed launch costs two event records on the
+ * stream, which lengthens the step around it. */
 enum {
     VMS_PH_CONDENSE = 0,       /* element residual + tangent + condensation + scatter kernel */
     VMS_PH_RESIDUAL = 1,       /* residual-only element kernel                            */
@@ -249,7 +249,12 @@ enum {
     VMS_PH_FILL = 8,           /* zero fill of the assembled outputs                      */
     VMS_NPHASES = 9
 };
-int vms_profile(vms_ctx* ctx, int enable);
+/* phase_mask: bit p enables phase p (VMS_PROFILE_ALL: every phase), 0 disables.
+ * every >= 1: only every every-th launch of an enabled phase is timed (a sample;
+ * the accumulators then cover the sampled launches only).  Each call clears the
+ * accumulators.  Timing one phase, sparsely, keeps the event cost off the rest. */
+#define VMS_PROFILE_ALL ((1u << VMS_NPHASES) - 1u)
+int vms_profile(vms_ctx* ctx, uint32_t phase_mask, int32_t every);
 /* Synchronising.  Each array has VMS_NPHASES entries; any may be NULL. */
 int vms_profile_read(vms_ctx* ctx, double* ms, int64_t* launches, double* alg_bytes);
 

@@ -99,7 +99,7 @@ _sig = {
     "vms_pc_features": [_vp, _vp, _vp, _vp],
     "vms_pc_blocks": [_vp, _vp, _vp, _vp, _vp],
     "vms_pc_train_step": [_vp, _vp, _vp, _i32, _vp, _vp, _i32, ctypes.c_float, _vp, _vp, _vp],
-    "vms_profile": [_vp, ctypes.c_int],
+    "vms_profile": [_vp, ctypes.c_uint32, ctypes.c_int32],
     "vms_profile_read": [_vp, _vp, _vp, _vp],
 }
 for _name, _args in _sig.items():
@@ -299,8 +299,18 @@ def vms_pc_train_step(ctx: Context, bsr_vals, r_batch, weights, adam_state, step
                                   _stream(stream)), ctx.handle)
 
 
-def vms_profile(ctx: Context, enable=True):
-    _check(_lib.vms_profile(ctx.handle, 1 if enable else 0), ctx.handle)
+def vms_profile(ctx: Context, enable=True, phases=None, every=1):
+    """Times the launches of the named phases (all phases when None), every `every`-th
+    launch of each; enable=False stops."""
+    if not enable:
+        mask = 0
+    elif phases is None:
+        mask = (1 << len(PHASES)) - 1
+    else:
+        mask = 0
+        for p in ([phases] if isinstance(phases, str) else phases):
+            mask |= 1 << PHASES.index(p)
+    _check(_lib.vms_profile(ctx.handle, mask, int(every)), ctx.handle)
 
 
 def vms_profile_read(ctx: Context):

@@ -52,15 +52,18 @@ static int prof_flush(vms_ctx* c) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return VMS_EHIP;
         const int ph = c->prof_phase[i];
+        if (ph < 0) continue;           // voided: the launch did no work
         c->prof_ms[ph] += ms;
         c->prof_acc_bytes[ph] += c->prof_bytes[i];
         c->prof_count[ph] += 1;
     }
     c->prof_used = 0;
+    ++c->prof_gen;
     return VMS_OK;
 }
 
 int prof_begin(vms_ctx* c, int phase, double bytes, hipStream_t s) {
+    if (c->prof_seen[phase]++ % c->prof_every != 0) return -1;
     if (c->prof_used == kProfPool && prof_flush(c) != VMS_OK) return -1;
     const int slot = c->prof_used++;
     c->prof_phase[slot] = phase;
@@ -71,11 +74,17 @@ int prof_begin(vms_ctx* c, int phase, double bytes, hipStream_t s) {
 
 void prof_end(vms_ctx* c, int slot, hipStream_t s) { (void)hipEventRecord(c->prof_ev[2 * slot + 1], s); }
 
+void prof_void(vms_ctx* c, int slot, int64_t gen) {
+    if (slot >= 0 && gen == c->prof_gen && slot < c->prof_used) c->prof_phase[slot] = -1;
+}
+
 }  // namespace vms
 
-extern "C" int vms_profile(vms_ctx* c, int enable) {
+extern "C" int vms_profile(vms_ctx* c, uint32_t phase_mask, int32_t every) {
     if (!c) return set_error(nullptr, VMS_EINVAL, "vms_profile: NULL ctx");
-    if (c->prof_ev.empty() && enable) {
+    if (phase_mask & ~VMS_PROFILE_ALL) return set_error(c, VMS_EINVAL, "vms_profile: unknown phase bit");
+    if (every < 1) return set_error(c, VMS_EINVAL, "vms_profile: every must be >= 1");
+    if (c->prof_ev.empty() && phase_mask) {
         c->prof_ev.resize(2 * kProfPool);
         for (auto& e : c->prof_ev)
             if (hipEventCreate(&e) != hipSuccess) return set_error(c, VMS_EHIP, "vms_profile: hipEventCreate");
@@ -88,7 +97,9 @@ extern "C" int vms_profile(vms_ctx* c, int enable) {
         c->prof_acc_bytes[i] = 0.0;
         c->prof_count[i] = 0;
     }
-    c->prof_on = enable != 0;
+    c->prof_mask = phase_mask;
+    c->prof_every = every;
+    for (int i = 0; i < VMS_NPHASES; ++i) c->prof_seen[i] = 0;
     return VMS_OK;
 }
 
@@ -112,6 +123,7 @@ static void free_all(vms_ctx* c) {
         if (p) (void)hipFree(p);
     for (auto e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->progress_host) (void)hipHostFree(c->progress_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
 }
@@ -353,6 +365,11 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->tvec, 3 * N * sizeof(float), "alloc tvec"));
     TRY(dev_alloc(c, &c->wgrad, (size_t)kRedBlocks * VMS_PC_NWEIGHTS * sizeof(float), "alloc wgrad"));
     TRY(dev_alloc(c, &c->fscal, 8 * sizeof(float), "alloc fscal"));
+    TRY(check_hip(c, hipHostMalloc(reinterpret_cast<void**>(&c->progress_host), 64,
+                                   hipHostMallocMapped | hipHostMallocCoherent), "alloc progress word"));
+    TRY(check_hip(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->progress_dev), c->progress_host, 0),
+                  "map progress word"));
+    *c->progress_host = 0;
     TRY(check_hip(c, hipEventCreate(&c->ev0), "event"));
     TRY(check_hip(c, hipEventCreate(&c->ev1), "event"));
 
@@ -375,6 +392,8 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(check_hip(c, tile_kernels_configure(c), "configure tile kernels"));
     TRY(check_hip(c, hipMemset(c->red, 0, sizeof(RedScratch)), "clear"));
     TRY(check_hip(c, hipMemset(c->gs, 0, sizeof(GmresState)), "clear"));
+    TRY(check_hip(c, hipMemcpy(&c->gs->progress, &c->progress_dev, sizeof(uint64_t*), hipMemcpyHostToDevice),
+                  "upload"));
     TRY(check_hip(c, hipMemset(c->flags, 0, 8 * sizeof(int32_t)), "clear"));
     TRY(check_hip(c, hipDeviceSynchronize(), "sync"));
     *out = c;

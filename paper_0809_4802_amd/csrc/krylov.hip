@@ -52,9 +52,14 @@ __global__ void fill_kernel(uint4* p, size_t n16) {
 }
 
 // ---------------------------------------------------------------------------------- SpMV
-// Four lanes per block row; lane r owns output dof r of its node and walks the
-// row's blocks, reading row r of each block (4 contiguous values) and the
-// 4-vector of the column node.  MODE 0: y = A x.  MODE 1: y = b - A x.
+// Eight lanes per block row.  Lane (q, r), q = 0, 1 and r = 0..3, owns output dof r and the
+// row's blocks q, q + 2, q + 4, ...: it reads row r of each (4 contiguous values) and the
+// 4-vector of the column node.  The first kSpmvUnroll blocks of a lane are all loaded before
+// any is used, so that its loads are in flight together (a row of this mesh has at most 15
+// blocks, i.e. 8 per lane); the two halves of a row are summed with one lane exchange.
+// MODE 0: y = A x.  MODE 1: y = b - A x.
+constexpr int kSpmvLanes = 8;
+constexpr int kSpmvUnroll = 8;
 template <typename TA, typename TX, typename TY, typename TACC, int MODE, typename TB = double>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colidx,
@@ -62,26 +67,54 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
                                                       const TB* __restrict__ b, TY* __restrict__ y,
                                                       const int* __restrict__ done) {
     if (done && *done) return;
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int row = tid >> 2;
-    const int r = tid & 3;
-    if (row >= n_rows) return;
+    constexpr int Q = kSpmvLanes / 4;
     using VA = typename Vec4<TA>::type;
     using VX = typename Vec4<TX>::type;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = tid / kSpmvLanes, sub = tid % kSpmvLanes;
+    const int q = sub >> 2, r = sub & 3;
     TACC acc = TACC(0);
-    const int k0 = rowptr[row], k1 = rowptr[row + 1];
-    for (int k = k0; k < k1; ++k) {
-        const int col = colidx[k];
-        const VA a = *reinterpret_cast<const VA*>(A + (size_t)k * 16 + r * 4);
-        const VX xv = *reinterpret_cast<const VX*>(x + (size_t)col * 4);
-        acc += TACC(a.x) * TACC(xv.x) + TACC(a.y) * TACC(xv.y) + TACC(a.z) * TACC(xv.z) +
-               TACC(a.w) * TACC(xv.w);
+    if (row < n_rows) {
+        const int k0 = rowptr[row], k1 = rowptr[row + 1];
+        int cols[kSpmvUnroll];
+#pragma unroll
+        for (int u = 0; u < kSpmvUnroll; ++u) {
+            const int k = k0 + q + u * Q;
+            cols[u] = k < k1 ? colidx[k] : -1;
+        }
+        VA av[kSpmvUnroll];
+        VX xv[kSpmvUnroll];
+#pragma unroll
+        for (int u = 0; u < kSpmvUnroll; ++u) {
+            if (cols[u] >= 0) {
+                av[u] = *reinterpret_cast<const VA*>(A + (size_t)(k0 + q + u * Q) * 16 + r * 4);
+                xv[u] = *reinterpret_cast<const VX*>(x + (size_t)cols[u] * 4);
+            } else {
+                av[u] = VA{TA(0), TA(0), TA(0), TA(0)};
+                xv[u] = VX{TX(0), TX(0), TX(0), TX(0)};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSpmvUnroll; ++u)
+            acc += TACC(av[u].x) * TACC(xv[u].x) + TACC(av[u].y) * TACC(xv[u].y) + TACC(av[u].z) * TACC(xv[u].z) +
+                   TACC(av[u].w) * TACC(xv[u].w);
+        // rows longer than kSpmvUnroll blocks per lane (other meshes)
+        for (int k = k0 + q + kSpmvUnroll * Q; k < k1; k += Q) {
+            const VA a = *reinterpret_cast<const VA*>(A + (size_t)k * 16 + r * 4);
+            const VX xx = *reinterpret_cast<const VX*>(x + (size_t)colidx[k] * 4);
+            acc += TACC(a.x) * TACC(xx.x) + TACC(a.y) * TACC(xx.y) + TACC(a.z) * TACC(xx.z) + TACC(a.w) * TACC(xx.w);
+        }
     }
-    if (MODE == 1)
-        y[4 * (size_t)row + r] = TY(TACC(b[4 * (size_t)row + r]) - acc);
-    else
-        y[4 * (size_t)row + r] = TY(acc);
+    acc += __shfl_xor(acc, 4, 64);       // lanes 4q + r of a row: q = 0 and q = 1
+    if (row < n_rows && q == 0) {
+        if (MODE == 1)
+            y[4 * (size_t)row + r] = TY(TACC(b[4 * (size_t)row + r]) - acc);
+        else
+            y[4 * (size_t)row + r] = TY(acc);
+    }
 }
+
+inline int spmv_grid(int n_rows) { return (int)(((int64_t)kSpmvLanes * n_rows + kBlock - 1) / kBlock); }
 
 // --------------------------------------------------------------------------- block-Jacobi
 // Inverse of each 4x4 diagonal block in FP64 (Gauss-Jordan, partial pivoting),
@@ -233,11 +266,18 @@ __global__ __launch_bounds__(kBlock) void coarse_setup_kernel(int n_nodes, const
     }
 }
 
+// Publishes the cycle's progress (completed columns k, done flag) to the host-mapped word.
+__device__ __forceinline__ void report_progress(GmresState* gs, int k, int done) {
+    const uint64_t word = ((uint64_t)gs->gen << 32) | ((uint64_t)k << 1) | (uint64_t)(done ? 1 : 0);
+    __hip_atomic_store(gs->progress, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // norm of a vector -> gs->beta, initialises the cycle (g = beta e_1, k = 0, done flag).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __restrict__ r,
                                                              const uint8_t* __restrict__ dmask, RedScratch* red,
-                                                             GmresState* gs, double tol_abs, int reorth) {
+                                                             GmresState* gs, double tol_abs, int reorth,
+                                                             unsigned gen) {
     __shared__ double lds[(kBlock / 64) * 2];
     double v[2] = {0.0, 0.0};
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -270,7 +310,9 @@ __global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __r
         gs->norm = nrm;
         gs->reorth = reorth;
         gs->redo = 0;
+        gs->gen = gen;
         red->counter = 0u;
+        report_progress(gs, 0, gs->done);
     }
 }
 
@@ -398,6 +440,7 @@ __device__ void complete_column(int jc, double hn, double psum, GmresState* gs) 
     gs->svs[jc + 1] = gs->sv;
     gs->k = jc + 1;
     if (conv || breakdown) gs->done = 1;
+    report_progress(gs, jc + 1, conv || breakdown);
 }
 
 // reduce_h: h = V^T w, H(:, j) = h, ||w||^2 before orthogonalisation.
@@ -510,16 +553,57 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int n, int j, const T* _
     }
 }
 
+// y = R^{-1} g for the k x k triangle of the rotated Hessenberg matrix (one workgroup): the
+// triangle is staged in LDS, then one wave eliminates column by column, lane l holding entries
+// l and l + 64 of the right-hand side.
+__global__ __launch_bounds__(kBlock) void backsub_kernel(GmresState* gs) {
+    const int k = gs->k;
+    if (k == 0) return;
+    constexpr int ld = kMaxRestart + 1;
+    __shared__ double Rl[kMaxRestart * kMaxRestart];
+    __shared__ double gl[kMaxRestart];
+    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+        const int col = idx / k, row = idx - col * k;
+        if (row <= col) Rl[idx] = gs->R[(size_t)col * ld + row];
+    }
+    for (int i = threadIdx.x; i < k; i += blockDim.x) gl[i] = gs->g[i];
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int l = threadIdx.x;
+    double g0 = l < k ? gl[l] : 0.0;
+    double g1 = l + 64 < k ? gl[l + 64] : 0.0;
+    for (int col = k - 1; col >= 0; --col) {
+        const double gc = __shfl(col < 64 ? g0 : g1, col & 63, 64);
+        const double yc = gc / Rl[col * k + col];
+        if (l == 0) gs->y[col] = yc;
+        if (l < col) g0 -= Rl[col * k + l] * yc;
+        if (l + 64 < col) g1 -= Rl[col * k + l + 64] * yc;
+    }
+}
+
 // t = sum_{i<k} y_i V_i
 template <typename T>
-__global__ void combine_kernel(int n, const T* __restrict__ V, const GmresState* gs, T* __restrict__ t) {
+__global__ __launch_bounds__(kBlock) void combine_kernel(int n, const T* __restrict__ V, const GmresState* gs,
+                                                         T* __restrict__ t) {
+    const int k = gs->k;
+    if (k == 0) return;
+    __shared__ double ys[kMaxRestart];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = gs->y[i];
+    __syncthreads();
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n) return;
-    const int k = gs->k;
     const size_t N = (size_t)n;
-    double s = 0.0;
-    for (int i = 0; i < k; ++i) s += gs->y[i] * double(V[(size_t)i * N + idx]);
-    t[idx] = T(s);
+    double sacc = 0.0;
+    int i = 0;
+    for (; i + 8 <= k; i += 8) {
+        double vv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) vv[q] = double(V[(size_t)(i + q) * N + idx]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sacc += ys[i + q] * vv[q];
+    }
+    for (; i < k; ++i) sacc += ys[i] * double(V[(size_t)i * N + idx]);
+    t[idx] = T(sacc);
 }
 
 // gs->st = sum of the free pressure entries of t (for the coarse term of P t)
@@ -527,6 +611,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void free_pressure_sum_kernel(int n_nodes, const T* __restrict__ t,
                                                                    const uint8_t* __restrict__ dmask,
                                                                    RedScratch* red, GmresState* gs) {
+    if (gs->k == 0) return;
     __shared__ double lds[kBlock / 64];
     double v[1] = {0.0};
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes; i += gridDim.x * blockDim.x)
@@ -549,6 +634,7 @@ template <typename T, typename TX>
 __global__ void precond_accumulate_kernel(int n_nodes, const T* __restrict__ Minv, const T* __restrict__ t,
                                           const uint8_t* __restrict__ dmask, const GmresState* gs,
                                           TX* __restrict__ x) {
+    if (gs->k == 0) return;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = tid >> 2, r = tid & 3;
     if (node >= n_nodes) return;
@@ -605,94 +691,122 @@ int read_scalar(vms_ctx* c, const double* dptr, double* h, hipStream_t s) {
     return check_hip(c, hipStreamSynchronize(s), "sync");
 }
 
-struct CycleStatus {
-    int k;
-    int done;
-};
+constexpr int kLeadSteps = 3;   // Arnoldi steps the host may issue ahead of the device
 
-// One GMRES(m) cycle on A d = r0 with right preconditioner Minv; the Krylov
-// correction Minv (V y) is added to x (double or float).  r0 is the cycle's
-// initial residual (precision T).  Returns the number of Arnoldi steps.
+// The device's progress word for cycle gen: completed columns (-1 before the cycle has
+// reported), *done = 1 once the cycle stopped (converged or broke down).
+int read_progress(const vms_ctx* c, uint32_t gen, int* done) {
+    const uint64_t word = __atomic_load_n(c->progress_host, __ATOMIC_ACQUIRE);
+    if ((uint32_t)(word >> 32) != gen) {
+        *done = 0;
+        return -1;
+    }
+    *done = (int)(word & 1u);
+    return (int)((word >> 1) & 0x7fffffffu);
+}
+
+// Waits, without synchronising the stream, until cycle gen has completed `need` columns or
+// stopped.  Returns 1 if it stopped, 0 if the columns are there (or the stream ran dry), a
+// negative status on a HIP error.
+int wait_progress(vms_ctx* c, uint32_t gen, int need, hipStream_t s) {
+    for (unsigned spin = 0;; ++spin) {
+        int done = 0;
+        const int k = read_progress(c, gen, &done);
+        if (done) return 1;
+        if (k >= need) return 0;
+        if ((spin & 255u) == 255u) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {           // every launch has finished: the word is final
+                read_progress(c, gen, &done);
+                return done;
+            }
+            if (q != hipErrorNotReady) {
+                (void)check_hip(c, q, "gmres: stream query");
+                return -1;
+            }
+        }
+    }
+}
+
+// Launches one GMRES(m) cycle on A d = r0 with right preconditioner Minv, adding the Krylov
+// correction Minv (V y) (+ coarse term) to x (double or float).  r0 is the cycle's initial
+// residual (precision T).  The host follows the device's progress through the mapped word,
+// keeps at most kLeadSteps steps queued ahead of it and stops issuing steps once the cycle has
+// converged; nothing here synchronises the stream.  finish_cycle gives the number of steps
+// once the caller has synchronised.
 template <typename T, typename TX>
 int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double tol_abs, int m, int budget,
-              int cgs2, CycleStatus* st, hipStream_t s) {
+              int cgs2, hipStream_t s) {
     const int n = 4 * c->n_nodes;
     T* V = (T*)c->V;
     T* w = (T*)c->w;
     T* z = (T*)c->z;
-    cycle_start_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, r0, c->dmask, c->red, c->gs, tol_abs, cgs2);
+    const uint32_t gen = ++c->cycle_gen;
+    c->cycle_timed.clear();
+    cycle_start_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, r0, c->dmask, c->red, c->gs, tol_abs, cgs2, gen);
     cycle_v0_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, r0, V, c->gs);
     const int steps = std::min(m, budget);
-    const int check_every = 8;
     const double vb = (double)n * sizeof(T);      // bytes of one Krylov vector
     const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 2.0 * vb;
     const int nch = std::max(1, std::min(kDotChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
     double* part = c->red->partial;
-    int j = 0;
-    for (; j < steps; ++j) {
+    // timed launches per step, so that steps issued after convergence (their kernels return
+    // at once) can be dropped from the phase timers
+    auto keep = [&](int jj, const PhaseScope& ph) {
+        if (ph.slot >= 0) {
+            c->cycle_timed.push_back(jj);
+            c->cycle_timed.push_back(ph.slot);
+            c->cycle_timed.push_back(ph.gen);
+        }
+    };
+    for (int j = 0; j < steps; ++j) {
+        if (j >= kLeadSteps) {
+            const int st = wait_progress(c, gen, j - kLeadSteps, s);
+            if (st < 0) return VMS_EHIP;
+            if (st == 1) break;
+        }
         {
             PhaseScope ph(c, VMS_PH_PCAPPLY, 7.0 * vb, s);
             arnoldi_pc_kernel<T><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, j, V, w, Minv, c->dmask, z, c->gs);
+            keep(j, ph);
         }
         {
             PhaseScope ph(c, VMS_PH_SPMV, spmv_bytes, s);
-            spmv_kernel<T, T, T, T, 0><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, c->rowptr, c->colidx, A, z,
-                                                                      (const double*)nullptr, w, &c->gs->done);
+            spmv_kernel<T, T, T, T, 0><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
+                c->n_nodes, c->rowptr, c->colidx, A, z, (const double*)nullptr, w, &c->gs->done);
+            keep(j, ph);
         }
         {
             PhaseScope ph(c, VMS_PH_DOTS, (j + 2) * vb, s);
             dots2d_kernel<T><<<dim3(nch, j + 2), kDotThreads, 0, s>>>(c->n_nodes, j, V, w, c->dmask, part, c->gs);
+            keep(j, ph);
         }
         reduce_h_kernel<<<1, kBlock, 0, s>>>(j, nch, part, c->gs);
         {
             PhaseScope ph(c, VMS_PH_UPDATE, (j + 3) * vb, s);
             update_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, j, V, w, c->gs);
+            keep(j, ph);
         }
         dots2d_kernel<T><<<dim3(nch, j + 3), kDotThreads, 0, s>>>(c->n_nodes, j, V, w, c->dmask, part, c->gs);
         reduce_c_kernel<<<1, kBlock, 0, s>>>(j, nch, part, c->gs);
-        if ((j + 1) % check_every == 0 && j + 1 < steps) {
-            int h[2];
-            if (check_hip(c, hipMemcpyAsync(h, &c->gs->k, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read k"))
-                return -1;
-            if (check_hip(c, hipStreamSynchronize(s), "sync")) return -1;
-            if (h[1]) {
-                ++j;
-                break;
-            }
-        }
     }
-    // every column completes in its own step (reduce_c)
-    {
-        int h[2];
-        if (check_hip(c, hipMemcpyAsync(h, &c->gs->k, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "read k"))
-            return -1;
-        if (check_hip(c, hipStreamSynchronize(s), "sync")) return -1;
-        st->k = h[0];
-        st->done = h[1];
-    }
-    if (st->k > 0) {
-        // back substitution R y = g on the host (R is at most kMaxRestart square)
-        const int k = st->k;
-        constexpr int ld = kMaxRestart + 1;
-        std::vector<double> R((size_t)k * ld), g(k), y(k);
-        if (check_hip(c, hipMemcpyAsync(R.data(), c->gs->R, R.size() * sizeof(double), hipMemcpyDeviceToHost, s),
-                      "read R") ||
-            check_hip(c, hipMemcpyAsync(g.data(), c->gs->g, k * sizeof(double), hipMemcpyDeviceToHost, s), "read g") ||
-            check_hip(c, hipStreamSynchronize(s), "sync"))
-            return -1;
-        for (int i = k - 1; i >= 0; --i) {
-            double acc = g[i];
-            for (int cc = i + 1; cc < k; ++cc) acc -= R[(size_t)cc * ld + i] * y[cc];
-            y[i] = acc / R[(size_t)i * ld + i];
-        }
-        if (check_hip(c, hipMemcpyAsync(c->gs->y, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s), "write y") ||
-            check_hip(c, hipStreamSynchronize(s), "sync"))
-            return -1;
-        combine_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, V, c->gs, z);
-        free_pressure_sum_kernel<T><<<red_grid(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, z, c->dmask, c->red, c->gs);
-        precond_accumulate_kernel<T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, c->dmask, c->gs, x);
-    }
-    return st->k;
+    // every column completes in its own step (reduce_c); y = R^{-1} g on the device
+    backsub_kernel<<<1, kBlock, 0, s>>>(c->gs);
+    combine_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, V, c->gs, z);
+    free_pressure_sum_kernel<T><<<red_grid(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, z, c->dmask, c->red, c->gs);
+    precond_accumulate_kernel<T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, c->dmask, c->gs, x);
+    return check_hip(c, hipGetLastError(), "gmres cycle launch");
+}
+
+// After the caller has synchronised the stream: Arnoldi steps of the last cycle.  Timed
+// launches of steps issued after convergence are dropped.
+int finish_cycle(vms_ctx* c) {
+    int done = 0;
+    const int k = std::max(0, read_progress(c, c->cycle_gen, &done));
+    for (size_t i = 0; i + 2 < c->cycle_timed.size(); i += 3)
+        if (c->cycle_timed[i] >= k) prof_void(c, (int)c->cycle_timed[i + 1], c->cycle_timed[i + 2]);
+    c->cycle_timed.clear();
+    return k;
 }
 
 }  // namespace
@@ -712,10 +826,10 @@ int launch_fill(void* p, size_t bytes, hipStream_t s) {
 int launch_spmv(vms_ctx* c, const void* A, const void* x, void* y, hipStream_t s) {
     const int n = 4 * c->n_nodes;
     if (c->prec == VMS_FP64)
-        spmv_kernel<double, double, double, double, 0><<<grid_for(n), kBlock, 0, s>>>(
+        spmv_kernel<double, double, double, double, 0><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
             c->n_nodes, c->rowptr, c->colidx, (const double*)A, (const double*)x, (const double*)nullptr, (double*)y, nullptr);
     else
-        spmv_kernel<float, float, float, float, 0><<<grid_for(n), kBlock, 0, s>>>(
+        spmv_kernel<float, float, float, float, 0><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
             c->n_nodes, c->rowptr, c->colidx, (const float*)A, (const float*)x, (const double*)nullptr, (float*)y, nullptr);
     return check_hip(c, hipGetLastError(), "spmv launch");
 }
@@ -737,10 +851,10 @@ int launch_bj_setup(vms_ctx* c, const void* A, void* Minv, hipStream_t s) {
 static int true_residual(vms_ctx* c, const void* A, const double* b, const double* x, double* rn, hipStream_t s) {
     const int n = 4 * c->n_nodes;
     if (c->prec == VMS_FP64)
-        spmv_kernel<double, double, double, double, 1><<<grid_for(n), kBlock, 0, s>>>(
+        spmv_kernel<double, double, double, double, 1><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
             c->n_nodes, c->rowptr, c->colidx, (const double*)A, x, b, c->r64, nullptr);
     else
-        spmv_kernel<float, double, double, double, 1><<<grid_for(n), kBlock, 0, s>>>(
+        spmv_kernel<float, double, double, double, 1><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
             c->n_nodes, c->rowptr, c->colidx, (const float*)A, x, b, c->r64, nullptr);
     norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, c->r64, c->red, c->rnorm + 2);
     return read_scalar(c, c->rnorm + 2, rn, s);
@@ -792,15 +906,16 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     const bool learned = o->pc == VMS_PC_LEARNED && o->pc_weights && !inf.fell_back_to_bj;
     const int learned_budget = learned ? max_iters / 2 : max_iters;
     bool using_learned = learned;
+    bool pending = false;          // an FP64 cycle was launched and not yet counted
     for (;;) {
-        if (using_learned && iters >= learned_budget) {
-            // the learned blocks did not deliver within half the budget: continue from the
-            // current iterate with plain block-Jacobi
-            if ((rc = launch_bj_setup(c, A, c->Minv, s))) return rc;
-            using_learned = false;
-            inf.fell_back_to_bj = 1;
+        if ((rc = true_residual(c, A, b, x, &rn, s))) return rc;      // synchronises
+        int last_k = -1;
+        if (pending) {
+            last_k = finish_cycle(c);
+            iters += last_k;
+            inf.restarts++;
+            pending = false;
         }
-        if ((rc = true_residual(c, A, b, x, &rn, s))) return rc;
         if (o->log_residuals && inf.logged < o->log_max) {
             convert_kernel<double, float><<<grid_for(n), kBlock, 0, s>>>(
                 n, c->r64, o->log_residuals + (size_t)inf.logged * n, 1.0);
@@ -811,22 +926,27 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             break;
         }
         if (rn <= tol) break;
+        if (last_k == 0) {
+            status = set_error(c, VMS_ENOCONV_GMRES, "gmres: stagnation (no Arnoldi progress)");
+            break;
+        }
         if (iters >= max_iters) {
             status = set_error(c, VMS_ENOCONV_GMRES, "gmres: iteration cap reached before rtol");
             break;
         }
-        CycleStatus st{0, 0};
+        if (using_learned && iters >= learned_budget) {
+            // the learned blocks did not deliver within half the budget: continue from the
+            // current iterate with plain block-Jacobi
+            if ((rc = launch_bj_setup(c, A, c->Minv, s))) return rc;
+            using_learned = false;
+            inf.fell_back_to_bj = 1;
+        }
         if (c->prec == VMS_FP64) {
             // one restart cycle on the FP64 residual; the true residual is recomputed above
-            const int k = run_cycle<double, double>(c, (const double*)A, c->r64, (const double*)c->Minv, x, tol,
-                                                    m, max_iters - iters, o->cgs2, &st, s);
-            if (k < 0) return VMS_EHIP;
-            iters += k;
-            inf.restarts++;
-            if (k == 0) {
-                status = set_error(c, VMS_ENOCONV_GMRES, "gmres: stagnation (no Arnoldi progress)");
-                break;
-            }
+            if ((rc = run_cycle<double, double>(c, (const double*)A, c->r64, (const double*)c->Minv, x, tol, m,
+                                                max_iters - iters, o->cgs2, s)))
+                return rc;
+            pending = true;
         } else {
             // FP64 iterative refinement: FP32 restarted GMRES on A d = r / ||r||, then x += ||r|| d
             if (inf.refinements >= refine_max) {
@@ -837,31 +957,30 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             float* rr = (float*)c->r;      // unit-norm residual of this sweep
             float* d = (float*)c->d;       // FP32 correction
             float* q = c->tvec;            // inner residual rr - A d
-            float* Ad = c->tvec + n;
             convert_kernel<double, float><<<grid_for(n), kBlock, 0, s>>>(n, c->r64, rr, 1.0 / rn);
             if ((rc = launch_fill(d, n * sizeof(float), s))) return rc;
             const double inner_tol = std::max(inner_rtol, 0.3 * tol / rn);
             const float* cycle_r = rr;
             int progress = 0;
             while (iters < max_iters) {
-                const int k = run_cycle<float, float>(c, (const float*)A, cycle_r, (const float*)c->Minv, d, inner_tol,
-                                                      m, max_iters - iters, o->cgs2, &st, s);
-                if (k < 0) return VMS_EHIP;
+                if ((rc = run_cycle<float, float>(c, (const float*)A, cycle_r, (const float*)c->Minv, d, inner_tol,
+                                                  m, max_iters - iters, o->cgs2, s)))
+                    return rc;
+                spmv_kernel<float, float, float, float, 1, float><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
+                    c->n_nodes, c->rowptr, c->colidx, (const float*)A, d, rr, q, nullptr);
+                norm_kernel<float><<<red_grid(n), kBlock, 0, s>>>(n, q, c->red, c->rnorm + 2);
+                double qn = 0.0;
+                if ((rc = read_scalar(c, c->rnorm + 2, &qn, s))) return rc;     // synchronises
+                const int k = finish_cycle(c);
                 iters += k;
                 progress += k;
                 inf.restarts++;
                 if (k == 0) break;
-                spmv_kernel<float, float, float, float, 1, float><<<grid_for(n), kBlock, 0, s>>>(
-                    c->n_nodes, c->rowptr, c->colidx, (const float*)A, d, rr, q, nullptr);
-                (void)Ad;
                 if (o->log_residuals && inf.logged < o->log_max) {
                     convert_kernel<float, float><<<grid_for(n), kBlock, 0, s>>>(
                         n, q, o->log_residuals + (size_t)inf.logged * n, 1.0);
                     inf.logged++;
                 }
-                norm_kernel<float><<<red_grid(n), kBlock, 0, s>>>(n, q, c->red, c->rnorm + 2);
-                double qn = 0.0;
-                if ((rc = read_scalar(c, c->rnorm + 2, &qn, s))) return rc;
                 if (!(qn > inner_tol) || !std::isfinite(qn)) break;
                 cycle_r = q;
             }

@@ -67,12 +67,13 @@ struct GmresState {
     double hn;                     // h(j+1, j) of the last completed column
     double ccol[kMaxRestart + 1];  // reorthogonalisation coefficients of the current step
     double svs[kMaxRestart + 1];   // free-pressure sum of every basis vector
-    int redo;                      // 1: the current step is being reorthogonalised
-    int nbc;                       // partial sums of the step's final norm (1 when not reorthogonalised)
+    int redo;                      // 1: the current step took a second Gram-Schmidt pass
     int reorth;                    // reorthogonalisation mode: 0 never, 1 when cancellation (DGKS), 2 always
     int k;                         // Arnoldi steps completed in this cycle
     int done;                      // 1: converged or breakdown, later kernels idle
     unsigned counter;              // arrival counter of last-block reductions
+    unsigned gen;                  // cycle number (host-assigned) reported with the progress word
+    uint64_t* progress;            // host-mapped progress word: gen << 32 | k << 1 | done
 };
 
 // Grid-wide reduction scratch.
@@ -133,6 +134,12 @@ struct vms_ctx {
     double* r64 = nullptr;           // [4 n_nodes]
     vms::GmresState* gs = nullptr;
     vms::RedScratch* red = nullptr;
+    // progress of the running GMRES cycle, written by the device into pinned host memory so
+    // that the host can follow it without synchronising the stream
+    uint64_t* progress_host = nullptr;
+    uint64_t* progress_dev = nullptr;
+    uint32_t cycle_gen = 0;
+    std::vector<int64_t> cycle_timed;    // timed launches of the cycle: (step, slot, generation)
 
     // learned preconditioner (device, float)
     float* feats = nullptr;          // [n_nodes][25]
@@ -147,7 +154,10 @@ struct vms_ctx {
     std::string err;
 
     // phase timers
-    bool prof_on = false;
+    uint32_t prof_mask = 0;                // phases being timed
+    int32_t prof_every = 1;                // time every n-th launch of a phase
+    int64_t prof_seen[VMS_NPHASES] = {};   // launches seen per phase
+    int64_t prof_gen = 0;                  // pending-slot generation (bumped by each flush)
     std::vector<hipEvent_t> prof_ev;       // pairs
     std::vector<int> prof_phase;           // pending slot -> phase
     std::vector<double> prof_bytes;        // pending slot -> algorithmic bytes
@@ -166,12 +176,18 @@ inline size_t elt_size(const vms_ctx* c) { return c->prec == VMS_FP64 ? 8 : 4; }
 // phase timers (ctx.cpp): a scope records an event pair around the launches it encloses
 int prof_begin(vms_ctx* c, int phase, double bytes, hipStream_t s);
 void prof_end(vms_ctx* c, int slot, hipStream_t s);
+// Drops a pending timed launch (one that returned without work) from the accumulators.
+void prof_void(vms_ctx* c, int slot, int64_t gen);
 struct PhaseScope {
     vms_ctx* c;
     int slot;
+    int64_t gen;
     hipStream_t s;
-    PhaseScope(vms_ctx* c_, int phase, double bytes, hipStream_t s_) : c(c_), slot(-1), s(s_) {
-        if (c->prof_on) slot = prof_begin(c, phase, bytes, s);
+    PhaseScope(vms_ctx* c_, int phase, double bytes, hipStream_t s_) : c(c_), slot(-1), gen(0), s(s_) {
+        if ((c->prof_mask >> phase) & 1u) {
+            slot = prof_begin(c, phase, bytes, s);
+            gen = c->prof_gen;
+        }
     }
     ~PhaseScope() {
         if (slot >= 0) prof_end(c, slot, s);

@@ -269,3 +269,30 @@ def test_invalid_arguments_are_reported(vms_lib, ragged):
     with pytest.raises(B.VmsError) as e:
         B.Context(to_dev(m.xyz), to_dev(m.tets.astype(np.int32)), to_dev(np.array([4 * m.n_nodes], np.int32)))
     assert e.value.code == B.VMS_EINVAL
+
+
+def test_phase_timer_mask_and_sampling(vms_lib):
+    """vms_profile: only the masked phase is timed, every n-th launch of it."""
+    B = vms_lib
+    m, bc, u, ctx = _cavity(4, 100.0, B.VMS_MIXED, B)
+    beta = to_dev(np.zeros((m.n_elems, 3)))
+    A_g, b_g, _ = B.vms_condense_assemble(ctx, to_dev(u), beta, 100.0)
+    counts = {}
+    for every in (1, 4):
+        B.vms_profile(ctx, True, phases=["spmv"], every=every)
+        rc, info = B.vms_gmres_solve(ctx, A_g, b_g, ctx.new_vec(), B.solve_opts(rtol=1e-8, max_iters=20000))
+        prof = B.vms_profile_read(ctx)
+        B.vms_profile(ctx, False)
+        assert all(v[1] == 0 for k, v in prof.items() if k != "spmv")
+        assert prof["spmv"][1] > 0 and prof["spmv"][0] > 0.0
+        counts[every] = (prof["spmv"][1], info.iters, info.refinements)
+    n1, it1, nref = counts[1]
+    n4, it4, _ = counts[4]
+    # one timed SpMV per Arnoldi step; steps issued after convergence (before the host saw
+    # the flag) are not counted
+    assert n1 == it1 and it4 == it1
+    # every 4th launch, counting the dropped ones (at most 7 after each inner solve)
+    assert abs(n4 - n1 / 4) <= 2 * (nref + 2)
+    with pytest.raises(B.VmsError) as e:
+        B.vms_profile(ctx, True, every=0)
+    assert e.value.code == B.VMS_EINVAL
