@@ -143,8 +143,10 @@ typedef struct {
     const float* pc_weights;   /* device, VMS_PC_LEARNED only (layout in vms_pc_*)       */
     int32_t refine_max;        /* mixed ctx: FP64 iterative-refinement sweeps (<= 0: 30) */
     double inner_rtol;         /* mixed ctx: FP32 GMRES tolerance per sweep (<= 0: 1e-5) */
-    int32_t cgs2;              /* classical Gram-Schmidt re-orthogonalisation: 0 never,
-                                  1 when ||w|| drops below ||w_before||/sqrt(2), 2 always */
+    int32_t cgs2;              /* nonzero: every basis vector gets a second classical
+                                  Gram-Schmidt pass, delayed into the next Arnoldi step so
+                                  that each step needs one reduction; 0: one pass (each
+                                  vector's norm is still measured, not estimated)          */
     int32_t coarse_pressure;   /* 1: add the coarse correction on the constant pressure
                                   mode, P v = M v + z (z^T v) / (z^T A z), z = 1 on every
                                   free pressure dof.  With one pinned pressure dof that mode
@@ -242,10 +244,10 @@ enum {
     VMS_PH_RESIDUAL = 1,       /* residual-only element kernel                            */
     VMS_PH_RECOVER = 2,        /* fine-scale recovery kernel                              */
     VMS_PH_PCSETUP = 3,        /* preconditioner block setup                              */
-    VMS_PH_PCAPPLY = 4,        /* normalisation + preconditioner apply in the Arnoldi step */
+    VMS_PH_PCAPPLY = 4,        /* preconditioner apply in the Arnoldi step                */
     VMS_PH_SPMV = 5,           /* block-CSR SpMV in the Arnoldi step                      */
-    VMS_PH_DOTS = 6,           /* first Gram-Schmidt dot products (V^T w, ||w||)          */
-    VMS_PH_UPDATE = 7,         /* first Gram-Schmidt update (w -= V h)                    */
+    VMS_PH_DOTS = 6,           /* Gram-Schmidt dot products (Q^T u, Q^T w, norms)         */
+    VMS_PH_UPDATE = 7,         /* Gram-Schmidt update (q_j and the next vector)           */
     VMS_PH_FILL = 8,           /* zero fill of the assembled outputs                      */
     VMS_NPHASES = 9
 };

@@ -66,7 +66,9 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
                                                       const TA* __restrict__ A, const TX* __restrict__ x,
                                                       const TB* __restrict__ b, TY* __restrict__ y,
                                                       const int* __restrict__ done) {
-    if (done && *done) return;
+    // a finished GMRES cycle (done != NULL and set) skips the store; the flag is read
+    // alongside the data so that it adds no latency in front of the loads
+    const int skip = done ? *done : 0;
     constexpr int Q = kSpmvLanes / 4;
     using VA = typename Vec4<TA>::type;
     using VX = typename Vec4<TX>::type;
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
         }
     }
     acc += __shfl_xor(acc, 4, 64);       // lanes 4q + r of a row: q = 0 and q = 1
-    if (row < n_rows && q == 0) {
+    if (row < n_rows && q == 0 && !skip) {
         if (MODE == 1)
             y[4 * (size_t)row + r] = TY(TACC(b[4 * (size_t)row + r]) - acc);
         else
@@ -299,8 +301,7 @@ __global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __r
     }
     if (last && threadIdx.x == 0) {
         const double nrm = sqrt(tot[0]);
-        gs->sv = nrm > 0.0 ? tot[1] / nrm : 0.0;
-        gs->svs[0] = gs->sv;
+        gs->su = nrm > 0.0 ? tot[1] / nrm : 0.0;
         gs->beta = nrm;
         gs->g[0] = nrm;
         gs->gin[0] = nrm;
@@ -309,7 +310,6 @@ __global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __r
         gs->done = (nrm <= tol_abs || !(nrm > 0.0)) ? 1 : 0;
         gs->norm = nrm;
         gs->reorth = reorth;
-        gs->redo = 0;
         gs->gen = gen;
         red->counter = 0u;
         report_progress(gs, 0, gs->done);
@@ -326,231 +326,354 @@ __global__ void cycle_v0_kernel(int n, const T* __restrict__ r, T* __restrict__ 
 }
 
 // ------------------------------------------------------------------- Arnoldi step kernels
-// Step j is a chain of small kernels; partial sums travel through plain-store slots and are
-// reduced by single-workgroup kernels, so no workgroup ever issues a device-scope fence (an
-// L2 write-back across the XCDs of this part) and every reduction has one level:
-//   arnoldi_pc     v_j = (w - V c) / h(j, j-1) (c = 0 unless step j-1 took a second pass),
-//                  z = P v_j (+ coarse pressure term)
-//   spmv           w = A z
-//   dots2d         slots: V_i . w (i <= j), w . w                        -> part
-//   reduce_h       h = slots, H(:, j) = h, ||w||^2                          (1 workgroup)
-//   update         w -= V h
-//   dots2d         slots: c = V^T w, w . w, free-pressure sum of w         -> part
-//   reduce_c       DGKS test: a second pass is taken when ||w|| < ||w_before|| / sqrt(2).
-//                  Its results need no further reduction: for orthonormal V,
-//                  ||w - V c||^2 = ||w||^2 - ||c||^2, and the free-pressure sum of w - V c is
-//                  S(w) - sum_i c_i S(v_i); H(:, j) += c.  Then h(j+1, j), Givens rotation,
-//                  residual estimate, done flag.  The subtraction w -= V c itself is folded
-//                  into the next arnoldi_pc.                               (1 workgroup)
-constexpr int kDotChunks = 64;            // workgroups per dot product
+// Gram-Schmidt with delayed reorthogonalisation and a single reduction per step (the DCGS2
+// scheme of Swirydowicz et al. / Bielich et al., written here for right-preconditioned
+// Arnoldi).  Entering step j, q_0 .. q_{j-1} are final and V[j] holds u_j, the next vector
+// after one classical Gram-Schmidt pass, normalised by an estimate; column j-1 of H is
+// provisional.  B = A P is the preconditioned operator, S(v) the sum of the free pressure
+// entries of v.
+//   arnoldi_pc   z = P u_j (block inverse + coarse pressure term, S(u_j) carried in gs)
+//   spmv         w = A z = B u_j
+//   dots         slots per (chunk, y): y < j -> (q_y . u_j, q_y . w);  y = j -> (u_j . u_j,
+//                u_j . w);  y = j + 1 -> (w . w, S(w))                          -> part
+//   reduce       (one workgroup) s = Q^T u_j, rho = sqrt(u_j . u_j - |s|^2):  q_j = (u_j - Q s)/rho
+//                is u_j's second pass, so column j-1 becomes final: H(0:j-1, j-1) += hh s,
+//                H(j, j-1) = hh rho (hh: its provisional subdiagonal); Givens rotation, residual
+//                estimate, done flag.  Then column j from the same sums: with t = Q^T w and
+//                c = (t, (u_j . w - s . t) / rho) = Q_j^T w,  H(0:j, j) = (c - H s) / rho, and the
+//                provisional subdiagonal hh = sqrt(w . w - |c|^2) / rho (Pythagoras).
+//   update       q_j = (u_j - Q s) / rho over V[j];  u_{j+1} = (w - Q t - c_j q_j) / (rho hh) to V[j+1]
+// An estimate that loses digits to cancellation only scales u_{j+1}; the next step measures
+// its norm directly (u . u), so the final subdiagonal hh rho is exact to rounding.  With
+// reorthogonalisation off, s is taken as 0 (one Gram-Schmidt pass, the norm still measured).
+constexpr int kDotChunks = VMS_DOT_CHUNKS;       // workgroups per dot product
 constexpr int kDotThreads = 256;
-static_assert((kMaxRestart + 3) * kDotChunks <= kRedBlocks * (kMaxRestart + 1), "dot slots exceed scratch");
+static_assert(2 * (kMaxRestart + 2) * kDotChunks <= kRedBlocks * (kMaxRestart + 1), "dot slots exceed scratch");
 
-// Slot y of a 2-D dot grid: y <= j -> V_y . w;  y == j+1 -> w . w;  y == j+2 -> free-pressure
-// sum of w.  One node (4 dofs) per vector load; one block reduction per workgroup.
 template <typename T>
-__global__ __launch_bounds__(kDotThreads) void dots2d_kernel(int n_nodes, int j, const T* __restrict__ V,
-                                                             const T* __restrict__ w,
-                                                             const uint8_t* __restrict__ dmask,
-                                                             double* __restrict__ part, const GmresState* gs) {
-    if (gs->done) return;
+__global__ __launch_bounds__(kDotThreads) void dots_kernel(int n_nodes, int j, const T* __restrict__ V,
+                                                           const T* __restrict__ w,
+                                                           const uint8_t* __restrict__ dmask,
+                                                           double* __restrict__ part, const GmresState* gs) {
+    const int skip = gs->done;
     using V4 = typename Vec4<T>::type;
     const int y = blockIdx.y;
-    const int kind = y <= j ? 0 : (y == j + 1 ? 1 : 2);
+    const int kind = y < j ? 0 : (y == j ? 1 : 2);
+    const size_t N4 = (size_t)n_nodes;          // float4 / double4 entries per vector
+    const V4* u4 = reinterpret_cast<const V4*>(V) + (size_t)j * N4;
     const V4* w4 = reinterpret_cast<const V4*>(w);
-    const V4* v4 = reinterpret_cast<const V4*>(V + (size_t)(kind == 0 ? y : 0) * 4 * (size_t)n_nodes);
+    const V4* q4 = reinterpret_cast<const V4*>(V) + (size_t)(kind == 0 ? y : 0) * N4;
     const int per = (n_nodes + gridDim.x - 1) / gridDim.x;
     const int i0 = blockIdx.x * per, i1 = min(n_nodes, i0 + per);
-    double acc = 0.0;
+    double a0 = 0.0, a1 = 0.0;
     for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         const V4 b = w4[i];
         if (kind == 0) {
-            const V4 a = v4[i];
-            acc += double(a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w);
+            const V4 q = q4[i], u = u4[i];
+            a0 += double(q.x * u.x + q.y * u.y + q.z * u.z + q.w * u.w);
+            a1 += double(q.x * b.x + q.y * b.y + q.z * b.z + q.w * b.w);
         } else if (kind == 1) {
-            acc += double(b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w);
-        } else if (!(dmask[i] & 8u)) {
-            acc += double(b.w);
+            const V4 u = u4[i];
+            a0 += double(u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w);
+            a1 += double(u.x * b.x + u.y * b.y + u.z * b.z + u.w * b.w);
+        } else {
+            a0 += double(b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w);
+            if (!(dmask[i] & 8u)) a1 += double(b.w);
         }
     }
-    acc = wave_sum(acc);
-    __shared__ double lds[kDotThreads / 64];
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    __shared__ double lds[2][kDotThreads / 64];
+    if ((threadIdx.x & 63) == 0) {
+        lds[0][threadIdx.x >> 6] = a0;
+        lds[1][threadIdx.x >> 6] = a1;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 2 && !skip) {
         double t = 0.0;
-        for (int k = 0; k < kDotThreads / 64; ++k) t += lds[k];
-        part[(size_t)y * kDotChunks + blockIdx.x] = t;
+        for (int k = 0; k < kDotThreads / 64; ++k) t += lds[threadIdx.x][k];
+        part[(size_t)(2 * y + threadIdx.x) * kDotChunks + blockIdx.x] = t;
     }
 }
 
-// Sums the slots of a dot grid into LDS (one slot per thread group, fixed order).
-__device__ void sum_slots(const double* __restrict__ part, int ns, int nchunks, double* out) {
-    for (int sl = threadIdx.x; sl < ns; sl += blockDim.x) {
-        const double* p = part + (size_t)sl * kDotChunks;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int k = 0;
-        for (; k + 4 <= nchunks; k += 4) {
-            a0 += p[k];
-            a1 += p[k + 1];
-            a2 += p[k + 2];
-            a3 += p[k + 3];
-        }
-        for (; k < nchunks; ++k) a0 += p[k];
-        out[sl] = (a0 + a1) + (a2 + a3);
-    }
-    __syncthreads();
-}
-
-// Completes column jc with h(jc+1, jc) = hn (one workgroup): rotations from LDS, residual
-// estimate, done flag; sv = free-pressure sum of the next basis vector.
-__device__ void complete_column(int jc, double hn, double psum, GmresState* gs) {
+// Givens rotation of column jc (held in LDS, rows 0 .. jc+1), with the rotations of columns
+// 0 .. jc-1 in LDS (cl, sl) and gj the rotated right-hand side entry jc; updates R, g, the
+// residual estimate, k and the done flag, and publishes the progress.  Returns 1 when the
+// cycle stops.  Called by one thread; the LDS operands are fetched eight at a time so that
+// only the rotation chain itself is sequential.
+__device__ int givens_column(int jc, const double* col, double* cl, double* sl, double gj, GmresState* gs) {
     constexpr int ld = kMaxRestart + 1;
-    __shared__ double col[kMaxRestart + 1], csl[kMaxRestart], snl[kMaxRestart];
-    const double* Hj = gs->H + (size_t)jc * ld;
-    for (int i = threadIdx.x; i <= jc; i += blockDim.x) col[i] = Hj[i];
-    for (int i = threadIdx.x; i < jc; i += blockDim.x) {
-        csl[i] = gs->cs[i];
-        snl[i] = gs->sn[i];
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
     double* Rj = gs->R + (size_t)jc * ld;
     double x = col[0];
-    for (int i = 0; i < jc; ++i) {
-        const double y = col[i + 1];
-        Rj[i] = csl[i] * x + snl[i] * y;
-        x = -snl[i] * x + csl[i] * y;
+    int i = 0;
+    for (; i + 8 <= jc; i += 8) {
+        double c8[8], s8[8], y8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            c8[q] = cl[i + q];
+            s8[q] = sl[i + q];
+            y8[q] = col[i + q + 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            Rj[i + q] = c8[q] * x + s8[q] * y8[q];
+            x = -s8[q] * x + c8[q] * y8[q];
+        }
     }
+    for (; i < jc; ++i) {
+        const double yv = col[i + 1];
+        Rj[i] = cl[i] * x + sl[i] * yv;
+        x = -sl[i] * x + cl[i] * yv;
+    }
+    const double hn = col[jc + 1];
     const double d = hypot(x, hn);
     const double cs = d > 0.0 ? x / d : 1.0;
     const double sn = d > 0.0 ? hn / d : 0.0;
-    const double gj = gs->gin[jc];
     const double gnext = -sn * gj;
     const bool conv = fabs(gnext) <= gs->tol_abs;
     const bool breakdown = !(hn > 1e-300 * (fabs(d) + 1e-300)) || !isfinite(hn) || !isfinite(gnext);
     Rj[jc] = d;
     gs->cs[jc] = cs;
     gs->sn[jc] = sn;
+    cl[jc] = cs;
+    sl[jc] = sn;
     gs->g[jc] = cs * gj;
     gs->gin[jc + 1] = gnext;
-    gs->H[(size_t)jc * ld + jc + 1] = hn;
-    gs->hn = hn;
-    gs->sv = hn > 0.0 ? psum / hn : 0.0;
-    gs->svs[jc + 1] = gs->sv;
     gs->k = jc + 1;
-    if (conv || breakdown) gs->done = 1;
-    report_progress(gs, jc + 1, conv || breakdown);
+    const int stop = (conv || breakdown) ? 1 : 0;
+    if (stop) gs->done = 1;
+    report_progress(gs, jc + 1, stop);
+    return stop;
 }
 
-// reduce_h: h = V^T w, H(:, j) = h, ||w||^2 before orthogonalisation.
-__global__ __launch_bounds__(kBlock) void reduce_h_kernel(int j, int nchunks, const double* __restrict__ part,
-                                                          GmresState* gs) {
-    if (gs->done) return;
-    __shared__ double v[kMaxRestart + 3];
-    sum_slots(part, j + 2, nchunks, v);
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-        gs->hcol[i] = v[i];
-        gs->H[(size_t)j * (kMaxRestart + 1) + i] = v[i];
+// Sum over the eight lanes of an aligned group.
+__device__ __forceinline__ double group8_sum(double v) {
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
+    return v;
+}
+
+// Step j's reduction (one workgroup of kRedThreads).  last = 1 at the end of a cycle: only
+// column j-1 is finalised.  Every global value the step needs (the dot slots, columns
+// 0 .. j-1 of H, rotations, pressure sums, flags) is loaded in one predicated round before
+// any is used, so the kernel pays the memory latency about once; slot sums use eight lanes
+// per slot (eight chunks each), H s eight lanes per row.
+constexpr int kRedThreads = 1024;
+constexpr int kHLoads = ((kMaxRestart + 1) * kMaxRestart + kRedThreads - 1) / kRedThreads;
+constexpr int kSlotLanes = 8;                               // lanes per dot slot
+constexpr int kSlotChunks = 64 / kSlotLanes;                // chunks per lane
+constexpr int kSlotGroups = kRedThreads / kSlotLanes;       // slots per round
+constexpr int kSlotRounds = (2 * (kMaxRestart + 2) + kSlotGroups - 1) / kSlotGroups;
+static_assert(kDotChunks <= 64, "a slot has at most 64 chunks");
+
+__global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks, const double* __restrict__ part,
+                                                             GmresState* gs, int last) {
+    constexpr int ld = kMaxRestart + 1;
+    const int lh = j + 1;                                  // rows 0 .. j of H in LDS
+    __shared__ double sums[2 * (kMaxRestart + 2)];
+    __shared__ double Hl[(kMaxRestart + 1) * kMaxRestart];
+    __shared__ double colj[kMaxRestart + 2];
+    __shared__ double cl[kMaxRestart], sl[kMaxRestart], svl[kMaxRestart + 1];
+    __shared__ double sc[8];
+    __shared__ int flags[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ns = 2 * (j + 2);
+    const int nh = lh * j;
+    const int grp = tid / kSlotLanes, sub = tid % kSlotLanes;
+    double pv[kSlotRounds][kSlotChunks];
+#pragma unroll
+    for (int r = 0; r < kSlotRounds; ++r) {
+        const int slot = grp + kSlotGroups * r;
+#pragma unroll
+        for (int c = 0; c < kSlotChunks; ++c) {
+            const int ch = sub * kSlotChunks + c;
+            pv[r][c] = (slot < ns && ch < nchunks) ? part[(size_t)slot * kDotChunks + ch] : 0.0;
+        }
     }
-    if (threadIdx.x == 0) gs->wn2 = v[j + 1];
-}
-
-// reduce_c: c = V^T w after the first pass; DGKS test; completes column j.
-__global__ __launch_bounds__(kBlock) void reduce_c_kernel(int j, int nchunks, const double* __restrict__ part,
-                                                          GmresState* gs) {
-    if (gs->done) return;
-    __shared__ double v[kMaxRestart + 3];
-    __shared__ double fin[2];
-    __shared__ int redo;
-    sum_slots(part, j + 3, nchunks, v);
-    if (threadIdx.x == 0) {
-        const double after = v[j + 1], before = gs->wn2;
-        const int r = (gs->reorth == 2 || (gs->reorth == 1 && after < 0.5 * before)) ? 1 : 0;
-        double n2 = after, ps = v[j + 2];
-        if (r) {
-            for (int i = 0; i <= j; ++i) {
-                n2 -= v[i] * v[i];
-                ps -= v[i] * gs->svs[i];
+    double hv[kHLoads];
+#pragma unroll
+    for (int q = 0; q < kHLoads; ++q) {
+        const int idx = tid + kRedThreads * q;
+        if (idx < nh) {
+            const int l = idx / lh, i = idx - l * lh;
+            hv[q] = gs->H[(size_t)l * ld + i];
+        } else {
+            hv[q] = 0.0;
+        }
+    }
+    if (tid < j) {
+        svl[tid] = gs->svs[tid];
+        if (tid + 1 < j) {
+            cl[tid] = gs->cs[tid];
+            sl[tid] = gs->sn[tid];
+        }
+    }
+    if (tid == 0) {
+        flags[0] = gs->done;
+        flags[1] = gs->reorth;
+        sc[5] = j > 0 ? gs->gin[j - 1] : 0.0;
+        sc[6] = gs->su;
+    }
+#pragma unroll
+    for (int q = 0; q < kHLoads; ++q) {
+        const int idx = tid + kRedThreads * q;
+        if (idx < nh) Hl[idx] = hv[q];
+    }
+#pragma unroll
+    for (int r = 0; r < kSlotRounds; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int c = 0; c < kSlotChunks; ++c) a += pv[r][c];
+        a = group8_sum(a);
+        const int slot = grp + kSlotGroups * r;
+        if (sub == 0 && slot < ns) sums[slot] = a;
+    }
+    __syncthreads();
+    if (flags[0]) return;
+    const int reorth = flags[1];
+    // sums: s_i = sums[2i], t_i = sums[2i+1] (i < j); then u.u, u.w, w.w, S(w).
+    // Wave 0 forms |s|^2, s.t, s.S(q), |t|^2, t.S(q) over i < j.
+    if (wave == 0) {
+        double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int i = lane; i < j; i += 64) {
+            const double si = reorth ? sums[2 * i] : 0.0, ti = sums[2 * i + 1], pi = svl[i];
+            a[0] += si * si;
+            a[1] += si * ti;
+            a[2] += si * pi;
+            a[3] += ti * ti;
+            a[4] += ti * pi;
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
+        if (lane == 0) {
+            sc[0] = j > 0 ? sqrt(fmax(sums[2 * j] - a[0], 0.0)) : 1.0;     // rho
+            sc[1] = a[1];
+            sc[2] = a[2];
+            sc[3] = a[3];
+            sc[4] = a[4];
+        }
+    }
+    __syncthreads();
+    const double rho = sc[0];
+    if (j > 0) {
+        // u_j's second pass completes column j-1
+        double* Hc = Hl + (size_t)(j - 1) * lh;
+        const double hh = Hc[j];
+        if (reorth)
+            for (int i = tid; i < j; i += kRedThreads) Hc[i] += hh * sums[2 * i];
+        __syncthreads();
+        if (tid == 0) {
+            Hc[j] = hh * rho;
+            int st = givens_column(j - 1, Hc, cl, sl, sc[5], gs);
+            if (!(rho > 0.0) || !isfinite(rho)) {
+                st = 1;                  // u_j vanished: column j-1 closes the cycle
+                gs->done = 1;
+                report_progress(gs, j, 1);
             }
+            svl[j] = rho > 0.0 ? (sc[6] - sc[2]) / rho : 0.0;     // S(q_j)
+            gs->svs[j] = svl[j];
+            flags[0] = st;
         }
-        redo = r;
-        gs->redo = r;
-        fin[0] = sqrt(fmax(n2, 0.0));
-        fin[1] = ps;
+        __syncthreads();
+        for (int i = tid; i <= j; i += kRedThreads) gs->H[(size_t)(j - 1) * ld + i] = Hc[i];
+        if (flags[0] || last) return;
+    } else {
+        if (tid == 0) {
+            svl[0] = sc[6];
+            gs->svs[0] = sc[6];
+        }
+        if (last) return;
+    }
+    // column j: c = (t, c_j) = Q_j^T w, H(0:j, j) = (c - H s) / rho
+    const double cj = (sums[2 * j + 1] - sc[1]) / rho;
+    for (int i0 = 0; i0 <= j; i0 += kSlotGroups) {
+        const int i = i0 + grp;
+        double hs = 0.0;
+        if (reorth && i <= j)
+            for (int l = max(0, i - 1) + sub; l < j; l += kSlotLanes) hs += Hl[(size_t)l * lh + i] * sums[2 * l];
+        hs = group8_sum(hs);
+        if (sub == 0 && i <= j) {
+            const double ci = i < j ? sums[2 * i + 1] : cj;
+            const double h = (ci - hs) / rho;
+            colj[i] = h;
+            gs->H[(size_t)j * ld + i] = h;
+        }
+    }
+    for (int i = tid; i < j; i += kRedThreads) {
+        gs->tcoef[i] = sums[2 * i + 1];
+        gs->scoef[i] = reorth ? sums[2 * i] : 0.0;
     }
     __syncthreads();
-    if (redo)
-        for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-            gs->ccol[i] = v[i];
-            gs->H[(size_t)j * (kMaxRestart + 1) + i] += v[i];
+    if (tid == 0) {
+        const double cc = sc[3] + cj * cj;                 // |c|^2
+        const double pw = sums[2 * j + 3] - sc[4] - cj * svl[j];
+        const double hh = sqrt(fmax(sums[2 * j + 2] - cc, 0.0)) / rho;
+        gs->H[(size_t)j * ld + j + 1] = hh;
+        gs->rho = rho;
+        gs->cj = cj;
+        gs->hh = hh;
+        gs->su = hh > 0.0 ? pw / (rho * hh) : 0.0;     // S(u_{j+1})
+        if (!(hh > 0.0) || !isfinite(hh)) {
+            // the Krylov space is invariant: column j is final with a zero subdiagonal
+            colj[j + 1] = 0.0;
+            givens_column(j, colj, cl, sl, gs->gin[j], gs);
+            gs->done = 1;
+            report_progress(gs, j + 1, 1);
         }
-    __syncthreads();
-    complete_column(j, fin[0], fin[1], gs);
+    }
 }
 
-// arnoldi_pc: v_j = (w - V c) / h(j, j-1) (j > 0; c only after a step with a second pass),
-// z = P v_j + coarse pressure term.  The four lanes of a node exchange their entries of v_j.
+// z = P u_j (block inverse of the node, plus the coarse pressure term on free pressure dofs).
 template <typename T>
-__global__ void arnoldi_pc_kernel(int n_nodes, int j, T* __restrict__ V, const T* __restrict__ w,
-                                  const T* __restrict__ Minv, const uint8_t* __restrict__ dmask, T* __restrict__ z,
-                                  const GmresState* gs) {
-    if (gs->done) return;
+__global__ void arnoldi_pc_kernel(int n_nodes, int j, const T* __restrict__ V, const T* __restrict__ Minv,
+                                  const uint8_t* __restrict__ dmask, T* __restrict__ z, const GmresState* gs) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = tid >> 2, r = tid & 3;
-    const bool active = node < n_nodes;
-    const size_t N = 4 * (size_t)n_nodes;
-    const size_t idx = 4 * (size_t)node + r;
-    T* vj = V + (size_t)j * N;
-    T mine = T(0);
-    if (active) {
-        if (j > 0) {
-            double sacc = double(w[idx]);
-            if (gs->redo) {
-                const double* cc = gs->ccol;
-                for (int i = 0; i < j; ++i) sacc -= cc[i] * double(V[(size_t)i * N + idx]);
-            }
-            mine = T(sacc / gs->hn);
-            vj[idx] = mine;
-        } else {
-            mine = vj[idx];
-        }
-    }
-    // lanes 4q .. 4q+3 of a wave hold one node; every lane takes part in the exchange
-    const int base = (threadIdx.x & 63) & ~3;
-    const T v0 = __shfl(mine, base, 64), v1 = __shfl(mine, base + 1, 64);
-    const T v2 = __shfl(mine, base + 2, 64), v3 = __shfl(mine, base + 3, 64);
-    if (!active) return;
+    if (node >= n_nodes) return;
+    const int skip = gs->done;
     using V4 = typename Vec4<T>::type;
+    const V4 u = *(reinterpret_cast<const V4*>(V) + (size_t)j * n_nodes + node);
     const V4 m = *reinterpret_cast<const V4*>(Minv + (size_t)node * 16 + r * 4);
-    T zz = m.x * v0 + m.y * v1 + m.z * v2 + m.w * v3;
-    if (r == 3 && !(dmask[node] & 8u)) zz += T(gs->kappa * gs->sv);
-    z[idx] = zz;
+    T zz = m.x * u.x + m.y * u.y + m.z * u.z + m.w * u.w;
+    if (r == 3 && !(dmask[node] & 8u)) zz += T(gs->kappa * gs->su);
+    if (!skip) z[4 * (size_t)node + r] = zz;
 }
 
-// w -= V h (h = gs->hcol, column j of the Hessenberg matrix from the first pass).
+// q_j = (u_j - Q s) / rho written over V[j];  u_{j+1} = (w - Q t - c_j q_j) / (rho hh) to V[j+1].
+// One element per thread; the basis is read once, in batches of eight vectors.  The
+// coefficients are uniform across the grid and come through scalar loads.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void update_kernel(int n, int j, const T* __restrict__ V, T* __restrict__ w,
+__global__ __launch_bounds__(kBlock) void update_kernel(int n, int j, T* __restrict__ V, const T* __restrict__ w,
                                                         const GmresState* gs) {
-    if (gs->done) return;
-    __shared__ double hs[kMaxRestart + 1];
-    const double* coef = gs->hcol;
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) hs[i] = coef[i];
-    __syncthreads();
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const double* __restrict__ ss = gs->scoef;
+    const double* __restrict__ ts = gs->tcoef;
     const size_t N = (size_t)n;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
-        double s = double(w[idx]);
-        int i = 0;
-        for (; i + 8 <= j + 1; i += 8) {
-            double vv[8];
+    T* uj = V + (size_t)j * N;
+    double aq = double(uj[idx]), aw = double(w[idx]);
+    int i = 0;
+    for (; i + 8 <= j; i += 8) {
+        double vv[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) vv[q] = double(V[(size_t)(i + q) * N + idx]);
+        for (int q = 0; q < 8; ++q) vv[q] = double(V[(size_t)(i + q) * N + idx]);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) s -= hs[i + q] * vv[q];
+        for (int q = 0; q < 8; ++q) {
+            aq -= ss[i + q] * vv[q];
+            aw -= ts[i + q] * vv[q];
         }
-        for (; i <= j; ++i) s -= hs[i] * double(V[(size_t)i * N + idx]);
-        w[idx] = T(s);
     }
+    for (; i < j; ++i) {
+        const double v = double(V[(size_t)i * N + idx]);
+        aq -= ss[i] * v;
+        aw -= ts[i] * v;
+    }
+    if (gs->done) return;
+    const double rho = gs->rho;
+    const double q = aq / rho;
+    uj[idx] = T(q);
+    V[(size_t)(j + 1) * N + idx] = T((aw - gs->cj * q) / (rho * gs->hh));
 }
 
 // y = R^{-1} g for the k x k triangle of the rotated Hessenberg matrix (one workgroup): the
@@ -766,8 +889,8 @@ int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double 
             if (st == 1) break;
         }
         {
-            PhaseScope ph(c, VMS_PH_PCAPPLY, 7.0 * vb, s);
-            arnoldi_pc_kernel<T><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, j, V, w, Minv, c->dmask, z, c->gs);
+            PhaseScope ph(c, VMS_PH_PCAPPLY, 6.0 * vb, s);
+            arnoldi_pc_kernel<T><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, j, V, Minv, c->dmask, z, c->gs);
             keep(j, ph);
         }
         {
@@ -778,19 +901,20 @@ int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double 
         }
         {
             PhaseScope ph(c, VMS_PH_DOTS, (j + 2) * vb, s);
-            dots2d_kernel<T><<<dim3(nch, j + 2), kDotThreads, 0, s>>>(c->n_nodes, j, V, w, c->dmask, part, c->gs);
+            dots_kernel<T><<<dim3(nch, j + 2), kDotThreads, 0, s>>>(c->n_nodes, j, V, w, c->dmask, part, c->gs);
             keep(j, ph);
         }
-        reduce_h_kernel<<<1, kBlock, 0, s>>>(j, nch, part, c->gs);
+        reduce_kernel<<<1, kRedThreads, 0, s>>>(j, nch, part, c->gs, 0);
         {
-            PhaseScope ph(c, VMS_PH_UPDATE, (j + 3) * vb, s);
+            PhaseScope ph(c, VMS_PH_UPDATE, (j + 4) * vb, s);
             update_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, j, V, w, c->gs);
             keep(j, ph);
         }
-        dots2d_kernel<T><<<dim3(nch, j + 3), kDotThreads, 0, s>>>(c->n_nodes, j, V, w, c->dmask, part, c->gs);
-        reduce_c_kernel<<<1, kBlock, 0, s>>>(j, nch, part, c->gs);
     }
-    // every column completes in its own step (reduce_c); y = R^{-1} g on the device
+    // the second pass of the last vector completes the last column
+    dots_kernel<T><<<dim3(nch, steps + 2), kDotThreads, 0, s>>>(c->n_nodes, steps, V, w, c->dmask, part, c->gs);
+    reduce_kernel<<<1, kRedThreads, 0, s>>>(steps, nch, part, c->gs, 1);
+    // y = R^{-1} g on the device
     backsub_kernel<<<1, kBlock, 0, s>>>(c->gs);
     combine_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, V, c->gs, z);
     free_pressure_sum_kernel<T><<<red_grid(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, z, c->dmask, c->red, c->gs);

@@ -17,6 +17,9 @@ namespace vms {
 constexpr int kBlock = 256;          // threads per workgroup for streaming kernels
 constexpr int kRedBlocks = 1024;     // workgroups of the grid-wide reductions
 constexpr int kMaxRestart = 128;
+#ifndef VMS_DOT_CHUNKS
+#define VMS_DOT_CHUNKS 64          // workgroups per GMRES dot product
+#endif
 constexpr int kTileNodes = 64;           // max nodes owned by one assembly tile
 #ifndef VMS_TILE_BLOCKS_FP64
 #define VMS_TILE_BLOCKS_FP64 420
@@ -56,19 +59,19 @@ struct GmresState {
     double g[kMaxRestart + 1];     // rotated right-hand side (final entries)
     double gin[kMaxRestart + 1];   // entry i before rotation i (gin[k] = residual estimate)
     double y[kMaxRestart];
-    double hcol[kMaxRestart + 1];  // CGS coefficients of the current step
+    double scoef[kMaxRestart];     // s = Q^T u_j: second-pass coefficients of the current step
+    double tcoef[kMaxRestart];     // t = Q^T w: first-pass coefficients of the current step
+    double svs[kMaxRestart + 1];   // free-pressure sum of every final basis vector
     double tol_abs;                // stop when |g[k]| <= tol_abs
     double beta;                   // norm of the cycle's initial residual
     double norm;                   // scratch: a finished reduction
     double kappa;                  // coarse pressure correction: 1 / (sum of free p-p entries), 0 = off
-    double sv;                     // sum of the free pressure entries of the current v_j
+    double su;                     // sum of the free pressure entries of u_j
     double st;                     // sum of the free pressure entries of the correction V y
-    double wn2;                    // ||w||^2 of the current step before orthogonalisation
-    double hn;                     // h(j+1, j) of the last completed column
-    double ccol[kMaxRestart + 1];  // reorthogonalisation coefficients of the current step
-    double svs[kMaxRestart + 1];   // free-pressure sum of every basis vector
-    int redo;                      // 1: the current step took a second Gram-Schmidt pass
-    int reorth;                    // reorthogonalisation mode: 0 never, 1 when cancellation (DGKS), 2 always
+    double rho;                    // norm of u_j after its second pass
+    double cj;                     // q_j . w
+    double hh;                     // provisional subdiagonal of column j (norm estimate of u_{j+1})
+    int reorth;                    // 0: one Gram-Schmidt pass; otherwise a delayed second pass
     int k;                         // Arnoldi steps completed in this cycle
     int done;                      // 1: converged or breakdown, later kernels idle
     unsigned counter;              // arrival counter of last-block reductions
