@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PROFILE_EVERY = 8            # timed region: HIP events on every 8th launch of the dominant kernel
 KERNEL_OF_PHASE = {"condense": "tile_kernel", "spmv": "spmv_kernel", "dots": "dots_kernel",
-                   "update": "update_kernel", "pc_apply": "arnoldi_pc_kernel"}
+                   "update": "update_kernel", "pc_apply": "ap_blocks_kernel"}
 
 
 def parse():

@@ -244,8 +244,8 @@ enum {
     VMS_PH_RESIDUAL = 1,       /* residual-only element kernel                            */
     VMS_PH_RECOVER = 2,        /* fine-scale recovery kernel                              */
     VMS_PH_PCSETUP = 3,        /* preconditioner block setup                              */
-    VMS_PH_PCAPPLY = 4,        /* preconditioner apply in the Arnoldi step                */
-    VMS_PH_SPMV = 5,           /* block-CSR SpMV in the Arnoldi step                      */
+    VMS_PH_PCAPPLY = 4,        /* A P formed once per solve (the Arnoldi SpMV applies P)  */
+    VMS_PH_SPMV = 5,           /* block-CSR SpMV with A P in the Arnoldi step             */
     VMS_PH_DOTS = 6,           /* Gram-Schmidt dot products (Q^T u, Q^T w, norms)         */
     VMS_PH_UPDATE = 7,         /* Gram-Schmidt update (q_j and the next vector)           */
     VMS_PH_FILL = 8,           /* zero fill of the assembled outputs                      */

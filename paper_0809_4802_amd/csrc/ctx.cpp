@@ -117,7 +117,7 @@ extern "C" int vms_profile_read(vms_ctx* c, double* ms, int64_t* launches, doubl
 static void free_all(vms_ctx* c) {
     void* ptrs[] = {c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
                     c->tpos, c->tile_node0, c->tile_iptr, c->item_ea, c->item_pos, c->A, c->rhs, c->du, c->rglob, c->rnorm, c->flags,
-                    c->V, c->w, c->z, c->d, c->r, c->Minv, c->x64, c->r64, c->gs, c->red,
+                    c->V, c->w, c->z, c->d, c->r, c->Minv, c->AP, c->Az, c->x64, c->r64, c->gs, c->red,
                     c->feats, c->hid, c->pblk, c->gblk, c->tvec, c->wgrad, c->fscal};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -354,6 +354,8 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->d, N * es, "alloc d"));
     TRY(dev_alloc(c, &c->r, N * es, "alloc r"));
     TRY(dev_alloc(c, &c->Minv, nn * 16 * es, "alloc Minv"));
+    TRY(dev_alloc(c, &c->AP, c->nb * 16 * es, "alloc A P"));
+    TRY(dev_alloc(c, &c->Az, N * es, "alloc A z"));
     TRY(dev_alloc(c, &c->x64, N * sizeof(double), "alloc x64"));
     TRY(dev_alloc(c, &c->r64, N * sizeof(double), "alloc r64"));
     TRY(dev_alloc(c, &c->gs, sizeof(GmresState), "alloc gmres state"));

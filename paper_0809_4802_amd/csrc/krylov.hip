@@ -57,7 +57,8 @@ __global__ void fill_kernel(uint4* p, size_t n16) {
 // 4-vector of the column node.  The first kSpmvUnroll blocks of a lane are all loaded before
 // any is used, so that its loads are in flight together (a row of this mesh has at most 15
 // blocks, i.e. 8 per lane); the two halves of a row are summed with one lane exchange.
-// MODE 0: y = A x.  MODE 1: y = b - A x.
+// MODE 0: y = A x.  MODE 1: y = b - A x.  MODE 2: y = A x + (kappa S) b with kappa and S (the
+// coarse pressure scale and the free-pressure sum of x) taken from the GMRES state.
 constexpr int kSpmvLanes = 8;
 constexpr int kSpmvUnroll = 8;
 template <typename TA, typename TX, typename TY, typename TACC, int MODE, typename TB = double>
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
                                                       const int32_t* __restrict__ colidx,
                                                       const TA* __restrict__ A, const TX* __restrict__ x,
                                                       const TB* __restrict__ b, TY* __restrict__ y,
-                                                      const int* __restrict__ done) {
+                                                      const int* __restrict__ done, const GmresState* gs) {
     // a finished GMRES cycle (done != NULL and set) skips the store; the flag is read
     // alongside the data so that it adds no latency in front of the loads
     const int skip = done ? *done : 0;
@@ -111,6 +112,8 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
     if (row < n_rows && q == 0 && !skip) {
         if (MODE == 1)
             y[4 * (size_t)row + r] = TY(TACC(b[4 * (size_t)row + r]) - acc);
+        else if (MODE == 2)
+            y[4 * (size_t)row + r] = TY(acc + TACC(gs->kappa * gs->su) * TACC(b[4 * (size_t)row + r]));
         else
             y[4 * (size_t)row + r] = TY(acc);
     }
@@ -323,6 +326,42 @@ __global__ void cycle_v0_kernel(int n, const T* __restrict__ r, T* __restrict__ 
     if (i >= n) return;
     const double b = gs->beta;
     V0[i] = b > 0.0 ? T(double(r[i]) / b) : T(0);
+}
+
+// A P for the Arnoldi steps: block (i, b) times the preconditioner block of node b, so that
+// the step's SpMV applies the preconditioner on the fly.  Four lanes per block, lane r forms
+// row r; the product is summed in FP64 and stored in T.
+template <typename T>
+__global__ void ap_blocks_kernel(int64_t nb, const int32_t* __restrict__ colidx, const T* __restrict__ A,
+                                 const T* __restrict__ Minv, T* __restrict__ AP) {
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t k = tid >> 2;
+    const int r = (int)(tid & 3);
+    if (k >= nb) return;
+    using V4 = typename Vec4<T>::type;
+    const V4 a = *reinterpret_cast<const V4*>(A + k * 16 + r * 4);
+    const T* M = Minv + (size_t)colidx[k] * 16;
+    double o[4];
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc)
+        o[cc] = double(a.x) * double(M[cc]) + double(a.y) * double(M[4 + cc]) + double(a.z) * double(M[8 + cc]) +
+                double(a.w) * double(M[12 + cc]);
+    *reinterpret_cast<V4*>(AP + k * 16 + r * 4) = V4{T(o[0]), T(o[1]), T(o[2]), T(o[3])};
+}
+
+// A z for z = 1 on every free pressure dof: per row, the sum of the pressure columns of the
+// blocks whose column node has a free pressure.  Four lanes per block row.
+template <typename T>
+__global__ void coarse_column_kernel(int n_rows, const int32_t* __restrict__ rowptr,
+                                     const int32_t* __restrict__ colidx, const T* __restrict__ A,
+                                     const uint8_t* __restrict__ dmask, T* __restrict__ Az) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = tid >> 2, r = tid & 3;
+    if (row >= n_rows) return;
+    double acc = 0.0;
+    for (int k = rowptr[row]; k < rowptr[row + 1]; ++k)
+        if (!(dmask[colidx[k]] & 8u)) acc += double(A[(size_t)k * 16 + r * 4 + 3]);
+    Az[4 * (size_t)row + r] = T(acc);
 }
 
 // ------------------------------------------------------------------- Arnoldi step kernels
@@ -624,22 +663,6 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks,
     }
 }
 
-// z = P u_j (block inverse of the node, plus the coarse pressure term on free pressure dofs).
-template <typename T>
-__global__ void arnoldi_pc_kernel(int n_nodes, int j, const T* __restrict__ V, const T* __restrict__ Minv,
-                                  const uint8_t* __restrict__ dmask, T* __restrict__ z, const GmresState* gs) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int node = tid >> 2, r = tid & 3;
-    if (node >= n_nodes) return;
-    const int skip = gs->done;
-    using V4 = typename Vec4<T>::type;
-    const V4 u = *(reinterpret_cast<const V4*>(V) + (size_t)j * n_nodes + node);
-    const V4 m = *reinterpret_cast<const V4*>(Minv + (size_t)node * 16 + r * 4);
-    T zz = m.x * u.x + m.y * u.y + m.z * u.z + m.w * u.w;
-    if (r == 3 && !(dmask[node] & 8u)) zz += T(gs->kappa * gs->su);
-    if (!skip) z[4 * (size_t)node + r] = zz;
-}
-
 // q_j = (u_j - Q s) / rho written over V[j];  u_{j+1} = (w - Q t - c_j q_j) / (rho hh) to V[j+1].
 // One element per thread; the basis is read once, in batches of eight vectors.  The
 // coefficients are uniform across the grid and come through scalar loads.
@@ -858,9 +881,11 @@ int wait_progress(vms_ctx* c, uint32_t gen, int need, hipStream_t s) {
 // converged; nothing here synchronises the stream.  finish_cycle gives the number of steps
 // once the caller has synchronised.
 template <typename T, typename TX>
-int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double tol_abs, int m, int budget,
-              int cgs2, hipStream_t s) {
+int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int m, int budget, int cgs2,
+              hipStream_t s) {
     const int n = 4 * c->n_nodes;
+    const T* AP = (const T*)c->AP;
+    const T* Az = (const T*)c->Az;
     T* V = (T*)c->V;
     T* w = (T*)c->w;
     T* z = (T*)c->z;
@@ -870,7 +895,7 @@ int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double 
     cycle_v0_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, r0, V, c->gs);
     const int steps = std::min(m, budget);
     const double vb = (double)n * sizeof(T);      // bytes of one Krylov vector
-    const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 2.0 * vb;
+    const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 3.0 * vb;
     const int nch = std::max(1, std::min(kDotChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
     double* part = c->red->partial;
     // timed launches per step, so that steps issued after convergence (their kernels return
@@ -889,14 +914,10 @@ int run_cycle(vms_ctx* c, const T* A, const T* r0, const T* Minv, TX* x, double 
             if (st == 1) break;
         }
         {
-            PhaseScope ph(c, VMS_PH_PCAPPLY, 6.0 * vb, s);
-            arnoldi_pc_kernel<T><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, j, V, Minv, c->dmask, z, c->gs);
-            keep(j, ph);
-        }
-        {
+            // w = A P u_j = (A P) u_j + kappa S(u_j) A z
             PhaseScope ph(c, VMS_PH_SPMV, spmv_bytes, s);
-            spmv_kernel<T, T, T, T, 0><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
-                c->n_nodes, c->rowptr, c->colidx, A, z, (const double*)nullptr, w, &c->gs->done);
+            spmv_kernel<T, T, T, T, 2, T><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
+                c->n_nodes, c->rowptr, c->colidx, AP, V + (size_t)j * n, Az, w, &c->gs->done, c->gs);
             keep(j, ph);
         }
         {
@@ -951,10 +972,10 @@ int launch_spmv(vms_ctx* c, const void* A, const void* x, void* y, hipStream_t s
     const int n = 4 * c->n_nodes;
     if (c->prec == VMS_FP64)
         spmv_kernel<double, double, double, double, 0><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
-            c->n_nodes, c->rowptr, c->colidx, (const double*)A, (const double*)x, (const double*)nullptr, (double*)y, nullptr);
+            c->n_nodes, c->rowptr, c->colidx, (const double*)A, (const double*)x, (const double*)nullptr, (double*)y, nullptr, nullptr);
     else
         spmv_kernel<float, float, float, float, 0><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
-            c->n_nodes, c->rowptr, c->colidx, (const float*)A, (const float*)x, (const double*)nullptr, (float*)y, nullptr);
+            c->n_nodes, c->rowptr, c->colidx, (const float*)A, (const float*)x, (const double*)nullptr, (float*)y, nullptr, nullptr);
     return check_hip(c, hipGetLastError(), "spmv launch");
 }
 
@@ -971,15 +992,34 @@ int launch_bj_setup(vms_ctx* c, const void* A, void* Minv, hipStream_t s) {
     return check_hip(c, hipGetLastError(), "bj setup launch");
 }
 
+// A P and A z for the Arnoldi steps (after the preconditioner blocks are set).
+int launch_ap_setup(vms_ctx* c, const void* A, hipStream_t s) {
+    const double es = elt_size(c);
+    PhaseScope ph(c, VMS_PH_PCAPPLY, (double)c->nb * (32.0 * es + 4.0) + (double)c->n_nodes * 16.0 * es, s);
+    const int g = (int)((4 * c->nb + kBlock - 1) / kBlock);
+    if (c->prec == VMS_FP64) {
+        ap_blocks_kernel<double><<<g, kBlock, 0, s>>>(c->nb, c->colidx, (const double*)A, (const double*)c->Minv,
+                                                     (double*)c->AP);
+        coarse_column_kernel<double><<<grid_for(4 * (int64_t)c->n_nodes), kBlock, 0, s>>>(
+            c->n_nodes, c->rowptr, c->colidx, (const double*)A, c->dmask, (double*)c->Az);
+    } else {
+        ap_blocks_kernel<float><<<g, kBlock, 0, s>>>(c->nb, c->colidx, (const float*)A, (const float*)c->Minv,
+                                                    (float*)c->AP);
+        coarse_column_kernel<float><<<grid_for(4 * (int64_t)c->n_nodes), kBlock, 0, s>>>(
+            c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, (float*)c->Az);
+    }
+    return check_hip(c, hipGetLastError(), "A P setup launch");
+}
+
 // FP64 residual r64 = b - A x64 and its norm (synchronising).
 static int true_residual(vms_ctx* c, const void* A, const double* b, const double* x, double* rn, hipStream_t s) {
     const int n = 4 * c->n_nodes;
     if (c->prec == VMS_FP64)
         spmv_kernel<double, double, double, double, 1><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
-            c->n_nodes, c->rowptr, c->colidx, (const double*)A, x, b, c->r64, nullptr);
+            c->n_nodes, c->rowptr, c->colidx, (const double*)A, x, b, c->r64, nullptr, nullptr);
     else
         spmv_kernel<float, double, double, double, 1><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
-            c->n_nodes, c->rowptr, c->colidx, (const float*)A, x, b, c->r64, nullptr);
+            c->n_nodes, c->rowptr, c->colidx, (const float*)A, x, b, c->r64, nullptr, nullptr);
     norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, c->r64, c->red, c->rnorm + 2);
     return read_scalar(c, c->rnorm + 2, rn, s);
 }
@@ -1013,6 +1053,7 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     else
         coarse_setup_kernel<float><<<red_grid(c->n_nodes), kBlock, 0, s>>>(
             c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, o->coarse_pressure, c->red, c->gs);
+    if ((rc = launch_ap_setup(c, A, s))) return rc;
     norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, b, c->red, c->rnorm + 3);
     double bn = 0.0;
     if ((rc = read_scalar(c, c->rnorm + 3, &bn, s))) return rc;
@@ -1062,13 +1103,14 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             // the learned blocks did not deliver within half the budget: continue from the
             // current iterate with plain block-Jacobi
             if ((rc = launch_bj_setup(c, A, c->Minv, s))) return rc;
+            if ((rc = launch_ap_setup(c, A, s))) return rc;
             using_learned = false;
             inf.fell_back_to_bj = 1;
         }
         if (c->prec == VMS_FP64) {
             // one restart cycle on the FP64 residual; the true residual is recomputed above
-            if ((rc = run_cycle<double, double>(c, (const double*)A, c->r64, (const double*)c->Minv, x, tol, m,
-                                                max_iters - iters, o->cgs2, s)))
+            if ((rc = run_cycle<double, double>(c, c->r64, (const double*)c->Minv, x, tol, m, max_iters - iters,
+                                                o->cgs2, s)))
                 return rc;
             pending = true;
         } else {
@@ -1087,11 +1129,11 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             const float* cycle_r = rr;
             int progress = 0;
             while (iters < max_iters) {
-                if ((rc = run_cycle<float, float>(c, (const float*)A, cycle_r, (const float*)c->Minv, d, inner_tol,
-                                                  m, max_iters - iters, o->cgs2, s)))
+                if ((rc = run_cycle<float, float>(c, cycle_r, (const float*)c->Minv, d, inner_tol, m,
+                                                  max_iters - iters, o->cgs2, s)))
                     return rc;
                 spmv_kernel<float, float, float, float, 1, float><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
-                    c->n_nodes, c->rowptr, c->colidx, (const float*)A, d, rr, q, nullptr);
+                    c->n_nodes, c->rowptr, c->colidx, (const float*)A, d, rr, q, nullptr, nullptr);
                 norm_kernel<float><<<red_grid(n), kBlock, 0, s>>>(n, q, c->red, c->rnorm + 2);
                 double qn = 0.0;
                 if ((rc = read_scalar(c, c->rnorm + 2, &qn, s))) return rc;     // synchronises

@@ -133,6 +133,8 @@ struct vms_ctx {
     void* d = nullptr;               // [4 n_nodes] correction accumulated by a solve
     void* r = nullptr;               // [4 n_nodes] inner residual
     void* Minv = nullptr;            // [n_nodes][16] preconditioner blocks
+    void* AP = nullptr;              // [nb][16] A P: each block times the preconditioner block of its column
+    void* Az = nullptr;              // [4 n_nodes] A z, z = 1 on every free pressure dof
     double* x64 = nullptr;           // [4 n_nodes]
     double* r64 = nullptr;           // [4 n_nodes]
     vms::GmresState* gs = nullptr;
