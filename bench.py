@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_EVERY = 8            # timed region: HIP events on every 8th launch of the dominant kernel
+COUNTER_ITERS = 64           # --counters: Arnoldi steps (SpMV launches) in the counter run
+COPY_MIB = 256               # --counters: size of the reference copy
 KERNEL_OF_PHASE = {"condense": "tile_kernel", "spmv": "spmv_kernel", "dots": "dots_kernel",
                    "update": "update_kernel", "pc_apply": "ap_blocks_kernel"}
 
@@ -38,6 +40,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle sample (0: every element of the workload)")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for hardware-counter passes: GMRES on the workload's mixed-precision "
+                         "tangent capped at COUNTER_ITERS Arnoldi steps, then a COPY_MIB device-to-device copy "
+                         "(the scale reference for the counters)")
     return ap.parse_args()
 
 
@@ -59,6 +65,9 @@ def main():
 
     dev = "cuda:0"
     cfg, mesh, u0, beta0, bc = build_workload(args.workload)
+    if args.counters:
+        counter_run(B, cfg, mesh, u0, beta0, bc, dev)
+        return
     xyz = torch.from_numpy(mesh.xyz).to(dev)
     tets = torch.from_numpy(mesh.tets).to(dev)
     dd = torch.from_numpy(bc.dofs).to(dev)
@@ -162,9 +171,10 @@ def main():
 
     ms, cnt, byt = prof[phase]
     achieved = byt / cnt / (ms / cnt / 1e3) / 1e9
+    traffic, traffic_src = measured_traffic(args.workload, phase)
     roofline = {"bound": "hbm", "kernel": KERNEL_OF_PHASE.get(phase, phase), "phase": phase,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
                 "avg_launch_us": round(1e3 * ms / cnt, 3), "launches_timed": cnt, "timed_every": PROFILE_EVERY,
                 "alg_bytes_per_launch": byt / cnt}
 
@@ -199,6 +209,49 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def spmv_source_hash():
+    """sha256 of the SpMV section of the GMRES source (the kernel the counters were taken on)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_0809_4802_amd", "csrc", "krylov.hip")).read()
+    a = src.index("// " + "-" * 82 + " SpMV")
+    b = src.index("// " + "-" * 75 + " block-Jacobi")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def measured_traffic(workload, phase):
+    """HBM-side bytes per launch of the dominant kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a copy of known size);
+    None when there is none or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_{phase}_traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as f:
+        d = json.load(f)
+    if phase != "spmv" or d.get("source_sha256") != spmv_source_hash():
+        return None, os.path.relpath(path, ROOT) + " (stale: kernel changed since the counters were taken)"
+    return d["traffic_bytes_per_launch"], os.path.relpath(path, ROOT)
+
+
+def counter_run(B, cfg, mesh, u0, beta0, bc, dev):
+    """The workload's mixed-precision tangent, GMRES(50) + block-Jacobi capped at COUNTER_ITERS
+    Arnoldi steps (as many launches of the Arnoldi SpMV), then one device-to-device copy of
+    COPY_MIB MiB.  Meant to run under rocprofv3 --pmc."""
+    import torch
+    ctx = B.Context(torch.from_numpy(mesh.xyz).to(dev), torch.from_numpy(mesh.tets).to(dev),
+                    torch.from_numpy(bc.dofs).to(dev), precision=B.VMS_MIXED)
+    A, rhs, _ = B.vms_condense_assemble(ctx, torch.from_numpy(u0).to(dev), torch.from_numpy(beta0).to(dev), cfg.re)
+    x = ctx.new_vec()
+    _, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=50, rtol=1e-14, max_iters=COUNTER_ITERS),
+                                allow_noconv=True)
+    src = torch.empty(COPY_MIB << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_run": True, "arnoldi_steps": int(info.iters), "copy_bytes": COPY_MIB << 20}))
 
 
 def cpu_baseline(mesh, u0, beta0, bc, cfg, n_sample):

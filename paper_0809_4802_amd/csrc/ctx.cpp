@@ -87,7 +87,9 @@ extern "C" int vms_profile(vms_ctx* c, uint32_t phase_mask, int32_t every) {
     if (c->prof_ev.empty() && phase_mask) {
         c->prof_ev.resize(2 * kProfPool);
         for (auto& e : c->prof_ev)
-            if (hipEventCreate(&e) != hipSuccess) return set_error(c, VMS_EHIP, "vms_profile: hipEventCreate");
+            // timing-only events: no system-scope fence (cache write-back) around the timed launches
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+                return set_error(c, VMS_EHIP, "vms_profile: hipEventCreate");
         c->prof_phase.resize(kProfPool);
         c->prof_bytes.resize(kProfPool);
     }
