@@ -142,7 +142,10 @@ typedef struct {
     vms_pc_kind pc;
     const float* pc_weights;   /* device, VMS_PC_LEARNED only (layout in vms_pc_*)       */
     int32_t refine_max;        /* mixed ctx: FP64 iterative-refinement sweeps (<= 0: 30) */
-    double inner_rtol;         /* mixed ctx: FP32 GMRES tolerance per sweep (<= 0: 1e-5) */
+    double inner_rtol;         /* mixed ctx: FP32 GMRES tolerance per sweep (<= 0: 1e-4); a
+                                  sweep also ends when a cycle's own estimate reached it but
+                                  the recomputed FP32 residual did not (the FP32 rounding
+                                  floor) or a cycle made no progress                       */
     int32_t cgs2;              /* nonzero: every basis vector gets a second classical
                                   Gram-Schmidt pass, delayed into the next Arnoldi step so
                                   that each step needs one reduction; 0: one pass (each

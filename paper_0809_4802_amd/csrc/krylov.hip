@@ -943,11 +943,13 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     return check_hip(c, hipGetLastError(), "gmres cycle launch");
 }
 
-// After the caller has synchronised the stream: Arnoldi steps of the last cycle.  Timed
-// launches of steps issued after convergence are dropped.
-int finish_cycle(vms_ctx* c) {
+// After the caller has synchronised the stream: Arnoldi steps of the last cycle (*stopped = 1
+// when the cycle ended on its own residual estimate or a breakdown, not on the step budget).
+// Timed launches of steps issued after convergence are dropped.
+int finish_cycle(vms_ctx* c, int* stopped = nullptr) {
     int done = 0;
     const int k = std::max(0, read_progress(c, c->cycle_gen, &done));
+    if (stopped) *stopped = done;
     for (size_t i = 0; i + 2 < c->cycle_timed.size(); i += 3)
         if (c->cycle_timed[i] >= k) prof_void(c, (int)c->cycle_timed[i + 1], c->cycle_timed[i + 2]);
     c->cycle_timed.clear();
@@ -1032,7 +1034,7 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     const int max_iters = o->max_iters > 0 ? o->max_iters : 100000;
     const double rtol = o->rtol > 0 ? o->rtol : 1e-8;
     const int refine_max = o->refine_max > 0 ? o->refine_max : 30;
-    const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-5;
+    const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-4;
     int rc;
 
     // preconditioner blocks
@@ -1128,6 +1130,7 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             const double inner_tol = std::max(inner_rtol, 0.3 * tol / rn);
             const float* cycle_r = rr;
             int progress = 0;
+            double qn_prev = 1.0;          // |rr| = 1
             while (iters < max_iters) {
                 if ((rc = run_cycle<float, float>(c, cycle_r, (const float*)c->Minv, d, inner_tol, m,
                                                   max_iters - iters, o->cgs2, s)))
@@ -1137,7 +1140,8 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
                 norm_kernel<float><<<red_grid(n), kBlock, 0, s>>>(n, q, c->red, c->rnorm + 2);
                 double qn = 0.0;
                 if ((rc = read_scalar(c, c->rnorm + 2, &qn, s))) return rc;     // synchronises
-                const int k = finish_cycle(c);
+                int stopped = 0;
+                const int k = finish_cycle(c, &stopped);
                 iters += k;
                 progress += k;
                 inf.restarts++;
@@ -1148,6 +1152,11 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
                     inf.logged++;
                 }
                 if (!(qn > inner_tol) || !std::isfinite(qn)) break;
+                // The FP32 inner residual has a rounding floor near eps32 |A| |d|: when the cycle's own
+                // estimate reached inner_tol but the recomputed residual did not, or a cycle made no
+                // progress, the sweep ends and the FP64 refinement continues from the new iterate.
+                if (stopped || qn > 0.99 * qn_prev) break;
+                qn_prev = qn;
                 cycle_r = q;
             }
             axpy64_kernel<float><<<grid_for(n), kBlock, 0, s>>>(n, rn, d, x);
