@@ -145,7 +145,7 @@ typedef struct {
     double inner_rtol;         /* mixed ctx: FP32 GMRES tolerance per sweep (<= 0: 1e-4); a
                                   sweep also ends when a cycle's own estimate reached it but
                                   the recomputed FP32 residual did not (the FP32 rounding
-                                  floor) or a cycle made no progress                       */
+                                  floor)                                                   */
     int32_t cgs2;              /* nonzero: every basis vector gets a second classical
                                   Gram-Schmidt pass, delayed into the next Arnoldi step so
                                   that each step needs one reduction; 0: one pass (each
