@@ -40,6 +40,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle sample (0: every element of the workload)")
+    ap.add_argument("--study", choices=["bfs"], default=None,
+                    help="bfs: the learned-correction study on the backward-facing step (train on the steady "
+                         "Re 400..800 continuation of bfs8, compare with block-Jacobi over the transient bfs16 "
+                         "run); prints its own JSON report instead of the bench line")
+    ap.add_argument("--study-steps", type=int, default=2, help="bfs16 time steps in --study bfs")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter passes: GMRES on the workload's mixed-precision "
                          "tangent capped at COUNTER_ITERS Arnoldi steps, then a COPY_MIB device-to-device copy "
@@ -64,6 +69,9 @@ def main():
     from workloads import build_workload
 
     dev = "cuda:0"
+    if args.study == "bfs":
+        bfs_study(B, driver, learned, build_workload, dev, args.study_steps)
+        return
     cfg, mesh, u0, beta0, bc = build_workload(args.workload)
     if args.counters:
         counter_run(B, cfg, mesh, u0, beta0, bc, dev)
@@ -209,6 +217,100 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bfs_study(B, driver, learned, build_workload, dev, steps):
+    """Learned correction on the backward-facing step.  Training data: the Newton systems of the
+    steady bfs8 continuation Re 400 -> 800 and of the first backward-Euler steps of bfs8 at
+    Re 800, dt 0.05 from an impulsive start (mixed, GMRES(50) + block-Jacobi, restart residuals
+    logged); the last transient system is held out for checkpoint selection.  Evaluation: the
+    transient bfs16 run (Re 800, dt 0.05, impulsive start) for `steps` steps, once with
+    block-Jacobi and once with the learned correction, Newton to 1e-8 per step; GMRES
+    iterations and wall time per step."""
+    import numpy as np
+    import torch
+    report = {"study": "bfs"}
+    t0 = time.perf_counter()
+    cfg8, m8, u8, b8, bc8 = build_workload("bfs8")
+    ctx8 = B.Context(torch.from_numpy(m8.xyz).to(dev), torch.from_numpy(m8.tets).to(dev),
+                     torch.from_numpy(bc8.dofs).to(dev), precision=B.VMS_MIXED)
+    lin8 = B.solve_opts(restart=50, rtol=1e-4, max_iters=20000)
+    u = torch.from_numpy(u8).to(dev)
+    beta = torch.from_numpy(b8).to(dev)
+    data, cont = [], []
+    for re in cfg8.re_sweep:
+        tr = time.perf_counter()
+        d, hist = learned.collect_newton_data(ctx8, u, beta, re, tol=cfg8.newton_tol, max_newton=12, lin=lin8,
+                                              per_step=32, allow_noconv=True)
+        converged = hist[-1] <= cfg8.newton_tol * hist[0]
+        cont.append({"re": re, "newton_steps": len(d), "converged": bool(converged),
+                     "seconds": round(time.perf_counter() - tr, 2),
+                     "rnorms": [float(f"{r:.3e}") for r in hist]})
+        log(f"bfs8 steady Re {re:g}: {cont[-1]}")
+        data += d
+        if not converged:
+            break
+    # transient bfs8 systems, impulsive start
+    u = torch.from_numpy(u8).to(dev)
+    beta = torch.from_numpy(b8).to(dev)
+    u_prev = torch.empty_like(u)
+    trans = []
+    for n in range(2):
+        tr = time.perf_counter()
+        u_prev.copy_(u)
+        d, hist = learned.collect_newton_data(ctx8, u, beta, 800.0, 0.05, u_prev, tol=1e-8, max_newton=8,
+                                              lin=lin8, per_step=32, allow_noconv=True)
+        trans += d
+        log(f"bfs8 transient step {n}: Newton {len(d)}, {time.perf_counter() - tr:.1f} s")
+    report["bfs8"] = {"n_elems": m8.n_elems, "n_nodes": m8.n_nodes, "continuation": cont,
+                      "transient_systems": len(trans), "training_systems": len(data) + len(trans) - 1,
+                      "seconds": time.perf_counter() - t0}
+    t1 = time.perf_counter()
+    train_set = data + trans[:-1]
+    val = [(A, S[0].contiguous()) for A, S in trans[-1:]]
+    weights, train = learned.train_validated(ctx8, train_set, val, steps=300, lr=3e-4, check_every=25)
+    train["seconds"] = time.perf_counter() - t1
+    report["training"] = train
+    log(f"training: {train}")
+    del data, trans, train_set, val
+    ctx8.close()
+    torch.cuda.empty_cache()
+
+    cfg, m, u0, beta0, bc = build_workload("bfs16")
+    ctx = B.Context(torch.from_numpy(m.xyz).to(dev), torch.from_numpy(m.tets).to(dev),
+                    torch.from_numpy(bc.dofs).to(dev), precision=B.VMS_MIXED)
+    dofs = torch.from_numpy(bc.dofs.astype(np.int64)).to(dev)
+    vals = torch.from_numpy(bc.values).to(dev)
+    report["bfs16"] = {"n_elems": m.n_elems, "n_nodes": m.n_nodes, "re": cfg.re, "dt": cfg.dt, "steps": steps}
+    for name, w in (("block_jacobi", None), ("learned", weights)):
+        if name == "learned" and w is None:
+            report["bfs16"][name] = "validation selected plain block-Jacobi"
+            continue
+        u = torch.from_numpy(u0).to(dev)
+        beta = torch.from_numpy(beta0).to(dev)
+        u_prev = torch.empty_like(u)
+        per_step = []
+        for n in range(steps):
+            u_prev.copy_(u)
+            driver.set_dirichlet(u, dofs, vals)
+            lin = B.solve_opts(restart=50, rtol=1e-9, max_iters=400000,
+                               pc=B.VMS_PC_LEARNED if w is not None else B.VMS_PC_BLOCK_JACOBI, pc_weights=w)
+            r = driver.newton_solve(ctx, u, beta, cfg.re, cfg.dt, u_prev, None, tol=cfg.newton_tol, lin=lin,
+                                    forcing="ew")
+            per_step.append({"seconds": r.seconds, "newton": len(r.rnorms) - 1,
+                             "gmres": int(sum(d["iters"] for d in r.lin)),
+                             "fell_back": int(sum(d["fell_back_to_bj"] for d in r.lin))})
+            log(f"bfs16 {name} step {n}: {per_step[-1]}")
+        secs = [p["seconds"] for p in per_step]
+        report["bfs16"][name] = {
+            "gmres_iters": int(sum(p["gmres"] for p in per_step)),
+            "newton_steps": int(sum(p["newton"] for p in per_step)),
+            "seconds": float(sum(secs)), "seconds_per_step_mean": float(np.mean(secs)),
+            "seconds_per_step_max": float(np.max(secs)),
+            "fell_back_to_bj": int(sum(p["fell_back"] for p in per_step)),
+            "gmres_per_step": [p["gmres"] for p in per_step]}
+        log(f"bfs16 {name}: " + json.dumps({k: v for k, v in report["bfs16"][name].items() if k != "gmres_per_step"}))
+    print(json.dumps(report), flush=True)
 
 
 def spmv_source_hash():

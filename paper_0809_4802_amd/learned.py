@@ -52,11 +52,13 @@ def train(ctx: B.Context, data, steps=200, lr=1e-3, batch=8, seed=1, weights=Non
 
 
 def collect_newton_data(ctx: B.Context, u, beta, Re, dt=0.0, u_prev=None, body=None, tol=1e-8, max_newton=20,
-                        lin: B.SolveOpts | None = None, per_step=32):
+                        lin: B.SolveOpts | None = None, per_step=32, allow_noconv=False):
     """Runs Newton-Schur (assemble, GMRES with restart-residual logging, recovery/update)
     through the C entry points and keeps, for every Newton step, a copy of the condensed
     tangent and the logged residuals.  u and beta advance in place.  Returns the list of
-    (bsr_vals, samples) and the residual history."""
+    (bsr_vals, samples) and the residual history.  allow_noconv: a linear solve that misses
+    its tolerance within lin.max_iters still contributes its system and residuals, and
+    Newton continues from its iterate."""
     lin = lin if lin is not None else B.solve_opts()
     data = []
     rn0 = None
@@ -73,7 +75,7 @@ def collect_newton_data(ctx: B.Context, u, beta, Re, dt=0.0, u_prev=None, body=N
         lin.log_residuals = log.data_ptr()
         lin.log_max = per_step
         du = ctx.new_vec()
-        _, info = B.vms_gmres_solve(ctx, A, rhs, du, lin)
+        _, info = B.vms_gmres_solve(ctx, A, rhs, du, lin, allow_noconv=allow_noconv)
         lin.log_residuals = None
         lin.log_max = 0
         data.append((A, log[:max(1, info.logged)].contiguous()))
