@@ -101,10 +101,11 @@ def train_validated(ctx: B.Context, data, val, steps=200, lr=3e-4, batch=8, seed
     held-out systems `val` (list of (bsr_vals, rhs)); plain block-Jacobi (the zero output
     layer) is one of the candidates, so the result is never worse on the validation set.
     Returns (weights or None for block-Jacobi, report)."""
-    def score(w):
-        return sum(gmres_iterations(ctx, A, b, w, rtol=val_rtol) for A, b in val)
+    def score(w, cap=20000):
+        return sum(gmres_iterations(ctx, A, b, w, rtol=val_rtol, max_iters=cap) for A, b in val)
 
     base = score(None)
+    cap = max(100, 2 * base // max(1, len(val)))      # a checkpoint slower than 2x block-Jacobi is out
     best_w, best = None, base
     report = {"val_iters_bj": base, "checkpoints": []}
     rng = np.random.default_rng(seed)
@@ -117,10 +118,24 @@ def train_validated(ctx: B.Context, data, val, steps=200, lr=3e-4, batch=8, seed
         idx = torch.from_numpy(rng.choice(S.shape[0], size=k, replace=False)).to(ctx.device)
         B.vms_pc_train_step(ctx, A, S.index_select(0, idx).contiguous(), w, state, step, lr, None, loss)
         if step % check_every == 0:
-            s = score(w)
+            s = score(w, cap)
             report["checkpoints"].append({"step": step, "loss": float(loss.item()), "val_iters": s})
             if s < best:
                 best, best_w = s, w.clone()
     report["selected"] = "bj" if best_w is None else "learned"
     report["val_iters_selected"] = best
     return best_w, report
+
+
+def train_select(ctx: B.Context, data, val, seeds=(1, 2, 3), **kw):
+    """train_validated for each seed; keeps the weights with the fewest validation iterations.
+    Returns (weights or None, report with one entry per seed)."""
+    best_w, best, reports = None, None, []
+    for seed in seeds:
+        w, rep = train_validated(ctx, data, val, seed=seed, **kw)
+        rep["seed"] = seed
+        reports.append(rep)
+        if best is None or rep["val_iters_selected"] < best:
+            best, best_w = rep["val_iters_selected"], w
+    return best_w, {"val_iters_bj": reports[0]["val_iters_bj"], "val_iters_selected": best,
+                    "selected": "bj" if best_w is None else "learned", "runs": reports}
