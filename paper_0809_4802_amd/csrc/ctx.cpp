@@ -296,14 +296,19 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
             }
             int64_t r1 = r0 + 1;
             while (r1 < nn && r1 - r0 < kTileNodes && rowptr[r1 + 1] - rowptr[r0] <= max_blocks) ++r1;
+            // Items round-robin over the owned vertices (the r-th element of every owned node, then
+            // the (r+1)-th, ...): a tile has at most 64 nodes, so the 64 lanes of a wave mostly own
+            // different vertices and their LDS row additions do not collide on an address.
             list.clear();
-            for (int64_t i = r0; i < r1; ++i)
-                for (int32_t k = n2e_ptr[i]; k < n2e_ptr[i + 1]; ++k) {
-                    const int32_t e = n2e[k];
+            int32_t rounds = 0;
+            for (int64_t i = r0; i < r1; ++i) rounds = std::max(rounds, n2e_ptr[i + 1] - n2e_ptr[i]);
+            for (int32_t r = 0; r < rounds; ++r)
+                for (int64_t i = r0; i < r1; ++i) {
+                    if (n2e_ptr[i] + r >= n2e_ptr[i + 1]) continue;
+                    const int32_t e = n2e[n2e_ptr[i] + r];
                     for (int a = 0; a < 4; ++a)
                         if (tets[4 * (int64_t)e + a] == i) list.emplace_back(e, a);
                 }
-            std::sort(list.begin(), list.end());   // element order: neighbouring lanes hit different rows
             const int32_t b0 = rowptr[r0];
             for (auto& it : list) {
                 const int32_t e = it.first, a = it.second;
