@@ -77,6 +77,8 @@ typedef struct {
                                   tangent blocks, block-CSR values and inner
                                   GMRES; FP64 K_ff^-1, residuals, refinement. */
     int32_t max_restart;       /* Krylov basis allocated (<= 0: 50)          */
+    int32_t full_system;       /* 1: also build the uncondensed system used by
+                                  vms_full_assemble / vms_full_newton_step   */
 } vms_create_opts;
 
 /* Builds the 4x4 block-CSR pattern of the condensed system (one block per
@@ -200,6 +202,37 @@ typedef struct {
 int vms_newton_step(vms_ctx* ctx, double* u, double* beta, const double* u_prev, double Re,
                     double dt, const double* body, const vms_newton_opts* opts,
                     vms_newton_info* info, hipStream_t stream);
+
+/* ---- uncondensed Newton-Raphson (the baseline the paper compares against) --
+ * Section 4.2 states the full Newton system over the coarse and fine unknowns
+ * together (Eq. NewtonUpdate2); Section 5 condenses it.  These calls solve it
+ * without condensation.  The system is a 4x4 block-CSR system over
+ * n_nodes + n_elems block rows: block row i < n_nodes holds the dofs
+ * (vx, vy, vz, p) of node i; block row n_nodes + e holds the three fine dofs
+ * (beta_x, beta_y, beta_z) of element e and one unused slot (identity row and
+ * column, zero rhs).  Blocks: node-node (K_cc summed over elements),
+ * node-element (K_cf, fourth column 0), element-node (K_fc, fourth row 0) and
+ * the element diagonal (K_ff, unit fourth diagonal).  Dirichlet rows and
+ * columns are replaced by the identity.  Needs vms_create_opts.full_system. */
+
+/* Read-only device views of the uncondensed pattern (see vms_bsr_info). */
+int vms_full_info(const vms_ctx* ctx, int64_t* nb, int32_t* n_rows, const int32_t** rowptr,
+                  const int32_t** colidx);
+
+/* Uncondensed tangent into bsr_vals (FP64 ctx: double, mixed ctx: float)
+ * [nb][16], rhs = -R (double [n_nodes + n_elems][4]), rnorm as in
+ * vms_condense_assemble.  Not synchronising. */
+int vms_full_assemble(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta,
+                      double Re, double dt, const double* body, void* bsr_vals, double* rhs,
+                      double* rnorm, hipStream_t stream);
+
+/* One Newton-Raphson iteration on the uncondensed system: assemble, solve with
+ * the context's GMRES (4x4 block-Jacobi on the block rows above; the learned
+ * correction is not available here), update u and beta in place, evaluate the
+ * new residual.  Synchronising. */
+int vms_full_newton_step(vms_ctx* ctx, double* u, double* beta, const double* u_prev, double Re,
+                         double dt, const double* body, const vms_newton_opts* opts,
+                         vms_newton_info* info, hipStream_t stream);
 
 /* ---- learned block-Jacobi correction ------------------------------------
  * Per node i: features x_i (25 floats) from the condensed tangent,

@@ -282,10 +282,11 @@ def newton_solve(prob: Problem, u, beta, tol=1e-10, max_newton=30, **kw):
     return u, beta, log
 
 
-def full_newton_step(prob: Problem, u, beta):
-    """Brute-force Newton step on the uncondensed system (Eq. NewtonUpdate2):
-    the 19x19 element Jacobians assembled over all 4 n_nodes + 3 n_elems
-    unknowns, Dirichlet rows/columns eliminated, solved by sparse LU."""
+def full_system(prob: Problem, u, beta):
+    """The uncondensed Newton system of Eq. NewtonUpdate2 (Section 4.2): the 19x19 element
+    Jacobians assembled over all 4 n_nodes + 3 n_elems unknowns (coarse dofs first, then the
+    fine dofs of element e at 4 n_nodes + 3 e + i), Dirichlet rows and columns replaced by
+    the identity.  Returns (A [csc], rhs = -R with zeros at Dirichlet dofs)."""
     R, K = prob.element(u, beta)
     nn, ne = prob.n_nodes, prob.n_elems
     nc = 4 * nn
@@ -305,5 +306,13 @@ def full_newton_step(prob: Problem, u, beta):
     rhs = np.zeros(n)
     np.add.at(rhs, dofs.ravel(), -R.ravel())
     rhs[prob.dirichlet_dofs] = 0.0
+    return A, rhs
+
+
+def full_newton_step(prob: Problem, u, beta):
+    """Brute-force Newton step on the uncondensed system (Eq. NewtonUpdate2), solved by
+    sparse LU."""
+    A, rhs = full_system(prob, u, beta)
     d = spla.spsolve(A, rhs)
+    nc = 4 * prob.n_nodes
     return u + d[:nc].reshape(-1, 4), beta + d[nc:].reshape(-1, 3)

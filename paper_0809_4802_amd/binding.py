@@ -32,7 +32,8 @@ PC_NWEIGHTS = PC_NHID * PC_NIN + PC_NHID + PC_NOUT * PC_NHID + PC_NOUT
 
 EXPORTED = ["vms_create", "vms_destroy", "vms_last_error", "vms_bsr_info", "vms_element_tangents",
             "vms_condense_assemble", "vms_residual", "vms_recover_update", "vms_bsr_spmv",
-            "vms_gmres_solve", "vms_newton_step", "vms_pc_features", "vms_pc_blocks",
+            "vms_gmres_solve", "vms_newton_step", "vms_full_info", "vms_full_assemble",
+            "vms_full_newton_step", "vms_pc_features", "vms_pc_blocks",
             "vms_pc_train_step", "vms_profile", "vms_profile_read"]
 PHASES = ["condense", "residual", "recover", "pc_setup", "pc_apply", "spmv", "dots", "update", "fill"]
 
@@ -50,7 +51,7 @@ class MeshDesc(ctypes.Structure):
 
 
 class CreateOpts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("max_restart", ctypes.c_int32)]
+    _fields_ = [("precision", ctypes.c_int), ("max_restart", ctypes.c_int32), ("full_system", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -96,6 +97,11 @@ _sig = {
     "vms_gmres_solve": [_vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _vp],
     "vms_newton_step": [_vp, _vp, _vp, _vp, _d, _d, _vp, ctypes.POINTER(NewtonOpts),
                         ctypes.POINTER(NewtonInfo), _vp],
+    "vms_full_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_i32), ctypes.POINTER(_vp),
+                      ctypes.POINTER(_vp)],
+    "vms_full_assemble": [_vp, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _vp, _vp],
+    "vms_full_newton_step": [_vp, _vp, _vp, _vp, _d, _d, _vp, ctypes.POINTER(NewtonOpts),
+                             ctypes.POINTER(NewtonInfo), _vp],
     "vms_pc_features": [_vp, _vp, _vp, _vp],
     "vms_pc_blocks": [_vp, _vp, _vp, _vp, _vp],
     "vms_pc_train_step": [_vp, _vp, _vp, _i32, _vp, _vp, _i32, ctypes.c_float, _vp, _vp, _vp],
@@ -141,7 +147,8 @@ def _dev(t, dtype, shape=None):
 class Context:
     """Owns a vms_ctx*.  Tensors passed to it must be CUDA (HIP) tensors."""
 
-    def __init__(self, xyz, tets, dirichlet_dofs, precision=VMS_FP64, max_restart=50, stream=None):
+    def __init__(self, xyz, tets, dirichlet_dofs, precision=VMS_FP64, max_restart=50, full_system=False,
+                 stream=None):
         xyz = _dev(xyz, torch.float64).contiguous()
         tets = _dev(tets, torch.int32).contiguous()
         dd = _dev(dirichlet_dofs, torch.int32).contiguous()
@@ -151,7 +158,7 @@ class Context:
         self.dtype = torch.float64 if precision == VMS_FP64 else torch.float32
         desc = MeshDesc(self.n_nodes, self.n_elems, xyz.data_ptr(), tets.data_ptr(), int(dd.numel()),
                         dd.data_ptr() if dd.numel() else None)
-        opts = CreateOpts(precision, max_restart)
+        opts = CreateOpts(precision, max_restart, 1 if full_system else 0)
         h = ctypes.c_void_p()
         _check(_lib.vms_create(ctypes.byref(desc), ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
         self.handle = h
@@ -159,6 +166,11 @@ class Context:
         _check(_lib.vms_bsr_info(h, ctypes.byref(nb), None, None, None, None), h)
         self.nb = int(nb.value)
         self.device = xyz.device
+        self.full_nb = self.full_rows = None
+        if full_system:
+            fnb, frows = ctypes.c_int64(), ctypes.c_int32()
+            _check(_lib.vms_full_info(h, ctypes.byref(fnb), ctypes.byref(frows), None, None), h)
+            self.full_nb, self.full_rows = int(fnb.value), int(frows.value)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -177,6 +189,24 @@ class Context:
 
     def new_vec(self, dtype=torch.float64):
         return torch.zeros((self.n_nodes, 4), dtype=dtype, device=self.device)
+
+    def new_full_bsr(self):
+        return torch.zeros((self.full_nb, 16), dtype=self.dtype, device=self.device)
+
+    def new_full_vec(self):
+        return torch.zeros((self.full_rows, 4), dtype=torch.float64, device=self.device)
+
+    def full_pattern(self):
+        """(rowptr, colidx) of the uncondensed system copied to host numpy arrays."""
+        rp, ci = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(_lib.vms_full_info(self.handle, None, None, ctypes.byref(rp), ctypes.byref(ci)), self.handle)
+        out = []
+        for ptr, n in ((rp, self.full_rows + 1), (ci, self.full_nb)):
+            t = torch.empty(n, dtype=torch.int32, device=self.device)
+            torch.cuda.synchronize()
+            _copy_device(t, ptr.value, n * 4)
+            out.append(t.cpu().numpy())
+        return tuple(out)
 
     def bsr_pattern(self):
         """(rowptr, colidx, diagpos) copied to host numpy arrays."""
@@ -275,6 +305,27 @@ def vms_newton_step(ctx: Context, u, beta, Re, dt=0.0, u_prev=None, body=None, l
     info = NewtonInfo()
     rc = _lib.vms_newton_step(ctx.handle, _ptr(u), _ptr(beta), _ptr(u_prev), float(Re), float(dt), _ptr(body),
                               ctypes.byref(opts), ctypes.byref(info), _stream(stream))
+    _check(rc, ctx.handle)
+    return info
+
+
+def vms_full_assemble(ctx: Context, u, beta, Re, dt=0.0, u_prev=None, body=None, bsr_vals=None, rhs=None,
+                      rnorm=None, stream=None):
+    bsr_vals = ctx.new_full_bsr() if bsr_vals is None else bsr_vals
+    rhs = ctx.new_full_vec() if rhs is None else rhs
+    rnorm = torch.zeros(1, dtype=torch.float64, device=ctx.device) if rnorm is None else rnorm
+    _check(_lib.vms_full_assemble(ctx.handle, _ptr(u), _ptr(u_prev), _ptr(beta), float(Re), float(dt),
+                                  _ptr(body), _ptr(bsr_vals), _ptr(rhs), _ptr(rnorm), _stream(stream)),
+           ctx.handle)
+    return bsr_vals, rhs, rnorm
+
+
+def vms_full_newton_step(ctx: Context, u, beta, Re, dt=0.0, u_prev=None, body=None, lin: SolveOpts = None,
+                         stream=None):
+    opts = NewtonOpts(lin if lin is not None else solve_opts())
+    info = NewtonInfo()
+    rc = _lib.vms_full_newton_step(ctx.handle, _ptr(u), _ptr(beta), _ptr(u_prev), float(Re), float(dt),
+                                   _ptr(body), ctypes.byref(opts), ctypes.byref(info), _stream(stream))
     _check(rc, ctx.handle)
     return info
 

@@ -117,7 +117,12 @@ extern "C" int vms_profile_read(vms_ctx* c, double* ms, int64_t* launches, doubl
 }
 
 static void free_all(vms_ctx* c) {
-    void* ptrs[] = {c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
+    if (c->full) {
+        free_all(c->full);
+        delete c->full;
+        c->full = nullptr;
+    }
+    void* ptrs[] = {c->full_cc, c->full_epos,c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
                     c->tpos, c->tile_node0, c->tile_iptr, c->item_ea, c->item_pos, c->A, c->rhs, c->du, c->rglob, c->rnorm, c->flags,
                     c->V, c->w, c->z, c->d, c->r, c->Minv, c->AP, c->Az, c->x64, c->r64, c->gs, c->red,
                     c->feats, c->hid, c->pblk, c->gblk, c->tvec, c->wgrad, c->fscal};
@@ -157,6 +162,123 @@ static int dev_alloc(vms_ctx* c, P** p, size_t bytes, const char* what) {
             return rc__;           \
         }                          \
     } while (0)
+
+// The uncondensed Newton system as a 4x4 block-CSR system over nn + ne block rows: node rows
+// hold their node-node blocks (the condensed pattern's columns, in the same order) followed by
+// one block per adjacent element; element rows hold the blocks of their four nodes (sorted)
+// followed by the diagonal block.  The solver-only child context gets the pattern, the masks
+// (the unused fourth dof of an element row is masked like a Dirichlet dof) and the Krylov
+// workspaces; the parent keeps the positions of the element contributions.
+static int create_full_system(vms_ctx* c, const std::vector<int32_t>& tets, const std::vector<int32_t>& n2e_ptr,
+                              const std::vector<int32_t>& n2e, const std::vector<int32_t>& rowptr,
+                              const std::vector<int32_t>& colidx, const std::vector<int32_t>& diagpos,
+                              const std::vector<uint8_t>& dmask) {
+    const int64_t nn = c->n_nodes, ne = c->n_elems, nr = nn + ne;
+    const int64_t nbf = c->nb + 9 * ne;
+    if (nbf >= (int64_t)INT32_MAX / 16 || 4 * nr >= (int64_t)INT32_MAX)
+        return set_error(c, VMS_EINVAL, "vms_create: uncondensed system exceeds int32 indexing");
+    std::vector<int32_t> fptr(nr + 1), fcol(nbf), fdiag(nr), fcc(c->nb), fepos(9 * ne);
+    std::vector<uint8_t> fmask(nr);
+    int64_t k = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+        fptr[i] = (int32_t)k;
+        for (int32_t b = rowptr[i]; b < rowptr[i + 1]; ++b) {
+            fcc[b] = (int32_t)k;
+            fcol[k++] = colidx[b];
+        }
+        fdiag[i] = fptr[i] + (diagpos[i] - rowptr[i]);
+        for (int32_t q = n2e_ptr[i]; q < n2e_ptr[i + 1]; ++q) fcol[k++] = (int32_t)(nn + n2e[q]);
+        fmask[i] = dmask[i];
+    }
+    for (int64_t e = 0; e < ne; ++e) {
+        const int64_t row = nn + e;
+        fptr[row] = (int32_t)k;
+        int32_t sorted[4] = {tets[4 * e], tets[4 * e + 1], tets[4 * e + 2], tets[4 * e + 3]};
+        std::sort(sorted, sorted + 4);
+        for (int a = 0; a < 4; ++a) fcol[k + a] = sorted[a];
+        for (int b = 0; b < 4; ++b)
+            fepos[9 * e + 4 + b] = (int32_t)(k + (std::find(sorted, sorted + 4, tets[4 * e + b]) - sorted));
+        fcol[k + 4] = (int32_t)row;
+        fdiag[row] = (int32_t)(k + 4);
+        fepos[9 * e + 8] = (int32_t)(k + 4);
+        k += 5;
+        fmask[row] = 8u;
+    }
+    fptr[nr] = (int32_t)k;
+    if (k != nbf) return set_error(c, VMS_EINVAL, "vms_create: uncondensed pattern size mismatch");
+    // (node a, element e): the position of e in node a's element list
+    for (int64_t i = 0; i < nn; ++i) {
+        const int32_t first = fptr[i] + (rowptr[i + 1] - rowptr[i]);
+        for (int32_t q = n2e_ptr[i]; q < n2e_ptr[i + 1]; ++q) {
+            const int32_t e = n2e[q];
+            for (int a = 0; a < 4; ++a)
+                if (tets[4 * (int64_t)e + a] == i) fepos[9 * (int64_t)e + a] = first + (q - n2e_ptr[i]);
+        }
+    }
+
+    vms_ctx* f = new vms_ctx();
+    c->full = f;
+    f->device = c->device;
+    f->prec = c->prec;
+    f->max_restart = c->max_restart;
+    f->n_nodes = (int32_t)nr;
+    f->full_nodes = c->n_nodes;
+    f->n_elems = 0;
+    f->nb = nbf;
+    const size_t es = elt_size(c);
+    const size_t N = 4 * (size_t)nr;
+    int rc;
+#define FTRY(x)                  \
+    do {                         \
+        if ((rc = (x)) != VMS_OK) { \
+            if (!f->err.empty()) c->err = f->err; \
+            return rc;           \
+        }                        \
+    } while (0)
+    FTRY(dev_alloc(c, &c->full_cc, c->nb * sizeof(int32_t), "alloc full map"));
+    FTRY(dev_alloc(c, &c->full_epos, 9 * ne * sizeof(int32_t), "alloc full map"));
+    FTRY(dev_alloc(f, &f->rowptr, (nr + 1) * sizeof(int32_t), "alloc full rowptr"));
+    FTRY(dev_alloc(f, &f->colidx, nbf * sizeof(int32_t), "alloc full colidx"));
+    FTRY(dev_alloc(f, &f->diagpos, nr * sizeof(int32_t), "alloc full diagpos"));
+    FTRY(dev_alloc(f, &f->dmask, nr, "alloc full dmask"));
+    FTRY(dev_alloc(f, &f->A, nbf * 16 * es, "alloc full A"));
+    FTRY(dev_alloc(f, &f->rhs, N * sizeof(double), "alloc full rhs"));
+    FTRY(dev_alloc(f, &f->du, N * sizeof(double), "alloc full du"));
+    FTRY(dev_alloc(f, &f->rnorm, 8 * sizeof(double), "alloc full rnorm"));
+    FTRY(dev_alloc(f, &f->flags, 8 * sizeof(int32_t), "alloc full flags"));
+    FTRY(dev_alloc(f, &f->V, (size_t)(f->max_restart + 1) * N * es, "alloc full Krylov basis"));
+    FTRY(dev_alloc(f, &f->w, N * es, "alloc full w"));
+    FTRY(dev_alloc(f, &f->z, N * es, "alloc full z"));
+    FTRY(dev_alloc(f, &f->d, N * es, "alloc full d"));
+    FTRY(dev_alloc(f, &f->r, N * es, "alloc full r"));
+    FTRY(dev_alloc(f, &f->Minv, nr * 16 * es, "alloc full Minv"));
+    FTRY(dev_alloc(f, &f->AP, nbf * 16 * es, "alloc full A P"));
+    FTRY(dev_alloc(f, &f->Az, N * es, "alloc full A z"));
+    FTRY(dev_alloc(f, &f->x64, N * sizeof(double), "alloc full x64"));
+    FTRY(dev_alloc(f, &f->r64, N * sizeof(double), "alloc full r64"));
+    FTRY(dev_alloc(f, &f->tvec, 3 * N * sizeof(float), "alloc full tvec"));
+    FTRY(dev_alloc(f, &f->gs, sizeof(GmresState), "alloc full gmres state"));
+    FTRY(dev_alloc(f, &f->red, sizeof(RedScratch), "alloc full reduction scratch"));
+    FTRY(check_hip(f, hipHostMalloc(reinterpret_cast<void**>(&f->progress_host), 64,
+                                    hipHostMallocMapped | hipHostMallocCoherent), "alloc progress word"));
+    FTRY(check_hip(f, hipHostGetDevicePointer(reinterpret_cast<void**>(&f->progress_dev), f->progress_host, 0),
+                   "map progress word"));
+    *f->progress_host = 0;
+    FTRY(check_hip(c, hipMemcpy(c->full_cc, fcc.data(), c->nb * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    FTRY(check_hip(c, hipMemcpy(c->full_epos, fepos.data(), 9 * ne * sizeof(int32_t), hipMemcpyHostToDevice),
+                   "upload"));
+    FTRY(check_hip(f, hipMemcpy(f->rowptr, fptr.data(), (nr + 1) * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    FTRY(check_hip(f, hipMemcpy(f->colidx, fcol.data(), nbf * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    FTRY(check_hip(f, hipMemcpy(f->diagpos, fdiag.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    FTRY(check_hip(f, hipMemcpy(f->dmask, fmask.data(), nr, hipMemcpyHostToDevice), "upload"));
+    FTRY(check_hip(f, hipMemset(f->red, 0, sizeof(RedScratch)), "clear"));
+    FTRY(check_hip(f, hipMemset(f->gs, 0, sizeof(GmresState)), "clear"));
+    FTRY(check_hip(f, hipMemset(f->flags, 0, 8 * sizeof(int32_t)), "clear"));
+    FTRY(check_hip(f, hipMemcpy(&f->gs->progress, &f->progress_dev, sizeof(uint64_t*), hipMemcpyHostToDevice),
+                   "upload"));
+#undef FTRY
+    return VMS_OK;
+}
 
 extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts,
                           hipStream_t stream, vms_ctx** out) {
@@ -403,9 +525,23 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(check_hip(c, hipMemset(c->gs, 0, sizeof(GmresState)), "clear"));
     TRY(check_hip(c, hipMemcpy(&c->gs->progress, &c->progress_dev, sizeof(uint64_t*), hipMemcpyHostToDevice),
                   "upload"));
+    if (opts && opts->full_system)
+        TRY(create_full_system(c, tets, n2e_ptr, n2e, rowptr, colidx, diagpos, dmask));
     TRY(check_hip(c, hipMemset(c->flags, 0, 8 * sizeof(int32_t)), "clear"));
     TRY(check_hip(c, hipDeviceSynchronize(), "sync"));
     *out = c;
+    return VMS_OK;
+}
+
+extern "C" int vms_full_info(const vms_ctx* ctx, int64_t* nb, int32_t* n_rows, const int32_t** rowptr,
+                             const int32_t** colidx) {
+    if (!ctx) return set_error(nullptr, VMS_EINVAL, "vms_full_info: NULL ctx");
+    if (!ctx->full) return set_error(const_cast<vms_ctx*>(ctx), VMS_EINVAL,
+                                     "vms_full_info: context created without full_system");
+    if (nb) *nb = ctx->full->nb;
+    if (n_rows) *n_rows = ctx->full->n_nodes;
+    if (rowptr) *rowptr = ctx->full->rowptr;
+    if (colidx) *colidx = ctx->full->colidx;
     return VMS_OK;
 }
 

@@ -323,6 +323,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // come precomputed from the host.
 //   CONDENSE = true : K* into Aval, -R* into rhs, R_cp into rglob, |R_f|^2 into slots
 //   CONDENSE = false: R_cp into rglob, |R_f|^2 into slots (residual only)
+//   SCHUR = false (with CONDENSE): the coarse blocks without condensation, K_cc into Aval and
+//   -R_cp into rhs (the node-node part of the uncondensed system)
 constexpr int kTileThreads = 512;
 
 struct TileArgs {
@@ -334,7 +336,7 @@ struct TileArgs {
     const int32_t* __restrict__ diagpos;
 };
 
-template <typename T, typename TACC, bool CONDENSE>
+template <typename T, typename TACC, bool CONDENSE, bool SCHUR = true>
 __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, TileArgs ta, T* __restrict__ Aval,
                                                                double* __restrict__ rhs, double* __restrict__ rglob,
                                                                double* __restrict__ red_slots) {
@@ -474,7 +476,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
         const int la = nid[a] - n0;
         double Kcf[4][3];
         double Ki[3][3];
-        if (CONDENSE) {
+        if (CONDENSE && SCHUR) {
             const double dk = 2.0 * nu * Kb - 0.5 * Cm * th;
             double Kff[3][3];
 #pragma unroll
@@ -516,19 +518,23 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
                 const double rs = Rc[r] - (Kcf[r][0] * zf[0] + Kcf[r][1] * zf[1] + Kcf[r][2] * zf[2]);
                 if (!(dma & (1u << r))) atomic_add(&rr[4 * la + r], -rs);
             }
+        } else if (CONDENSE) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (!(dma & (1u << r))) atomic_add(&rr[4 * la + r], -Rc[r]);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             if (!(dma & (1u << r))) atomic_add(&rg[4 * la + r], Rc[r]);
         if (!CONDENSE) continue;
 
-        // Y(a) = K_cf(a) K_ff^-1 (FP64 product, kept in T)
+        // Y(a) = K_cf(a) K_ff^-1 (FP64 product, kept in T); zero without condensation
         T Y[4][3];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                Y[r][j] = T(Kcf[r][0] * Ki[0][j] + Kcf[r][1] * Ki[1][j] + Kcf[r][2] * Ki[2][j]);
+                Y[r][j] = SCHUR ? T(Kcf[r][0] * Ki[0][j] + Kcf[r][1] * Ki[1][j] + Kcf[r][2] * Ki[2][j]) : T(0);
         T keep_r[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) keep_r[r] = (dma & (1u << r)) ? T(0) : T(1);
@@ -796,6 +802,121 @@ hipError_t tile_kernels_configure(vms_ctx* c) {
     return e;
 }
 
+// Uncondensed system, element part (one lane per element): the coupling blocks K_cf(a)
+// (node a's row, the element's column; fourth column 0), K_fc(b) (the element's row, node b's
+// column; fourth row 0) and K_ff (element diagonal, unit fourth diagonal) written to their
+// unique positions, Dirichlet rows and columns zeroed; the element's rhs rows -R_f.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void full_element_kernel(ElemArgs args, int n_nodes,
+                                                              const int32_t* __restrict__ epos,
+                                                              T* __restrict__ vals, double* __restrict__ rhs) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= args.n_elems) return;
+    Elem E;
+    if (!load_element(args, e, E)) {
+        atomicMin(&args.flags[0], e);
+        return;
+    }
+    const double nu = args.nu, inv_dt = E.transient ? args.inv_dt : 0.0;
+    const int nid[4] = {E.t.x, E.t.y, E.t.z, E.t.w};
+    uint32_t dm[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) dm[a] = args.dmask[nid[a]];
+    const int32_t* ep = epos + 9 * (size_t)e;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        T Kcf[4][3];
+        coarse_fine_block<T>(E, a, Kcf);
+        T* dst = vals + (size_t)ep[a] * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool keep = !(dm[a] & (1u << r));
+#pragma unroll
+            for (int q = 0; q < 3; ++q) dst[4 * r + q] = keep ? Kcf[r][q] : T(0);
+            dst[4 * r + 3] = T(0);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        T Kfc[3][4];
+        fine_coarse_block<T>(E, b, inv_dt, Kfc);
+        T* dst = vals + (size_t)ep[4 + b] * 16;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[4 * i + q] = (dm[b] & (1u << q)) ? T(0) : Kfc[i][q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[12 + q] = T(0);
+    }
+    double Ki[3][3], Kff[3][3];
+    fine_block_inverse(E, nu, Ki, Kff);
+    T* dst = vals + (size_t)ep[8] * 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[4 * i + q] = (i < 3 && q < 3) ? T(Kff[i][q]) : T(i == q ? 1 : 0);
+    double Rf[3];
+    fine_residual(E, nu, inv_dt, Rf);
+    double* rr = rhs + 4 * ((size_t)n_nodes + e);
+    rr[0] = -Rf[0];
+    rr[1] = -Rf[1];
+    rr[2] = -Rf[2];
+    rr[3] = 0.0;
+}
+
+// Node-node blocks (condensed pattern) and node rhs rows into the uncondensed system.
+template <typename T>
+__global__ void full_copy_kernel(int64_t nb, int n4, const int32_t* __restrict__ cc, const T* __restrict__ src,
+                                 T* __restrict__ dst, const double* __restrict__ rsrc, double* __restrict__ rdst) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < nb * 16) dst[(size_t)cc[i >> 4] * 16 + (i & 15)] = src[i];
+    if (i < n4) rdst[i] = rsrc[i];
+}
+
+// u += dx (node rows), beta += dx (element rows, first three entries).
+__global__ void full_update_kernel(int n_nodes, int n_elems, const double* __restrict__ dx, double* __restrict__ u,
+                                   double* __restrict__ beta) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < 4 * (int64_t)n_nodes) u[i] += dx[i];
+    if (i < 3 * (int64_t)n_elems) {
+        const int64_t e = i / 3, q = i - 3 * e;
+        beta[i] += dx[4 * ((int64_t)n_nodes + e) + q];
+    }
+}
+
+int launch_full_assemble(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
+                         double inv_dt, const double* body, void* vals, double* rhs, hipStream_t s) {
+    int rc;
+    if ((rc = launch_fill(slots_of(c), 64 * 8 * sizeof(double), s))) return rc;
+    flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
+    ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
+    const int64_t nb16 = c->nb * 16;
+    const int n4 = 4 * c->n_nodes;
+    const int gcopy = (int)((std::max<int64_t>(nb16, n4) + kBlock - 1) / kBlock);
+    if (c->prec == VMS_FP64) {
+        tile_kernel<double, double, true, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(
+            a, tile_args(c), (double*)c->A, c->rhs, c->rglob, slots_of(c));
+        full_element_kernel<double><<<grid_for(c->n_elems), kBlock, 0, s>>>(a, c->n_nodes, c->full_epos,
+                                                                            (double*)vals, rhs);
+        full_copy_kernel<double><<<gcopy, kBlock, 0, s>>>(c->nb, n4, c->full_cc, (const double*)c->A,
+                                                          (double*)vals, c->rhs, rhs);
+    } else {
+        tile_kernel<float, MixedAcc, true, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(
+            a, tile_args(c), (float*)c->A, c->rhs, c->rglob, slots_of(c));
+        full_element_kernel<float><<<grid_for(c->n_elems), kBlock, 0, s>>>(a, c->n_nodes, c->full_epos,
+                                                                          (float*)vals, rhs);
+        full_copy_kernel<float><<<gcopy, kBlock, 0, s>>>(c->nb, n4, c->full_cc, (const float*)c->A, (float*)vals,
+                                                         c->rhs, rhs);
+    }
+    return check_hip(c, hipGetLastError(), "full assemble launch");
+}
+
+int launch_full_update(vms_ctx* c, const double* dx, double* u, double* beta, hipStream_t s) {
+    const int64_t n = std::max<int64_t>(4 * (int64_t)c->n_nodes, 3 * (int64_t)c->n_elems);
+    full_update_kernel<<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, c->n_elems, dx, u, beta);
+    return check_hip(c, hipGetLastError(), "full update launch");
+}
+
 int launch_condense(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
                     double inv_dt, const double* body, void* A, double* rhs, double* rglob,
                     double* /*red_acc*/, hipStream_t s) {
@@ -893,6 +1014,20 @@ extern "C" int vms_condense_assemble(vms_ctx* c, const double* u, const double* 
     if (!bsr_vals || !rhs) return set_error(c, VMS_EINVAL, "vms_condense_assemble: NULL output");
     rc = launch_condense(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body,
                          bsr_vals, rhs, c->rglob, nullptr, s);
+    if (rc) return rc;
+    if (rnorm) return launch_norm_finalize(c, c->rglob, nullptr, rnorm, s);
+    return VMS_OK;
+}
+
+extern "C" int vms_full_assemble(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double Re,
+                                 double dt, const double* body, void* bsr_vals, double* rhs, double* rnorm,
+                                 hipStream_t s) {
+    int rc = check_state_args(c, u, beta, Re, dt, u_prev, "vms_full_assemble");
+    if (rc) return rc;
+    if (!c->full) return set_error(c, VMS_EINVAL, "vms_full_assemble: context created without full_system");
+    if (!bsr_vals || !rhs) return set_error(c, VMS_EINVAL, "vms_full_assemble: NULL output");
+    rc = launch_full_assemble(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body,
+                              bsr_vals, rhs, s);
     if (rc) return rc;
     if (rnorm) return launch_norm_finalize(c, c->rglob, nullptr, rnorm, s);
     return VMS_OK;

@@ -125,18 +125,16 @@ inline int spmv_grid(int n_rows) { return (int)(((int64_t)kSpmvLanes * n_rows + 
 // Inverse of each 4x4 diagonal block in FP64 (Gauss-Jordan, partial pivoting),
 // stored in the preconditioner precision.  A singular block is replaced by the
 // identity and counted in flags[2].
-template <typename TA, typename TM>
-__global__ void bj_setup_kernel(int n, const int32_t* __restrict__ diagpos, const TA* __restrict__ A,
-                                TM* __restrict__ Minv, int32_t* flags) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const TA* D = A + (size_t)diagpos[i] * 16;
+// Inverts the FP64 4x4 block D into out (precision TM); a singular block becomes the
+// identity and is counted in flags[2].
+template <typename TM>
+__device__ void invert_block_store(const double (&D)[4][4], TM* __restrict__ out, int32_t* flags) {
     double m[4][8];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            m[r][c] = double(D[r * 4 + c]);
+            m[r][c] = D[r][c];
             m[r][4 + c] = (r == c) ? 1.0 : 0.0;
         }
     bool ok = true;
@@ -173,12 +171,78 @@ __global__ void bj_setup_kernel(int n, const int32_t* __restrict__ diagpos, cons
             for (int c = 0; c < 8; ++c) m[r][c] -= f * m[col][c];
         }
     }
-    TM* out = Minv + (size_t)i * 16;
     if (!ok) atomicAdd(&flags[2], 1);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) out[r * 4 + c] = ok ? TM(m[r][4 + c]) : TM(r == c ? 1 : 0);
+}
+
+template <typename TA, typename TM>
+__global__ void bj_setup_kernel(int n, const int32_t* __restrict__ diagpos, const TA* __restrict__ A,
+                                TM* __restrict__ Minv, int32_t* flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const TA* Dp = A + (size_t)diagpos[i] * 16;
+    double D[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) D[r][c] = double(Dp[r * 4 + c]);
+    invert_block_store<TM>(D, Minv + (size_t)i * 16, flags);
+}
+
+// Uncondensed system (node rows 0..nn, element rows after them; each element row holds the
+// element's K_fc blocks, its K_ff block padded to 4x4 and nothing else).  The node diagonal
+// blocks of that system have a zero pressure-pressure entry, so their plain inverse is no
+// preconditioner.  Node row i instead gets the inverse of the diagonal block of the Schur
+// complement, K_cc(i,i) - sum_e K_cf(i,e) K_ff(e)^-1 K_fc(e,i) (Section 5), formed from the
+// assembled blocks and the element rows' inverses already in Minv.
+template <typename TA, typename TM>
+__global__ void schur_diag_pc_kernel(int nn, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                     const int32_t* __restrict__ diagpos, const TA* __restrict__ A,
+                                     TM* __restrict__ Minv, int32_t* flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    double D[4][4];
+    {
+        const TA* Dp = A + (size_t)diagpos[i] * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) D[r][c] = double(Dp[r * 4 + c]);
+    }
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const int e = colidx[k];
+        if (e < nn) continue;
+        int kf = -1;                                   // block (e, i) in element row e
+        for (int q = rowptr[e]; q < rowptr[e + 1]; ++q)
+            if (colidx[q] == i) kf = q;
+        if (kf < 0) continue;
+        const TA* Cf = A + (size_t)k * 16;
+        const TA* Fc = A + (size_t)kf * 16;
+        const TM* P = Minv + (size_t)e * 16;
+        double W[4][4];                                // K_ff^-1 K_fc (padded)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) t += double(P[r * 4 + q]) * double(Fc[q * 4 + c]);
+                W[r][c] = t;
+            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) t += double(Cf[r * 4 + q]) * W[q][c];
+                D[r][c] -= t;
+            }
+    }
+    invert_block_store<TM>(D, Minv + (size_t)i * 16, flags);
 }
 
 // ------------------------------------------------------------------------ reductions
@@ -519,8 +583,10 @@ constexpr int kSlotGroups = kRedThreads / kSlotLanes;       // slots per round
 constexpr int kSlotRounds = (2 * (kMaxRestart + 2) + kSlotGroups - 1) / kSlotGroups;
 static_assert(kDotChunks <= 64, "a slot has at most 64 chunks");
 
+// eps_dot: relative accuracy of the dot products (precision of the stored vectors); a squared
+// norm that cancels below eps_dot times its input is a numerical breakdown.
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks, const double* __restrict__ part,
-                                                             GmresState* gs, int last) {
+                                                             GmresState* gs, int last, double eps_dot) {
     constexpr int ld = kMaxRestart + 1;
     const int lh = j + 1;                                  // rows 0 .. j of H in LDS
     __shared__ double sums[2 * (kMaxRestart + 2)];
@@ -599,7 +665,8 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks,
 #pragma unroll
         for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
         if (lane == 0) {
-            sc[0] = j > 0 ? sqrt(fmax(sums[2 * j] - a[0], 0.0)) : 1.0;     // rho
+            const double r2 = sums[2 * j] - a[0];
+            sc[0] = j > 0 ? (r2 > eps_dot * sums[2 * j] ? sqrt(r2) : 0.0) : 1.0;     // rho
             sc[1] = a[1];
             sc[2] = a[2];
             sc[3] = a[3];
@@ -660,7 +727,8 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks,
     if (tid == 0) {
         const double cc = sc[3] + cj * cj;                 // |c|^2
         const double pw = sums[2 * j + 3] - sc[4] - cj * svl[j];
-        const double hh = sqrt(fmax(sums[2 * j + 2] - cc, 0.0)) / rho;
+        const double h2 = sums[2 * j + 2] - cc;
+        const double hh = h2 > eps_dot * sums[2 * j + 2] ? sqrt(h2) / rho : 0.0;
         gs->H[(size_t)j * ld + j + 1] = hh;
         gs->rho = rho;
         gs->cj = cj;
@@ -911,6 +979,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 3.0 * vb;
     const int nch = std::max(1, std::min(kDotChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
     double* part = c->red->partial;
+    const double eps_dot = sizeof(T) == 8 ? 1e-14 : 1e-6;
     // timed launches per step, so that steps issued after convergence (their kernels return
     // at once) can be dropped from the phase timers
     auto keep = [&](int jj, const PhaseScope& ph) {
@@ -938,7 +1007,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
             dots_kernel<T><<<dim3(nch, j + 2), kDotThreads, 0, s>>>(c->n_nodes, j, V, w, c->dmask, part, c->gs);
             keep(j, ph);
         }
-        reduce_kernel<<<1, kRedThreads, 0, s>>>(j, nch, part, c->gs, 0);
+        reduce_kernel<<<1, kRedThreads, 0, s>>>(j, nch, part, c->gs, 0, eps_dot);
         {
             PhaseScope ph(c, VMS_PH_UPDATE, (j + 4) * vb, s);
             update_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, j, V, w, c->gs);
@@ -947,7 +1016,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     }
     // the second pass of the last vector completes the last column
     dots_kernel<T><<<dim3(nch, steps + 2), kDotThreads, 0, s>>>(c->n_nodes, steps, V, w, c->dmask, part, c->gs);
-    reduce_kernel<<<1, kRedThreads, 0, s>>>(steps, nch, part, c->gs, 1);
+    reduce_kernel<<<1, kRedThreads, 0, s>>>(steps, nch, part, c->gs, 1, eps_dot);
     // y = R^{-1} g on the device
     backsub_kernel<<<1, kBlock, 0, s>>>(c->gs);
     combine_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, V, c->gs, z);
@@ -1007,6 +1076,21 @@ int launch_bj_setup(vms_ctx* c, const void* A, void* Minv, hipStream_t s) {
     return check_hip(c, hipGetLastError(), "bj setup launch");
 }
 
+// Block-Jacobi for the uncondensed system: K_ff^-1 on element rows, the Schur diagonal
+// inverse on node rows.
+static int launch_full_pc_setup(vms_ctx* c, const void* A, void* Minv, hipStream_t s) {
+    int rc = launch_bj_setup(c, A, Minv, s);
+    if (rc) return rc;
+    const int nn = c->full_nodes;
+    if (c->prec == VMS_FP64)
+        schur_diag_pc_kernel<double, double><<<grid_for(nn), kBlock, 0, s>>>(
+            nn, c->rowptr, c->colidx, c->diagpos, (const double*)A, (double*)Minv, c->flags);
+    else
+        schur_diag_pc_kernel<float, float><<<grid_for(nn), kBlock, 0, s>>>(
+            nn, c->rowptr, c->colidx, c->diagpos, (const float*)A, (float*)Minv, c->flags);
+    return check_hip(c, hipGetLastError(), "schur diagonal setup launch");
+}
+
 // A P and A z for the Arnoldi steps (after the preconditioner blocks are set).
 int launch_ap_setup(vms_ctx* c, const void* A, hipStream_t s) {
     const double es = elt_size(c);
@@ -1059,6 +1143,8 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
         } else if (rc) {
             return rc;
         }
+    } else if (c->full_nodes > 0) {
+        if ((rc = launch_full_pc_setup(c, A, c->Minv, s))) return rc;
     } else {
         if ((rc = launch_bj_setup(c, A, c->Minv, s))) return rc;
     }

@@ -146,6 +146,14 @@ struct vms_ctx {
     uint32_t cycle_gen = 0;
     std::vector<int64_t> cycle_timed;    // timed launches of the cycle: (step, slot, generation)
 
+    // uncondensed system (vms_create_opts.full_system): a solver-only child context over the
+    // n_nodes + n_elems block rows (its n_nodes field counts block rows), and the positions of
+    // the element contributions in its pattern
+    vms_ctx* full = nullptr;
+    int32_t* full_cc = nullptr;      // [nb] position of condensed-pattern block k in the full pattern
+    int32_t* full_epos = nullptr;    // [n_elems][9]: (node a, elem) a = 0..3, (elem, node b) b = 0..3, (elem, elem)
+    int32_t full_nodes = 0;          // in the child: number of node block rows (0 in other contexts)
+
     // learned preconditioner (device, float)
     float* feats = nullptr;          // [n_nodes][25]
     float* hid = nullptr;            // [n_nodes][64]
@@ -210,6 +218,11 @@ int launch_residual(vms_ctx* ctx, const double* u, const double* u_prev, const d
 int launch_norm_finalize(vms_ctx* ctx, const double* rglob, const double* red_acc, double* out,
                          hipStream_t s);
 int check_element_flags(vms_ctx* ctx, hipStream_t s);
+// Uncondensed system (ctx->full must exist): assembly into vals / rhs of the full pattern, and
+// the Newton update from its solution dx.
+int launch_full_assemble(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta, double nu,
+                         double inv_dt, const double* body, void* vals, double* rhs, hipStream_t s);
+int launch_full_update(vms_ctx* ctx, const double* dx, double* u, double* beta, hipStream_t s);
 
 // linear algebra (krylov.hip)
 int launch_fill(void* p, size_t bytes, hipStream_t s);
