@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle sample (0: every element of the workload)")
-    ap.add_argument("--study", choices=["bfs"], default=None,
+    ap.add_argument("--study", choices=["bfs", "nr"], default=None,
                     help="bfs: the learned-correction study on the backward-facing step (train on the steady "
                          "Re 400..800 continuation of bfs8, compare with block-Jacobi over the transient bfs16 "
                          "run); prints its own JSON report instead of the bench line")
@@ -71,6 +71,9 @@ def main():
     dev = "cuda:0"
     if args.study == "bfs":
         bfs_study(B, driver, learned, build_workload, dev, args.study_steps)
+        return
+    if args.study == "nr":
+        nr_study(B, driver, build_workload, dev, args.workload)
         return
     cfg, mesh, u0, beta0, bc = build_workload(args.workload)
     if args.counters:
@@ -217,6 +220,44 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def nr_study(B, driver, build_workload, dev, workload):
+    """Newton-Raphson on the uncondensed system (coarse and fine unknowns together, Section 4.2)
+    against Newton-Schur (Section 5), time to 1e-8 from the same initial state, FP64 and
+    mixed precision, GMRES(50) with inexact-Newton forcing in both.  Newton-Raphson is
+    preconditioned by block-Jacobi with the Schur complement's diagonal blocks on node rows and
+    K_ff^-1 on element rows, plus the constant-pressure coarse correction."""
+    import torch
+    cfg, mesh, u0, beta0, bc = build_workload(workload)
+    xyz = torch.from_numpy(mesh.xyz).to(dev)
+    tets = torch.from_numpy(mesh.tets).to(dev)
+    dd = torch.from_numpy(bc.dofs).to(dev)
+    u0d = torch.from_numpy(u0).to(dev)
+    b0d = torch.from_numpy(beta0).to(dev)
+    report = {"study": "nr", "workload": workload, "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes,
+              "unknowns": {"schur": 4 * mesh.n_nodes, "full": 4 * mesh.n_nodes + 3 * mesh.n_elems}}
+    for prec_name, prec in (("fp64", B.VMS_FP64), ("mixed", B.VMS_MIXED)):
+        ctx = B.Context(xyz, tets, dd, precision=prec, full_system=True)
+        for method in ("schur", "full"):
+            runs = []
+            for _ in range(2):                     # warm, timed
+                u = u0d.clone()
+                beta = b0d.clone()
+                torch.cuda.synchronize()
+                runs.append(driver.newton_solve(ctx, u, beta, cfg.re, tol=cfg.newton_tol,
+                                                lin=B.solve_opts(restart=50, rtol=1e-9, max_iters=60000),
+                                                forcing="ew", max_newton=30, method=method))
+            r = runs[-1]
+            key = f"{prec_name}_{method}"
+            report[key] = {"seconds": r.seconds, "newton_steps": len(r.rnorms) - 1,
+                           "gmres_iters": int(sum(d["iters"] for d in r.lin)),
+                           "gmres_iters_per_step": [int(d["iters"]) for d in r.lin],
+                           "final_rel_residual": r.rnorms[-1] / r.rnorms[0]}
+            log(f"{key}: {report[key]}")
+        report[f"{prec_name}_schur_speedup"] = report[f"{prec_name}_full"]["seconds"] / report[f"{prec_name}_schur"]["seconds"]
+        del ctx
+    print(json.dumps(report), flush=True)
 
 
 def bfs_study(B, driver, learned, build_workload, dev, steps):

@@ -122,7 +122,7 @@ static void free_all(vms_ctx* c) {
         delete c->full;
         c->full = nullptr;
     }
-    void* ptrs[] = {c->full_cc, c->full_epos,c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
+    void* ptrs[] = {c->full_cc, c->full_epos, c->zfull, c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
                     c->tpos, c->tile_node0, c->tile_iptr, c->item_ea, c->item_pos, c->A, c->rhs, c->du, c->rglob, c->rnorm, c->flags,
                     c->V, c->w, c->z, c->d, c->r, c->Minv, c->AP, c->Az, c->x64, c->r64, c->gs, c->red,
                     c->feats, c->hid, c->pblk, c->gblk, c->tvec, c->wgrad, c->fscal};
@@ -254,6 +254,7 @@ static int create_full_system(vms_ctx* c, const std::vector<int32_t>& tets, cons
     FTRY(dev_alloc(f, &f->Minv, nr * 16 * es, "alloc full Minv"));
     FTRY(dev_alloc(f, &f->AP, nbf * 16 * es, "alloc full A P"));
     FTRY(dev_alloc(f, &f->Az, N * es, "alloc full A z"));
+    FTRY(dev_alloc(f, &f->zfull, N * sizeof(double), "alloc full coarse vector"));
     FTRY(dev_alloc(f, &f->x64, N * sizeof(double), "alloc full x64"));
     FTRY(dev_alloc(f, &f->r64, N * sizeof(double), "alloc full r64"));
     FTRY(dev_alloc(f, &f->tvec, 3 * N * sizeof(float), "alloc full tvec"));

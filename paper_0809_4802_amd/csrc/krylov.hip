@@ -348,6 +348,78 @@ __global__ __launch_bounds__(kBlock) void coarse_setup_kernel(int n_nodes, const
     }
 }
 
+// Coarse vector of the uncondensed system: 1 on the free node pressures and, on each element
+// row, the fine response -K_ff^-1 K_fc 1_p (K_fc columns of prescribed dofs are zero).  The
+// response vanishes up to rounding unless the element touches a pinned pressure (the
+// gradients of an element sum to zero); with it, 1_p^T A z equals the Schur complement's
+// 1_p^T S 1_p, which the plain indicator (zero pressure-pressure block) would miss.
+template <typename TA, typename TM>
+__global__ void full_coarse_vector_kernel(int nn, int n_rows, const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ colidx, const TA* __restrict__ A,
+                                          const TM* __restrict__ Minv, const uint8_t* __restrict__ dmask,
+                                          double* __restrict__ zvec) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_rows) return;
+    double* zi = zvec + 4 * (size_t)i;
+    if (i < nn) {
+        zi[0] = zi[1] = zi[2] = 0.0;
+        zi[3] = (dmask[i] & 8u) ? 0.0 : 1.0;
+        return;
+    }
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const int b = colidx[k];
+        if (b >= nn || (dmask[b] & 8u)) continue;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) t[q] += double(A[(size_t)k * 16 + 4 * q + 3]);
+    }
+    const TM* P = Minv + (size_t)i * 16;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        zi[r] = -(double(P[4 * r]) * t[0] + double(P[4 * r + 1]) * t[1] + double(P[4 * r + 2]) * t[2]);
+    zi[3] = 0.0;
+}
+
+// kappa = 1 / (1_p^T A z) for the explicit coarse vector z, switched off (as for the condensed
+// system) when the sum is below 1e-8 x the summed magnitudes of the free pressure rows' terms.
+template <typename TA>
+__global__ __launch_bounds__(kBlock) void full_coarse_setup_kernel(int nn, const int32_t* __restrict__ rowptr,
+                                                                   const int32_t* __restrict__ colidx,
+                                                                   const TA* __restrict__ A,
+                                                                   const uint8_t* __restrict__ dmask,
+                                                                   const double* __restrict__ zvec, int enabled,
+                                                                   RedScratch* red, GmresState* gs) {
+    __shared__ double lds[(kBlock / 64) * 2];
+    double v[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += gridDim.x * blockDim.x) {
+        if (dmask[i] & 8u) continue;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const double* zc = zvec + 4 * (size_t)colidx[k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double a = double(A[(size_t)k * 16 + 12 + q]);
+                v[0] += a * zc[q];
+                v[1] += fabs(a * zc[q]);
+            }
+        }
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        red->partial[blockIdx.x] = v[0];
+        red->partial[kRedBlocks + blockIdx.x] = v[1];
+    }
+    if (!arrive_last(&red->counter)) return;
+    __threadfence();
+    __shared__ double tot[2];
+    reduce_partials(red->partial, kRedBlocks, 2, gridDim.x, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const bool usable = isfinite(tot[0]) && fabs(tot[0]) > 1e-8 * tot[1];
+        gs->kappa = (enabled && usable) ? 1.0 / tot[0] : 0.0;
+        red->counter = 0u;
+    }
+}
+
 // Publishes the cycle's progress (completed columns k, done flag) to the host-mapped word.
 __device__ __forceinline__ void report_progress(GmresState* gs, int k, int done) {
     const uint64_t word = ((uint64_t)gs->gen << 32) | ((uint64_t)k << 1) | (uint64_t)(done ? 1 : 0);
@@ -856,11 +928,12 @@ __global__ __launch_bounds__(kBlock) void free_pressure_sum_kernel(int n_nodes, 
     }
 }
 
-// x += P t = Minv t + z kappa (z^T t)  (x in TX: double for the FP64 solution, float for an inner correction)
+// x += P t = Minv t + z kappa (1_p^T t)  (x in TX: double for the FP64 solution, float for an inner
+// correction).  z is the indicator of the free pressure dofs 1_p, or the explicit vector zvec.
 template <typename T, typename TX>
 __global__ void precond_accumulate_kernel(int n_nodes, const T* __restrict__ Minv, const T* __restrict__ t,
-                                          const uint8_t* __restrict__ dmask, const GmresState* gs,
-                                          TX* __restrict__ x) {
+                                          const uint8_t* __restrict__ dmask, const double* __restrict__ zvec,
+                                          const GmresState* gs, TX* __restrict__ x) {
     if (gs->k == 0) return;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = tid >> 2, r = tid & 3;
@@ -870,7 +943,10 @@ __global__ void precond_accumulate_kernel(int n_nodes, const T* __restrict__ Min
     const V4 v = *reinterpret_cast<const V4*>(t + 4 * (size_t)node);
     double s = double(m.x) * double(v.x) + double(m.y) * double(v.y) + double(m.z) * double(v.z) +
                double(m.w) * double(v.w);
-    if (r == 3 && !(dmask[node] & 8u)) s += gs->kappa * gs->st;
+    if (zvec)
+        s += gs->kappa * gs->st * zvec[4 * (size_t)node + r];
+    else if (r == 3 && !(dmask[node] & 8u))
+        s += gs->kappa * gs->st;
     x[4 * (size_t)node + r] = TX(double(x[4 * (size_t)node + r]) + s);
 }
 
@@ -1021,7 +1097,8 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     backsub_kernel<<<1, kBlock, 0, s>>>(c->gs);
     combine_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, V, c->gs, z);
     free_pressure_sum_kernel<T><<<red_grid(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, z, c->dmask, c->red, c->gs);
-    precond_accumulate_kernel<T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, c->dmask, c->gs, x);
+    precond_accumulate_kernel<T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, c->dmask, c->zfull, c->gs,
+                                                                    x);
     return check_hip(c, hipGetLastError(), "gmres cycle launch");
 }
 
@@ -1099,13 +1176,23 @@ int launch_ap_setup(vms_ctx* c, const void* A, hipStream_t s) {
     if (c->prec == VMS_FP64) {
         ap_blocks_kernel<double><<<g, kBlock, 0, s>>>(c->nb, c->colidx, (const double*)A, (const double*)c->Minv,
                                                      (double*)c->AP);
-        coarse_column_kernel<double><<<grid_for(4 * (int64_t)c->n_nodes), kBlock, 0, s>>>(
-            c->n_nodes, c->rowptr, c->colidx, (const double*)A, c->dmask, (double*)c->Az);
+        if (c->zfull)
+            spmv_kernel<double, double, double, double, 0><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
+                c->n_nodes, c->rowptr, c->colidx, (const double*)A, c->zfull, (const double*)nullptr,
+                (double*)c->Az, nullptr, nullptr);
+        else
+            coarse_column_kernel<double><<<grid_for(4 * (int64_t)c->n_nodes), kBlock, 0, s>>>(
+                c->n_nodes, c->rowptr, c->colidx, (const double*)A, c->dmask, (double*)c->Az);
     } else {
         ap_blocks_kernel<float><<<g, kBlock, 0, s>>>(c->nb, c->colidx, (const float*)A, (const float*)c->Minv,
                                                     (float*)c->AP);
-        coarse_column_kernel<float><<<grid_for(4 * (int64_t)c->n_nodes), kBlock, 0, s>>>(
-            c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, (float*)c->Az);
+        if (c->zfull)
+            spmv_kernel<float, double, float, double, 0><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
+                c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->zfull, (const double*)nullptr,
+                (float*)c->Az, nullptr, nullptr);
+        else
+            coarse_column_kernel<float><<<grid_for(4 * (int64_t)c->n_nodes), kBlock, 0, s>>>(
+                c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, (float*)c->Az);
     }
     return check_hip(c, hipGetLastError(), "A P setup launch");
 }
@@ -1148,12 +1235,26 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     } else {
         if ((rc = launch_bj_setup(c, A, c->Minv, s))) return rc;
     }
-    if (c->prec == VMS_FP64)
+    if (c->zfull) {
+        const int nn = c->full_nodes;
+        if (c->prec == VMS_FP64) {
+            full_coarse_vector_kernel<double, double><<<grid_for(c->n_nodes), kBlock, 0, s>>>(
+                nn, c->n_nodes, c->rowptr, c->colidx, (const double*)A, (const double*)c->Minv, c->dmask, c->zfull);
+            full_coarse_setup_kernel<double><<<red_grid(nn), kBlock, 0, s>>>(
+                nn, c->rowptr, c->colidx, (const double*)A, c->dmask, c->zfull, o->coarse_pressure, c->red, c->gs);
+        } else {
+            full_coarse_vector_kernel<float, float><<<grid_for(c->n_nodes), kBlock, 0, s>>>(
+                nn, c->n_nodes, c->rowptr, c->colidx, (const float*)A, (const float*)c->Minv, c->dmask, c->zfull);
+            full_coarse_setup_kernel<float><<<red_grid(nn), kBlock, 0, s>>>(
+                nn, c->rowptr, c->colidx, (const float*)A, c->dmask, c->zfull, o->coarse_pressure, c->red, c->gs);
+        }
+    } else if (c->prec == VMS_FP64) {
         coarse_setup_kernel<double><<<red_grid(c->n_nodes), kBlock, 0, s>>>(
             c->n_nodes, c->rowptr, c->colidx, (const double*)A, c->dmask, o->coarse_pressure, c->red, c->gs);
-    else
+    } else {
         coarse_setup_kernel<float><<<red_grid(c->n_nodes), kBlock, 0, s>>>(
             c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, o->coarse_pressure, c->red, c->gs);
+    }
     if ((rc = launch_ap_setup(c, A, s))) return rc;
     norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, b, c->red, c->rnorm + 3);
     double bn = 0.0;

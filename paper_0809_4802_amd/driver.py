@@ -44,11 +44,16 @@ def forcing_term(k, rn, rn_prev, eta_prev, tol, r0, eta_max=0.1, gamma=0.9):
 
 def newton_solve(ctx: B.Context, u, beta, Re, dt=0.0, u_prev=None, body=None, tol=1e-8, max_newton=25,
                  lin: B.SolveOpts | None = None, stream=None, raise_on_fail=True,
-                 forcing: str = "fixed") -> NewtonResult:
-    """Newton-Schur iterations until ||R_k|| <= tol ||R_0|| (FP64 residual).
+                 forcing: str = "fixed", method: str = "schur") -> NewtonResult:
+    """Newton iterations until ||R_k|| <= tol ||R_0|| (FP64 residual).
 
+    method="schur": Newton-Schur (condensed system, Section 5); method="full": Newton-Raphson
+    on the uncondensed system (Section 4.2; the context needs full_system=True).
     forcing="fixed": every linear solve to lin.rtol.  forcing="ew": inexact
     Newton, linear tolerance from forcing_term() (never below lin.rtol)."""
+    if method not in ("schur", "full"):
+        raise ValueError(f"method must be 'schur' or 'full', not {method!r}")
+    step = B.vms_newton_step if method == "schur" else B.vms_full_newton_step
     lin = lin if lin is not None else B.solve_opts()
     res = NewtonResult(converged=False)
     torch.cuda.synchronize()
@@ -68,7 +73,7 @@ def newton_solve(ctx: B.Context, u, beta, Re, dt=0.0, u_prev=None, body=None, to
         else:
             saved = lin.rtol
         try:
-            info = B.vms_newton_step(ctx, u, beta, Re, dt, u_prev, body, lin, stream)
+            info = step(ctx, u, beta, Re, dt, u_prev, body, lin, stream)
         finally:
             lin.rtol = saved
         rn_prev = info.rnorm_before
