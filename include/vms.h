@@ -289,8 +289,12 @@ enum {
 };
 /* phase_mask: bit p enables phase p (VMS_PROFILE_ALL: every phase), 0 disables.
  * every >= 1: only every every-th launch of an enabled phase is timed (a sample;
- * the accumulators then cover the sampled launches only).  Each call clears the
- * accumulators.  Timing one phase, sparsely, keeps the event cost off the rest. */
+ * the accumulators then cover the sampled launches only).  A full GMRES restart
+ * cycle is replayed from a recorded HIP graph, and events cannot time launches
+ * inside a graph: there the sample is every every-th cycle, launched directly,
+ * with each of its launches of an enabled phase timed (the environment variable
+ * VMS_CYCLE_GRAPHS=0 turns the graphs off).  Each call clears the accumulators.
+ * Timing one phase, sparsely, keeps the event cost off the rest. */
 #define VMS_PROFILE_ALL ((1u << VMS_NPHASES) - 1u)
 int vms_profile(vms_ctx* ctx, uint32_t phase_mask, int32_t every);
 /* Synchronising.  Each array has VMS_NPHASES entries; any may be NULL. */

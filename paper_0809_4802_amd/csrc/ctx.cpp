@@ -63,7 +63,7 @@ static int prof_flush(vms_ctx* c) {
 }
 
 int prof_begin(vms_ctx* c, int phase, double bytes, hipStream_t s) {
-    if (c->prof_seen[phase]++ % c->prof_every != 0) return -1;
+    if (!c->prof_force && c->prof_seen[phase]++ % c->prof_every != 0) return -1;
     if (c->prof_used == kProfPool && prof_flush(c) != VMS_OK) return -1;
     const int slot = c->prof_used++;
     c->prof_phase[slot] = phase;
@@ -102,6 +102,7 @@ extern "C" int vms_profile(vms_ctx* c, uint32_t phase_mask, int32_t every) {
     c->prof_mask = phase_mask;
     c->prof_every = every;
     for (int i = 0; i < VMS_NPHASES; ++i) c->prof_seen[i] = 0;
+    c->prof_cycles = 0;
     return VMS_OK;
 }
 
@@ -131,6 +132,8 @@ static void free_all(vms_ctx* c) {
     for (auto e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
     if (c->progress_host) (void)hipHostFree(c->progress_host);
+    if (c->cycle_exec) (void)hipGraphExecDestroy(c->cycle_exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
 }

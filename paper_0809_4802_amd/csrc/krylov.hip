@@ -16,6 +16,7 @@
 // sequence of launches with no host round trip; the host looks at the
 // convergence flag only every few steps.
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "vms_internal.h"
@@ -985,7 +986,13 @@ __global__ void axpy64_kernel(int n, double alpha, const T* __restrict__ d, doub
     if (i < n) x[i] += alpha * double(d[i]);
 }
 
-inline int red_grid(int64_t n) { return std::max(1, std::min(kRedBlocks, grid_for(n))); }
+// Workgroups of a grid-wide reduction: each one pays a device-scope fence and an atomic on the
+// arrival counter, which costs more than streaming a few more elements per thread.
+#ifndef VMS_RED_GRID_MAX
+#define VMS_RED_GRID_MAX 1024
+#endif
+static_assert(VMS_RED_GRID_MAX <= kRedBlocks, "reduction grid exceeds the partials");
+inline int red_grid(int64_t n) { return std::max(1, std::min(VMS_RED_GRID_MAX, grid_for(n))); }
 
 // Reads a device double with a stream sync.
 int read_scalar(vms_ctx* c, const double* dptr, double* h, hipStream_t s) {
@@ -994,7 +1001,10 @@ int read_scalar(vms_ctx* c, const double* dptr, double* h, hipStream_t s) {
     return check_hip(c, hipStreamSynchronize(s), "sync");
 }
 
-constexpr int kLeadSteps = 3;   // Arnoldi steps the host may issue ahead of the device
+#ifndef VMS_LEAD_STEPS
+#define VMS_LEAD_STEPS 3
+#endif
+constexpr int kLeadSteps = VMS_LEAD_STEPS;   // Arnoldi steps the host may issue ahead of the device
 
 // The device's progress word for cycle gen: completed columns (-1 before the cycle has
 // reported), *done = 1 once the cycle stopped (converged or broke down).
@@ -1037,6 +1047,12 @@ int wait_progress(vms_ctx* c, uint32_t gen, int need, hipStream_t s) {
 // keeps at most kLeadSteps steps queued ahead of it and stops issuing steps once the cycle has
 // converged; nothing here synchronises the stream.  finish_cycle gives the number of steps
 // once the caller has synchronised.
+// Cycle graphs are on unless VMS_CYCLE_GRAPHS=0 in the environment (read at every cycle).
+inline bool cycle_graphs_enabled() {
+    const char* e = std::getenv("VMS_CYCLE_GRAPHS");
+    return !(e && e[0] == '0');
+}
+
 template <typename T, typename TX>
 int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int m, int budget, int cgs2,
               hipStream_t s) {
@@ -1065,34 +1081,78 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
             c->cycle_timed.push_back(ph.gen);
         }
     };
-    for (int j = 0; j < steps; ++j) {
-        if (j >= kLeadSteps) {
-            const int st = wait_progress(c, gen, j - kLeadSteps, s);
-            if (st < 0) return VMS_EHIP;
-            if (st == 1) break;
-        }
-        {
+    auto timed = [&](int phase, double bytes, int j, hipStream_t st, auto&& launch) {
+        PhaseScope ph(c, phase, bytes, st);
+        launch();
+        keep(j, ph);
+    };
+    // the Arnoldi steps and the tail on stream st; with lead, the host keeps at most kLeadSteps
+    // steps queued ahead of the device and stops issuing once the cycle has converged
+    auto issue = [&](int steps_, bool lead, hipStream_t st) -> int {
+        for (int j = 0; j < steps_; ++j) {
+            if (lead && j >= kLeadSteps) {
+                const int sw = wait_progress(c, gen, j - kLeadSteps, st);
+                if (sw < 0) return VMS_EHIP;
+                if (sw == 1) break;
+            }
             // w = A P u_j = (A P) u_j + kappa S(u_j) A z
-            PhaseScope ph(c, VMS_PH_SPMV, spmv_bytes, s);
-            spmv_kernel<T, T, T, T, 2, T><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
-                c->n_nodes, c->rowptr, c->colidx, AP, V + (size_t)j * n, Az, w, &c->gs->done, c->gs);
-            keep(j, ph);
+            timed(VMS_PH_SPMV, spmv_bytes, j, st, [&] {
+                spmv_kernel<T, T, T, T, 2, T><<<spmv_grid(c->n_nodes), kBlock, 0, st>>>(
+                    c->n_nodes, c->rowptr, c->colidx, AP, V + (size_t)j * n, Az, w, &c->gs->done, c->gs);
+            });
+            timed(VMS_PH_DOTS, (j + 2) * vb, j, st, [&] {
+                dots_kernel<T><<<dim3(nch, j + 2), kDotThreads, 0, st>>>(c->n_nodes, j, V, w, c->dmask, part,
+                                                                         c->gs);
+            });
+            reduce_kernel<<<1, kRedThreads, 0, st>>>(j, nch, part, c->gs, 0, eps_dot);
+            timed(VMS_PH_UPDATE, (j + 4) * vb, j, st, [&] {
+                update_kernel<T><<<grid_for(n), kBlock, 0, st>>>(n, j, V, w, c->gs);
+            });
         }
-        {
-            PhaseScope ph(c, VMS_PH_DOTS, (j + 2) * vb, s);
-            dots_kernel<T><<<dim3(nch, j + 2), kDotThreads, 0, s>>>(c->n_nodes, j, V, w, c->dmask, part, c->gs);
-            keep(j, ph);
+        // the second pass of the last vector completes the last column
+        dots_kernel<T><<<dim3(nch, steps_ + 2), kDotThreads, 0, st>>>(c->n_nodes, steps_, V, w, c->dmask, part,
+                                                                      c->gs);
+        reduce_kernel<<<1, kRedThreads, 0, st>>>(steps_, nch, part, c->gs, 1, eps_dot);
+        return VMS_OK;
+    };
+    // With the phase timers on, every prof_every-th cycle is launched directly and every launch
+    // of a timed phase in it is timed (events cannot time launches inside a graph).
+    const bool graphs = steps == m && cycle_graphs_enabled();
+    const bool sampled = c->prof_mask != 0 && c->prof_cycles++ % c->prof_every == 0;
+    if (graphs && !sampled) {
+        // a full cycle: replay the recorded steps (the kernels after convergence return at once)
+        if (!c->cycle_exec || c->cycle_exec_m != m) {
+            int rc = VMS_OK;
+            if (!c->cap_stream &&
+                (rc = check_hip(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream")))
+                return rc;
+            if (c->cycle_exec) {
+                (void)hipGraphExecDestroy(c->cycle_exec);
+                c->cycle_exec = nullptr;
+            }
+            if ((rc = check_hip(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
+                                "begin capture")))
+                return rc;
+            const uint32_t mask = c->prof_mask;      // nothing is timed inside the graph
+            c->prof_mask = 0;
+            rc = issue(m, false, c->cap_stream);
+            c->prof_mask = mask;
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+            if (rc) return rc;
+            if ((rc = check_hip(c, e, "end capture"))) return rc;
+            rc = check_hip(c, hipGraphInstantiate(&c->cycle_exec, g, nullptr, nullptr, 0), "graph instantiate");
+            (void)hipGraphDestroy(g);
+            if (rc) return rc;
+            c->cycle_exec_m = m;
         }
-        reduce_kernel<<<1, kRedThreads, 0, s>>>(j, nch, part, c->gs, 0, eps_dot);
-        {
-            PhaseScope ph(c, VMS_PH_UPDATE, (j + 4) * vb, s);
-            update_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, j, V, w, c->gs);
-            keep(j, ph);
-        }
+        if (int rc = check_hip(c, hipGraphLaunch(c->cycle_exec, s), "graph launch")) return rc;
+    } else {
+        c->prof_force = graphs && sampled;
+        const int rc = issue(steps, true, s);
+        c->prof_force = false;
+        if (rc) return rc;
     }
-    // the second pass of the last vector completes the last column
-    dots_kernel<T><<<dim3(nch, steps + 2), kDotThreads, 0, s>>>(c->n_nodes, steps, V, w, c->dmask, part, c->gs);
-    reduce_kernel<<<1, kRedThreads, 0, s>>>(steps, nch, part, c->gs, 1, eps_dot);
     // y = R^{-1} g on the device
     backsub_kernel<<<1, kBlock, 0, s>>>(c->gs);
     combine_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, V, c->gs, z);

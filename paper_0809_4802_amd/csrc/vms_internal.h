@@ -145,6 +145,12 @@ struct vms_ctx {
     uint64_t* progress_dev = nullptr;
     uint32_t cycle_gen = 0;
     std::vector<int64_t> cycle_timed;    // timed launches of the cycle: (step, slot, generation)
+    // a full restart cycle's Arnoldi steps recorded once as a graph (replayed with one launch)
+    hipStream_t cap_stream = nullptr;    // stream the graph is captured on
+    hipGraphExec_t cycle_exec = nullptr;
+    int cycle_exec_m = 0;                // restart length of cycle_exec
+    int64_t prof_cycles = 0;             // cycles seen while the phase timers are on
+    bool prof_force = false;             // a sampled cycle: every launch of a timed phase is timed
 
     // uncondensed system (vms_create_opts.full_system): a solver-only child context over the
     // n_nodes + n_elems block rows (its n_nodes field counts block rows), and the positions of
