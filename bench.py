@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_EVERY = 8            # timed region: HIP events on every 8th launch of the dominant kernel
+PROFILE_EVERY = 8            # timed region: HIP events on the dominant kernel's launches in every 8th GMRES cycle
 COUNTER_ITERS = 64           # --counters: Arnoldi steps (SpMV launches) in the counter run
 COPY_MIB = 256               # --counters: size of the reference copy
 KERNEL_OF_PHASE = {"condense": "tile_kernel", "spmv": "spmv_kernel", "dots": "dots_kernel",

@@ -989,7 +989,7 @@ __global__ void axpy64_kernel(int n, double alpha, const T* __restrict__ d, doub
 // Workgroups of a grid-wide reduction: each one pays a device-scope fence and an atomic on the
 // arrival counter, which costs more than streaming a few more elements per thread.
 #ifndef VMS_RED_GRID_MAX
-#define VMS_RED_GRID_MAX 1024
+#define VMS_RED_GRID_MAX 128
 #endif
 static_assert(VMS_RED_GRID_MAX <= kRedBlocks, "reduction grid exceeds the partials");
 inline int red_grid(int64_t n) { return std::max(1, std::min(VMS_RED_GRID_MAX, grid_for(n))); }
