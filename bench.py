@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle sample (0: every element of the workload)")
-    ap.add_argument("--study", choices=["bfs", "nr"], default=None,
+    ap.add_argument("--study", choices=["bfs", "nr", "picard"], default=None,
                     help="bfs: the learned-correction study on the backward-facing step (train on the steady "
                          "Re 400..800 continuation of bfs8, compare with block-Jacobi over the transient bfs16 "
                          "run); prints its own JSON report instead of the bench line")
@@ -74,6 +74,9 @@ def main():
         return
     if args.study == "nr":
         nr_study(B, driver, build_workload, dev, args.workload)
+        return
+    if args.study == "picard":
+        picard_study(B, driver, build_workload, dev, args.workload)
         return
     cfg, mesh, u0, beta0, bc = build_workload(args.workload)
     if args.counters:
@@ -257,6 +260,36 @@ def nr_study(B, driver, build_workload, dev, workload):
             log(f"{key}: {report[key]}")
         report[f"{prec_name}_schur_speedup"] = report[f"{prec_name}_full"]["seconds"] / report[f"{prec_name}_schur"]["seconds"]
         del ctx
+    print(json.dumps(report), flush=True)
+
+
+def picard_study(B, driver, build_workload, dev, workload, reynolds=(100.0, 400.0, 1000.0), max_steps=60):
+    """Consistent Newton (Section 4.2) against the fixed-point linearisation the introduction
+    argues against (advecting velocity held at the iterate), mixed precision, from the same
+    initial state, to 1e-8 or max_steps, inexact-Newton forcing and GMRES(50) in both."""
+    import torch
+    cfg, mesh, u0, beta0, bc = build_workload(workload)
+    ctx = B.Context(torch.from_numpy(mesh.xyz).to(dev), torch.from_numpy(mesh.tets).to(dev),
+                    torch.from_numpy(bc.dofs).to(dev), precision=B.VMS_MIXED)
+    report = {"study": "picard", "workload": workload, "n_elems": mesh.n_elems}
+    for re in reynolds:
+        for name, kind in (("newton", B.VMS_LIN_NEWTON), ("picard", B.VMS_LIN_PICARD)):
+            B.vms_set_linearization(ctx, kind)
+            u = torch.from_numpy(u0).to(dev)
+            beta = torch.from_numpy(beta0).to(dev)
+            try:
+                r = driver.newton_solve(ctx, u, beta, re, tol=cfg.newton_tol,
+                                        lin=B.solve_opts(restart=50, rtol=1e-9, max_iters=60000),
+                                        forcing="ew", max_newton=max_steps, raise_on_fail=False)
+                out = {"converged": bool(r.converged), "steps": len(r.rnorms) - 1, "seconds": r.seconds,
+                       "gmres_iters": int(sum(d["iters"] for d in r.lin)),
+                       "rel_residuals": [x / r.rnorms[0] for x in r.rnorms]}
+            except B.VmsError as e:          # a linear solve that fails is a result here
+                out = {"converged": False, "error": str(e)}
+            key = f"re{re:g}_{name}"
+            report[key] = out
+            log(f"{key}: " + json.dumps({k: v for k, v in out.items() if k != "rel_residuals"}))
+    B.vms_set_linearization(ctx, B.VMS_LIN_NEWTON)
     print(json.dumps(report), flush=True)
 
 

@@ -57,6 +57,7 @@ typedef struct vms_ctx vms_ctx;
 
 typedef enum { VMS_FP64 = 0, VMS_MIXED = 1 } vms_precision;
 typedef enum { VMS_PC_BLOCK_JACOBI = 0, VMS_PC_LEARNED = 1 } vms_pc_kind;
+typedef enum { VMS_LIN_NEWTON = 0, VMS_LIN_PICARD = 1 } vms_linearization;
 
 /* Mesh, read once by vms_create (the library keeps its own copies).
  *   xyz   device double [n_nodes][3]
@@ -227,9 +228,13 @@ int vms_full_assemble(vms_ctx* ctx, const double* u, const double* u_prev, const
                       double* rnorm, hipStream_t stream);
 
 /* One Newton-Raphson iteration on the uncondensed system: assemble, solve with
- * the context's GMRES (4x4 block-Jacobi on the block rows above; the learned
- * correction is not available here), update u and beta in place, evaluate the
- * new residual.  Synchronising. */
+ * the context's GMRES, update u and beta in place, evaluate the new residual.
+ * Preconditioner: block-diagonal on the block rows above, the inverse of the
+ * Schur complement's diagonal block K_cc(i,i) - sum_e K_cf(i,e) K_ff(e)^-1 K_fc(e,i)
+ * on node rows (the plain node block has a zero pressure diagonal) and K_ff^-1
+ * on element rows, plus the constant-pressure coarse correction with the
+ * fine-scale response of the pressure mode; opts->lin.pc is ignored (the
+ * learned correction is trained on condensed blocks).  Synchronising. */
 int vms_full_newton_step(vms_ctx* ctx, double* u, double* beta, const double* u_prev, double Re,
                          double dt, const double* body, const vms_newton_opts* opts,
                          vms_newton_info* info, hipStream_t stream);
@@ -299,6 +304,19 @@ enum {
 int vms_profile(vms_ctx* ctx, uint32_t phase_mask, int32_t every);
 /* Synchronising.  Each array has VMS_NPHASES entries; any may be NULL. */
 int vms_profile_read(vms_ctx* ctx, double* ms, int64_t* launches, double* alg_bytes);
+
+/* ---- linearisation ----------------------------------------------------------
+ * The paper linearises consistently (Newton-Raphson, Section 4.2) and, in its
+ * introduction, contrasts this with fixed-point iteration, which holds the
+ * advecting velocity of (v . grad) v at the current iterate.  VMS_LIN_PICARD
+ * switches every tangent this context forms (vms_element_tangents,
+ * vms_condense_assemble, vms_newton_step, the recovery, the uncondensed path)
+ * to that fixed-point tangent: the terms from the derivative of the advecting
+ * coarse and fine velocity are dropped, everything else is unchanged.  The
+ * residual is the same, so a converged solve reaches the same solution, at a
+ * linear instead of a quadratic rate.  Default VMS_LIN_NEWTON.  Not
+ * synchronising; VMS_EINVAL for another value. */
+int vms_set_linearization(vms_ctx* ctx, int kind);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,14 @@
  *   row's integrand in the direction of each of the 19 element unknowns
  *     d[(v.grad)v] = (dv.grad) v + (v.grad) dv,
  *   integrated with the same rule.  This is a pointwise linearisation,
- *   written independently of any closed-form integration.
+ *   written independently of any closed-form integration.  With picard = 1 the
+ *   advecting velocity is held at the current iterate (the fixed-point
+ *   linearisation the introduction contrasts with Newton's): d[(v.grad)v] =
+ *   (v.grad) dv only.
+ *
+ *   For tests of that tangent the advecting velocity of the residual can be
+ *   taken from a separate state (u_adv, beta_adv; NULL: the state itself):
+ *   the convective term is then (v_adv.grad) v, affine in the unknowns.
  *
  *   Bubble b = c * 256 l0 l1 l2 l3 (barycentric l_a; c = 1 normally; the
  *   paper leaves the bubble unspecified, see Section 3.3).
@@ -33,7 +40,8 @@
  *   xyz [n_nodes][3], tets [n_elems][4], u [n_nodes][4], u_prev [n_nodes][4]
  *   or NULL (steady), beta [n_elems][3], body [n_nodes][3] or NULL,
  *   lam [nq][4], w [nq] (reference weights summing to 1/6),
- *   R [n_elems][19], K [n_elems][19][19] or NULL.
+ *   R [n_elems][19], K [n_elems][19][19] or NULL; u_adv [n_nodes][4] and
+ *   beta_adv [n_elems][3] or NULL (both or neither).
  * Returns 0, or 1 + (index of the first element with det J <= 0).
  */
 #include <stdint.h>
@@ -72,9 +80,10 @@ static double tet_geometry(const double X[4][3], double g[4][3])
 }
 
 static void element_one(const double X[4][3], const double U[4][4], const double Uprev[4][4],
-                        const double F[4][3], const double beta[3], double nu, double inv_dt,
-                        double bscale, int nq, const double* lam, const double* wq,
-                        double det, const double g[4][3], double R[NDOF], double* K)
+                        const double Uadv[4][4], const double F[4][3], const double beta[3],
+                        const double beta_adv[3], double nu, double inv_dt, double bscale, int picard,
+                        int nq, const double* lam, const double* wq, double det, const double g[4][3],
+                        double R[NDOF], double* K)
 {
     memset(R, 0, sizeof(double) * NDOF);
     if (K) memset(K, 0, sizeof(double) * NDOF * NDOF);
@@ -99,23 +108,25 @@ static void element_one(const double X[4][3], const double U[4][4], const double
             for (int i = 0; i < 3; ++i) db[i] += prod * g[a][i];
         }
         /* fields at the point */
-        double vbar[3] = {0, 0, 0}, vprev[3] = {0, 0, 0}, f[3] = {0, 0, 0}, p = 0.0;
+        double vbar[3] = {0, 0, 0}, vprev[3] = {0, 0, 0}, f[3] = {0, 0, 0}, p = 0.0, vadv[3] = {0, 0, 0};
         for (int a = 0; a < 4; ++a) {
             for (int i = 0; i < 3; ++i) {
                 vbar[i] += L[a] * U[a][i];
                 vprev[i] += L[a] * Uprev[a][i];
                 f[i] += L[a] * F[a][i];
+                vadv[i] += L[a] * Uadv[a][i];
             }
             p += L[a] * U[a][3];
         }
-        double v[3], G[3][3];
+        double v[3], va[3], G[3][3];
         for (int i = 0; i < 3; ++i) {
             v[i] = vbar[i] + bub * beta[i];
+            va[i] = vadv[i] + bub * beta_adv[i];      /* advecting velocity */
             for (int j = 0; j < 3; ++j) G[i][j] = Gbar[i][j] + beta[i] * db[j];
         }
         double conv[3];
         for (int i = 0; i < 3; ++i)
-            conv[i] = G[i][0] * v[0] + G[i][1] * v[1] + G[i][2] * v[2];
+            conv[i] = G[i][0] * va[0] + G[i][1] * va[1] + G[i][2] * va[2];
         double divv = G[0][0] + G[1][1] + G[2][2];
 
         /* test functions: momentum rows carry (value tw, gradient tg), continuity rows tq */
@@ -182,10 +193,11 @@ static void element_one(const double X[4][3], const double U[4][4], const double
         }
         for (int c = 0; c < NDOF; ++c) {
             double dm[3];
-            for (int i = 0; i < 3; ++i)
-                dm[i] = dG[c][i][0] * v[0] + dG[c][i][1] * v[1] + dG[c][i][2] * v[2]
-                      + G[i][0] * dv[c][0] + G[i][1] * dv[c][1] + G[i][2] * dv[c][2]
-                      + dvb[c][i] * inv_dt;
+            for (int i = 0; i < 3; ++i) {
+                /* (v.grad) dv: the advected field; (dv.grad) v: the advecting one (Newton only) */
+                dm[i] = dG[c][i][0] * va[0] + dG[c][i][1] * va[1] + dG[c][i][2] * va[2] + dvb[c][i] * inv_dt;
+                if (!picard) dm[i] += G[i][0] * dv[c][0] + G[i][1] * dv[c][1] + G[i][2] * dv[c][2];
+            }
             double ddiv = dG[c][0][0] + dG[c][1][1] + dG[c][2][2];
             for (int r = 0; r < NDOF; ++r) {
                 double val;
@@ -207,13 +219,13 @@ static void element_one(const double X[4][3], const double U[4][4], const double
 
 int oracle_element(int64_t n_elems, const int32_t* tets, const double* xyz, const double* u,
                    const double* u_prev, const double* beta, const double* body, double nu,
-                   double inv_dt, double bscale, int nq, const double* lam, const double* wq,
-                   double* R, double* K)
+                   double inv_dt, double bscale, int picard, const double* u_adv, const double* beta_adv,
+                   int nq, const double* lam, const double* wq, double* R, double* K)
 {
     int64_t first_bad = -1;
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < n_elems; ++e) {
-        double X[4][3], U[4][4], Up[4][4], F[4][3], g[4][3];
+        double X[4][3], U[4][4], Up[4][4], Ua[4][4], F[4][3], g[4][3];
         for (int a = 0; a < 4; ++a) {
             int64_t n = tets[4 * e + a];
             for (int i = 0; i < 3; ++i) {
@@ -223,6 +235,7 @@ int oracle_element(int64_t n_elems, const int32_t* tets, const double* xyz, cons
             for (int i = 0; i < 4; ++i) {
                 U[a][i] = u[4 * n + i];
                 Up[a][i] = u_prev ? u_prev[4 * n + i] : 0.0;
+                Ua[a][i] = u_adv ? u_adv[4 * n + i] : U[a][i];
             }
         }
         double det = tet_geometry(X, g);
@@ -231,8 +244,9 @@ int oracle_element(int64_t n_elems, const int32_t* tets, const double* xyz, cons
             if (first_bad < 0 || e < first_bad) first_bad = e;
             continue;
         }
-        element_one(X, U, Up, F, beta + 3 * e, nu, u_prev ? inv_dt : 0.0, bscale, nq, lam, wq,
-                    det, g, R + NDOF * e, K ? K + (int64_t)NDOF * NDOF * e : NULL);
+        element_one(X, U, Up, Ua, F, beta + 3 * e, beta_adv ? beta_adv + 3 * e : beta + 3 * e, nu,
+                    u_prev ? inv_dt : 0.0, bscale, picard, nq, lam, wq, det, g, R + NDOF * e,
+                    K ? K + (int64_t)NDOF * NDOF * e : NULL);
     }
     return first_bad < 0 ? 0 : (int)(1 + first_bad);
 }

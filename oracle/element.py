@@ -42,7 +42,7 @@ def _load():
         lib.oracle_element.restype = ctypes.c_int
         lib.oracle_element.argtypes = [ctypes.c_int64, ip, dp, dp, dp, dp, dp, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
-                                       dp, dp]
+                                       ctypes.c_int, dp, dp, dp, dp]
         _lib = lib
     return _lib
 
@@ -54,12 +54,15 @@ def _ptr(a, ctype):
 
 
 def element_residual_tangent(xyz, tets, u, beta, nu, dt=0.0, u_prev=None, body=None,
-                             bubble_scale=1.0, with_tangent=True, n_quad=7):
+                             bubble_scale=1.0, with_tangent=True, n_quad=7, picard=False, advect=None):
     """Element residuals R [E, 19] and tangents K [E, 19, 19] (K None if not requested).
 
     xyz [n_nodes, 3], tets [E, 4], u [n_nodes, 4] = (v, p), beta [E, 3],
     nu kinematic viscosity, dt <= 0 for steady (u_prev ignored), body
-    [n_nodes, 3] P1 nodal body force or None.
+    [n_nodes, 3] P1 nodal body force or None.  picard: the fixed-point tangent
+    (advecting velocity held fixed) instead of Newton's.  advect = (u_adv, beta_adv):
+    the advecting velocity of the residual's convective term from that state (tests of
+    the fixed-point tangent); None: the state itself.
     """
     lib = _load()
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -75,12 +78,18 @@ def element_residual_tangent(xyz, tets, u, beta, nu, dt=0.0, u_prev=None, body=N
     lam, w = tet_rule(n_quad)
     lam = np.ascontiguousarray(lam)
     w = np.ascontiguousarray(w)
+    ua = ba = None
+    if advect is not None:
+        ua = np.ascontiguousarray(advect[0], dtype=np.float64)
+        ba = np.ascontiguousarray(advect[1], dtype=np.float64)
+        assert ua.shape == u.shape and ba.shape == beta.shape
     R = np.zeros((E, NDOF))
     K = np.zeros((E, NDOF, NDOF)) if with_tangent else None
     rc = lib.oracle_element(E, _ptr(tets, ctypes.c_int32), _ptr(xyz, ctypes.c_double),
                             _ptr(u, ctypes.c_double), _ptr(up, ctypes.c_double),
                             _ptr(beta, ctypes.c_double), _ptr(f, ctypes.c_double),
                             float(nu), (1.0 / dt) if transient else 0.0, float(bubble_scale),
+                            1 if picard else 0, _ptr(ua, ctypes.c_double), _ptr(ba, ctypes.c_double),
                             int(lam.shape[0]), _ptr(lam, ctypes.c_double), _ptr(w, ctypes.c_double),
                             _ptr(R, ctypes.c_double), _ptr(K, ctypes.c_double))
     if rc != 0:

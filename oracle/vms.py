@@ -114,6 +114,7 @@ class Problem:
     dt: float = 0.0
     u_prev: np.ndarray | None = None
     body: np.ndarray | None = None
+    picard: bool = False        # fixed-point tangent (advecting velocity held) instead of Newton's
 
     @property
     def n_nodes(self):
@@ -125,7 +126,7 @@ class Problem:
 
     def element(self, u, beta, with_tangent=True):
         return element_residual_tangent(self.xyz, self.tets, u, beta, self.nu, self.dt,
-                                        self.u_prev, self.body, with_tangent=with_tangent)
+                                        self.u_prev, self.body, with_tangent=with_tangent, picard=self.picard)
 
 
 def condensed_system(prob: Problem, u, beta):

@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "VMS_OK", -1: "VMS_EINVAL", -2: "VMS_EDEGENERATE", -3: "VMS_E
                 -7: "VMS_EHIP", -8: "VMS_ENOMEM"}
 VMS_FP64, VMS_MIXED = 0, 1
 VMS_PC_BLOCK_JACOBI, VMS_PC_LEARNED = 0, 1
+VMS_LIN_NEWTON, VMS_LIN_PICARD = 0, 1
 PC_NIN, PC_NHID, PC_NOUT = 25, 64, 16
 PC_NWEIGHTS = PC_NHID * PC_NIN + PC_NHID + PC_NOUT * PC_NHID + PC_NOUT
 
@@ -34,7 +35,7 @@ EXPORTED = ["vms_create", "vms_destroy", "vms_last_error", "vms_bsr_info", "vms_
             "vms_condense_assemble", "vms_residual", "vms_recover_update", "vms_bsr_spmv",
             "vms_gmres_solve", "vms_newton_step", "vms_full_info", "vms_full_assemble",
             "vms_full_newton_step", "vms_pc_features", "vms_pc_blocks",
-            "vms_pc_train_step", "vms_profile", "vms_profile_read"]
+            "vms_pc_train_step", "vms_profile", "vms_profile_read", "vms_set_linearization"]
 PHASES = ["condense", "residual", "recover", "pc_setup", "pc_apply", "spmv", "dots", "update", "fill"]
 
 
@@ -97,6 +98,7 @@ _sig = {
     "vms_gmres_solve": [_vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), _vp],
     "vms_newton_step": [_vp, _vp, _vp, _vp, _d, _d, _vp, ctypes.POINTER(NewtonOpts),
                         ctypes.POINTER(NewtonInfo), _vp],
+    "vms_set_linearization": [_vp, ctypes.c_int],
     "vms_full_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_i32), ctypes.POINTER(_vp),
                       ctypes.POINTER(_vp)],
     "vms_full_assemble": [_vp, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _vp, _vp],
@@ -307,6 +309,11 @@ def vms_newton_step(ctx: Context, u, beta, Re, dt=0.0, u_prev=None, body=None, l
                               ctypes.byref(opts), ctypes.byref(info), _stream(stream))
     _check(rc, ctx.handle)
     return info
+
+
+def vms_set_linearization(ctx: Context, kind):
+    """kind: VMS_LIN_NEWTON (consistent tangent) or VMS_LIN_PICARD (advecting velocity held)."""
+    _check(_lib.vms_set_linearization(ctx.handle, int(kind)), ctx.handle)
 
 
 def vms_full_assemble(ctx: Context, u, beta, Re, dt=0.0, u_prev=None, body=None, bsr_vals=None, rhs=None,

@@ -537,6 +537,14 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     return VMS_OK;
 }
 
+extern "C" int vms_set_linearization(vms_ctx* ctx, int kind) {
+    if (!ctx) return set_error(nullptr, VMS_EINVAL, "vms_set_linearization: NULL ctx");
+    if (kind != VMS_LIN_NEWTON && kind != VMS_LIN_PICARD)
+        return set_error(ctx, VMS_EINVAL, "vms_set_linearization: unknown kind");
+    ctx->linearization = kind;
+    return VMS_OK;
+}
+
 extern "C" int vms_full_info(const vms_ctx* ctx, int64_t* nb, int32_t* n_rows, const int32_t** rowptr,
                              const int32_t** colidx) {
     if (!ctx) return set_error(nullptr, VMS_EINVAL, "vms_full_info: NULL ctx");

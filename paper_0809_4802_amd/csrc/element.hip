@@ -48,6 +48,7 @@ struct ElemArgs {
     const double* __restrict__ body;     // [n][3] or null
     double nu;
     double inv_dt;
+    double adv;                          // 1: Newton tangent; 0: fixed-point tangent (advecting velocity held)
     int n_elems;
     int32_t* flags;                      // [0] first degenerate element, [1] first singular K_ff
 };
@@ -72,6 +73,7 @@ struct Elem {
     double f[4][3];
     bool transient;
     bool has_body;
+    double adv;        // weight of the tangent's advecting-velocity terms (1 Newton, 0 fixed point)
 };
 
 __device__ __forceinline__ bool load_element(const ElemArgs& A, int e, Elem& E) {
@@ -140,6 +142,7 @@ __device__ __forceinline__ bool load_element(const ElemArgs& A, int e, Elem& E) 
     E.th = E.G[0][0] + E.G[1][1] + E.G[2][2];
 
     E.transient = A.u_prev != nullptr && A.inv_dt != 0.0;
+    E.adv = A.adv;
 #pragma unroll
     for (int i = 0; i < 3; ++i) E.dvs[i] = 0.0;
     if (E.transient) {
@@ -221,7 +224,7 @@ __device__ __forceinline__ bool fine_block_inverse(const Elem& E, double nu, dou
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) Kff[i][j] = E.C * E.G[i][j] + (i == j ? d : 0.0);
+        for (int j = 0; j < 3; ++j) Kff[i][j] = E.adv * E.C * E.G[i][j] + (i == j ? d : 0.0);
     const double c00 = Kff[1][1] * Kff[2][2] - Kff[1][2] * Kff[2][1];
     const double c01 = Kff[1][2] * Kff[2][0] - Kff[1][0] * Kff[2][2];
     const double c02 = Kff[1][0] * Kff[2][1] - Kff[1][1] * Kff[2][0];
@@ -250,7 +253,7 @@ __device__ __forceinline__ void fine_coarse_block(const Elem& E, int b, double i
     const double gW = E.g[b][0] * E.Wv[0] + E.g[b][1] * E.Wv[1] + E.g[b][2] * E.Wv[2];
     const double gb = E.g[b][0] * E.be[0] + E.g[b][1] * E.be[1] + E.g[b][2] * E.be[2];
     const T diag = T(gW + E.C * gb + E.B1 * inv_dt);
-    const T B1 = T(E.B1), hC = T(0.5 * E.C), B = T(E.B);
+    const T B1 = T(E.adv * E.B1), hC = T(E.adv * 0.5 * E.C), B = T(E.B);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
 #pragma unroll
@@ -266,7 +269,7 @@ __device__ __forceinline__ void coarse_fine_block(const Elem& E, int a, T K[4][3
     const double gW = E.g[a][0] * E.Wv[0] + E.g[a][1] * E.Wv[1] + E.g[a][2] * E.Wv[2];
     const double bg = E.be[0] * E.g[a][0] + E.be[1] * E.g[a][1] + E.be[2] * E.g[a][2];
     const T diag = T(-(gW + E.th * E.B1) - 0.5 * E.C * bg);
-    const T B1 = T(E.B1), hC = T(0.5 * E.C), B = T(E.B);
+    const T B1 = T(E.adv * E.B1), hC = T(E.adv * 0.5 * E.C), B = T(E.B);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -276,10 +279,11 @@ __device__ __forceinline__ void coarse_fine_block(const Elem& E, int a, T K[4][3
     for (int j = 0; j < 3; ++j) K[3][j] = B * T(E.g[a][j]);
 }
 
-// K_cc(a,b): 4x4 block, precision T.  Gt, gt, Vt, bt are T copies of the fields.
+// K_cc(a,b): 4x4 block, precision T.  Gt, gt, Vt, bt are T copies of the fields; adv
+// weighs the terms from the derivative of the advecting velocity (1 Newton, 0 fixed point).
 template <typename T>
 __device__ __forceinline__ void coarse_block(const T Gt[3][3], const T gt[4][3], const T Va[3],
-                                             const T bt[3], T vol, T B1, T two_nu_vol, T inv_dt,
+                                             const T bt[3], T vol, T B1, T two_nu_vol, T inv_dt, T adv,
                                              int a, int b, T K[4][4]) {
     const T mab = vol * (a == b ? T(0.1) : T(0.05));
     const T gbV = gt[b][0] * Va[0] + gt[b][1] * Va[1] + gt[b][2] * Va[2];
@@ -291,7 +295,7 @@ __device__ __forceinline__ void coarse_block(const T Gt[3][3], const T gt[4][3],
     for (int i = 0; i < 3; ++i) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            K[i][j] = mab * Gt[i][j] - B1 * bt[i] * (gt[a][j] + gt[b][j]) + (i == j ? s : T(0));
+            K[i][j] = adv * (mab * Gt[i][j] - B1 * bt[i] * (gt[a][j] + gt[b][j])) + (i == j ? s : T(0));
         K[i][3] = qv * gt[a][i];
         K[3][i] = qv * gt[b][i];
     }
@@ -482,7 +486,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) Kff[i][j] = Cm * G[i][j] + (i == j ? dk : 0.0);
+                for (int j = 0; j < 3; ++j) Kff[i][j] = args.adv * Cm * G[i][j] + (i == j ? dk : 0.0);
             const double k00 = Kff[1][1] * Kff[2][2] - Kff[1][2] * Kff[2][1];
             const double k01 = Kff[1][2] * Kff[2][0] - Kff[1][0] * Kff[2][2];
             const double k02 = Kff[1][0] * Kff[2][1] - Kff[1][1] * Kff[2][0];
@@ -507,7 +511,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
-                    Kcf[i][j] = B1 * G[i][j] - 0.5 * Cm * be[i] * ga[j] + (i == j ? dg : 0.0);
+                    Kcf[i][j] = args.adv * (B1 * G[i][j] - 0.5 * Cm * be[i] * ga[j]) + (i == j ? dg : 0.0);
 #pragma unroll
             for (int j = 0; j < 3; ++j) Kcf[3][j] = Bm * ga[j];
             double zf[3];
@@ -538,10 +542,12 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
         T keep_r[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) keep_r[r] = (dma & (1u << r)) ? T(0) : T(1);
-        const T Gt[3][3] = {{T(G[0][0]), T(G[0][1]), T(G[0][2])},
-                            {T(G[1][0]), T(G[1][1]), T(G[1][2])},
-                            {T(G[2][0]), T(G[2][1]), T(G[2][2])}};
-        const T bt[3] = {T(be[0]), T(be[1]), T(be[2])};
+        // the advecting-velocity terms (weight adv) of K_vv and K_fv
+        const double av = args.adv;
+        const T Gt[3][3] = {{T(av * G[0][0]), T(av * G[0][1]), T(av * G[0][2])},
+                            {T(av * G[1][0]), T(av * G[1][1]), T(av * G[1][2])},
+                            {T(av * G[2][0]), T(av * G[2][1]), T(av * G[2][2])}};
+        const T bt[3] = {T(av * be[0]), T(av * be[1]), T(av * be[2])};
         const T gat[3] = {T(ga[0]), T(ga[1]), T(ga[2])};
         const T B1t = T(B1), hCt = T(0.5 * Cm), qv = T(-0.25 * vol);
         const uint2 pp = ta.pos[k];
@@ -647,7 +653,7 @@ __global__ __launch_bounds__(kBlock) void raw_kernel(ElemArgs args, double* __re
         for (int i = 0; i < 3; ++i) Va[i] = T(m0 * (E.vs[i] + E.v[a][i]));
         for (int b = 0; b < 4; ++b) {
             T Kb[4][4];
-            coarse_block<T>(Gt, gt, Va, bt, volt, B1t, tnv, idt, a, b, Kb);
+            coarse_block<T>(Gt, gt, Va, bt, volt, B1t, tnv, idt, T(E.adv), a, b, Kb);
             for (int r = 0; r < 4; ++r)
                 for (int c = 0; c < 4; ++c) K[(4 * a + r) * 19 + 4 * b + c] = double(Kb[r][c]);
         }
@@ -769,6 +775,7 @@ ElemArgs make_args(vms_ctx* c, const double* u, const double* u_prev, const doub
     a.body = body;
     a.nu = nu;
     a.inv_dt = u_prev ? inv_dt : 0.0;
+    a.adv = c->linearization == VMS_LIN_PICARD ? 0.0 : 1.0;
     a.n_elems = c->n_elems;
     a.flags = c->flags;
     return a;

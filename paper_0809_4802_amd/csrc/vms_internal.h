@@ -158,6 +158,7 @@ struct vms_ctx {
     vms_ctx* full = nullptr;
     int32_t* full_cc = nullptr;      // [nb] position of condensed-pattern block k in the full pattern
     int32_t* full_epos = nullptr;    // [n_elems][9]: (node a, elem) a = 0..3, (elem, node b) b = 0..3, (elem, elem)
+    int32_t linearization = VMS_LIN_NEWTON;   // tangent of the element kernels (vms_set_linearization)
     int32_t full_nodes = 0;          // in the child: number of node block rows (0 in other contexts)
     double* zfull = nullptr;         // in the child: [4 n_nodes] coarse vector (free pressures + fine response)
 
