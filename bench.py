@@ -136,7 +136,10 @@ def main():
     ctx = ctxs["mixed"]
     data, _ = learned.collect_newton_data(ctx, u0d.clone(), b0d.clone(), cfg.re,
                                           lin=B.solve_opts(restart=50, rtol=1e-4, max_iters=60000), per_step=48)
-    val = [(A, S[0].contiguous()) for A, S in data[-1:]]      # first logged residual = the rhs
+    # checkpoints are scored by GMRES iterations on the two last (hardest) Newton systems: the
+    # last one held out of training, the one before it a training system (first logged
+    # residual = the rhs)
+    val = [(A, S[0].contiguous()) for A, S in data[-2:]]
     weights, train_report = learned.train_select(ctx, data[:-1] or data, val, seeds=(1, 2, 3), steps=200, lr=3e-4)
     train_report["seconds"] = time.perf_counter() - t0
     log(f"learned PC: {train_report}")
