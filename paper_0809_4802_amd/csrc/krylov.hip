@@ -68,8 +68,8 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
                                                       const TA* __restrict__ A, const TX* __restrict__ x,
                                                       const TB* __restrict__ b, TY* __restrict__ y,
                                                       const int* __restrict__ done, const GmresState* gs) {
-    // a finished GMRES cycle (done != NULL and set) skips the store; the flag is read
-    // alongside the data so that it adds no latency in front of the loads
+    // a finished GMRES cycle (done != NULL and set) reads no blocks and stores nothing; the
+    // flag is read alongside the row bounds, which the block loads wait for anyway
     const int skip = done ? *done : 0;
     constexpr int Q = kSpmvLanes / 4;
     using VA = typename Vec4<TA>::type;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
     const int q = sub >> 2, r = sub & 3;
     TACC acc = TACC(0);
     if (row < n_rows) {
-        const int k0 = rowptr[row], k1 = rowptr[row + 1];
+        const int k0 = rowptr[row], k1 = skip ? k0 : rowptr[row + 1];
         int cols[kSpmvUnroll];
 #pragma unroll
         for (int u = 0; u < kSpmvUnroll; ++u) {
