@@ -115,7 +115,9 @@ int vms_element_tangents(vms_ctx* ctx, const double* u, const double* u_prev, co
  * Rows and columns of Dirichlet dofs are replaced by the identity and their
  * rhs by 0.  rnorm (device double[1], may be NULL) receives the FP64 Newton
  * residual norm ||[R_c; R_p] (assembled, free dofs), R_f (all elements)||_2
- * at the input state.  Not synchronising. */
+ * at the input state.  Not synchronising, so a singular K_ff is not reported
+ * here (the condensed blocks of that element are then meaningless); vms_newton_step reports it
+ * (VMS_ESINGULAR_KFF, the first such element in vms_last_error). */
 int vms_condense_assemble(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta,
                           double Re, double dt, const double* body, void* bsr_vals, double* rhs,
                           double* rnorm, hipStream_t stream);

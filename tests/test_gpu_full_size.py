@@ -1,0 +1,67 @@
+"""Full-size workloads on the GPU, checked on sampled outputs the oracle computes one by one.
+
+* cavity 32^3 (196,608 tets, Re 100): the benchmarked solve, FP64 and mixed, GMRES(50) with
+  block-Jacobi and inexact-Newton forcing, to 1e-8.  The oracle's FP64 residual of the final
+  state at sampled interior nodes (assembled from their element patches) and sampled
+  elements (fine-scale equations) must be below the Newton tolerance; the two precision forms
+  reach the same solution.
+* backward-facing step bfs8 (1,248,000 tets, open outlet, no pressure pin), steady Re 400 from
+  rest, mixed, to 1e-8: the same sampled residual check.
+"""
+import numpy as np
+import pytest
+import torch
+
+from workloads import build_workload, boundary_nodes
+from tests.gpu_common import DEV, make_context, rel_fro
+from tests.test_gpu_es import _patch_residuals
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(B, m, u0, beta0, dofs, Re, precision, tol=1e-8, max_newton=30):
+    from paper_0809_4802_amd import driver
+    ctx = make_context(B, m, dofs, precision)
+    u = torch.from_numpy(u0).to(DEV)
+    beta = torch.from_numpy(beta0).to(DEV)
+    res = driver.newton_solve(ctx, u, beta, Re, tol=tol, forcing="ew", max_newton=max_newton,
+                              lin=B.solve_opts(restart=50, rtol=1e-9, max_iters=60000))
+    return res, u.cpu().numpy(), beta.cpu().numpy()
+
+
+def _check_sampled_residual(m, dofs, u, beta, Re, r0, tol, seed):
+    rng = np.random.default_rng(seed)
+    interior = np.nonzero(~boundary_nodes(m.tets, m.n_nodes))[0]
+    interior = np.setdiff1d(interior, dofs[dofs % 4 == 3] // 4)
+    nodes = np.sort(rng.choice(interior, size=64, replace=False))
+    elems = np.sort(rng.choice(m.n_elems, size=256, replace=False))
+    Rn, Rf = _patch_residuals(m, u, beta, 1.0 / Re, 0.0, None, nodes, elems)
+    assert np.abs(Rn).max() <= 1.01 * tol * r0, (np.abs(Rn).max(), r0)
+    assert np.abs(Rf).max() <= 1.01 * tol * r0, (np.abs(Rf).max(), r0)
+
+
+def test_cavity32_benchmark_solve_sampled(vms_lib):
+    B = vms_lib
+    cfg, m, u0, beta0, bc = build_workload("cavity32")
+    assert m.n_elems == 196_608 and cfg.re == 100.0
+    sols = {}
+    for prec in (B.VMS_FP64, B.VMS_MIXED):
+        res, u, beta = _solve(B, m, u0, beta0, bc.dofs, cfg.re, prec)
+        assert res.converged and len(res.rnorms) <= 8
+        _check_sampled_residual(m, bc.dofs, u, beta, cfg.re, res.rnorms[0], cfg.newton_tol, seed=7 + prec)
+        sols[prec] = u
+        print(f"cavity32 {'mixed' if prec else 'fp64'}: Newton {len(res.rnorms) - 1} steps, "
+              f"GMRES {sum(d['iters'] for d in res.lin)} iterations, {res.seconds:.3f} s")
+    assert rel_fro(sols[B.VMS_MIXED], sols[B.VMS_FP64]) <= 1e-5
+
+
+def test_bfs8_steady_re400_sampled(vms_lib):
+    B = vms_lib
+    cfg, m, u0, beta0, bc = build_workload("bfs8")
+    assert m.n_elems == 1_248_000
+    assert not np.any(bc.dofs % 4 == 3)                 # open outlet: no pressure pin
+    res, u, beta = _solve(B, m, u0, beta0, bc.dofs, 400.0, B.VMS_MIXED, max_newton=15)
+    assert res.converged
+    _check_sampled_residual(m, bc.dofs, u, beta, 400.0, res.rnorms[0], 1e-8, seed=11)
+    print(f"bfs8 Re 400: Newton {len(res.rnorms) - 1} steps, GMRES {sum(d['iters'] for d in res.lin)} "
+          f"iterations, {res.seconds:.2f} s")

@@ -322,3 +322,41 @@ def test_cycle_graph_replays_match_direct_launches(vms_lib, monkeypatch, precisi
         assert torch.equal(x, x_ref), rep
         B.vms_condense_assemble(ctx, to_dev(u), beta, 100.0)          # other work between replays
         torch.cuda.synchronize()
+
+
+def test_empty_mesh_bad_index_and_singular_fine_block(vms_lib):
+    """Edge cases: an empty mesh and a node index out of range are rejected at creation; a
+    state that makes every K_ff singular is reported (VMS_ESINGULAR_KFF), not solved.  On the
+    congruent Kuhn tets of a cube, u = (g x, 0, 0) with g = 2 d / C (d = 2 nu K_b) zeroes two
+    diagonal entries of K_ff = C (G - theta/2 I) + d I in every element (closed-form moments)."""
+    B = vms_lib
+    with pytest.raises(B.VmsError) as e:
+        B.Context(to_dev(np.zeros((4, 3))), to_dev(np.zeros((0, 4), np.int32)), to_dev(np.array([0], np.int32)))
+    assert e.value.code == B.VMS_EINVAL
+    m = kuhn_box((2, 2, 2), (0, 0, 0), (1.0, 1.0, 1.0))
+    bad = m.tets.astype(np.int32).copy()
+    bad[3, 2] = m.n_nodes
+    with pytest.raises(B.VmsError) as e:
+        B.Context(to_dev(m.xyz), to_dev(bad), to_dev(np.array([3], np.int32)))
+    assert e.value.code == B.VMS_EINVAL
+    # closed-form moments of one tet (all six Kuhn tets of a cell are congruent)
+    X = m.xyz[m.tets[0]]
+    J = (X[1:] - X[0]).T
+    vol = abs(np.linalg.det(J)) / 6.0
+    Ginv = np.linalg.inv(J)                      # rows: gradients of the barycentrics 1..3
+    g = np.vstack([-Ginv.sum(axis=0), Ginv])
+    Kb = 4096.0 / 945.0 * vol * np.sum(g * g)
+    C = 8192.0 * vol / 51975.0
+    Re = 1.0
+    gx = 2.0 * (2.0 / Re * Kb) / C
+    u = np.zeros((m.n_nodes, 4))
+    u[:, 0] = gx * m.xyz[:, 0]
+    ctx = make_context(B, m, wall_bc(m), B.VMS_FP64)
+    beta = torch.zeros((m.n_elems, 3), dtype=torch.float64, device=DEV)
+    ud = to_dev(u)
+    with pytest.raises(B.VmsError) as e:
+        B.vms_newton_step(ctx, ud, beta, Re)
+    assert e.value.code == B.VMS_ESINGULAR_KFF and "K_ff singular" in str(e.value)
+    assert torch.equal(ud, to_dev(u))                 # the state is left as it was
+    # a small velocity gradient is regular again
+    B.vms_newton_step(ctx, to_dev(0.01 * u), beta, Re, lin=B.solve_opts(rtol=1e-8, max_iters=20000))
