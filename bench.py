@@ -313,7 +313,7 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=128):
     t0 = time.perf_counter()
     cfg8, m8, u8, b8, bc8 = build_workload("bfs8")
     ctx8 = B.Context(torch.from_numpy(m8.xyz).to(dev), torch.from_numpy(m8.tets).to(dev),
-                     torch.from_numpy(bc8.dofs).to(dev), precision=B.VMS_MIXED)
+                     torch.from_numpy(bc8.dofs).to(dev), precision=B.VMS_MIXED, max_restart=restart)
     lin8 = B.solve_opts(restart=50, rtol=1e-4, max_iters=20000)
     u = torch.from_numpy(u8).to(dev)
     beta = torch.from_numpy(b8).to(dev)
@@ -348,7 +348,8 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=128):
     t1 = time.perf_counter()
     train_set = data + trans[:-1]
     val = [(A, S[0].contiguous()) for A, S in trans[-1:]]
-    weights, train = learned.train_validated(ctx8, train_set, val, steps=300, lr=3e-4, check_every=25)
+    weights, train = learned.train_validated(ctx8, train_set, val, steps=300, lr=3e-4, check_every=25,
+                                             val_restart=min(restart, 128), val_max_iters=60000)
     train["seconds"] = time.perf_counter() - t1
     report["training"] = train
     log(f"training: {train}")

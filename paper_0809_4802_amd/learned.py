@@ -96,13 +96,13 @@ def gmres_iterations(ctx: B.Context, A, b, weights, rtol=1e-4, max_iters=20000, 
 
 
 def train_validated(ctx: B.Context, data, val, steps=200, lr=3e-4, batch=8, seed=1, check_every=20,
-                    val_rtol=1e-4):
+                    val_rtol=1e-4, val_restart=50, val_max_iters=20000):
     """Trains on `data` and keeps the checkpoint with the fewest GMRES iterations on the
     held-out systems `val` (list of (bsr_vals, rhs)); plain block-Jacobi (the zero output
     layer) is one of the candidates, so the result is never worse on the validation set.
     Returns (weights or None for block-Jacobi, report)."""
-    def score(w, cap=20000):
-        return sum(gmres_iterations(ctx, A, b, w, rtol=val_rtol, max_iters=cap) for A, b in val)
+    def score(w, cap=val_max_iters):
+        return sum(gmres_iterations(ctx, A, b, w, rtol=val_rtol, max_iters=cap, restart=val_restart) for A, b in val)
 
     base = score(None)
     cap = max(100, 2 * base // max(1, len(val)))      # a checkpoint slower than 2x block-Jacobi is out
