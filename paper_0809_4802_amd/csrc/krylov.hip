@@ -17,6 +17,7 @@
 // convergence flag only every few steps.
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <vector>
 
 #include "vms_internal.h"
@@ -446,9 +447,13 @@ __global__ __launch_bounds__(kBlock) void full_coarse_setup_kernel(int nn, const
 }
 
 // Publishes the cycle's progress (completed columns k, done flag) to the host-mapped word.
+__device__ __forceinline__ void report_progress(uint64_t* progress, unsigned gen, int k, int done) {
+    const uint64_t word = ((uint64_t)gen << 32) | ((uint64_t)k << 1) | (uint64_t)(done ? 1 : 0);
+    __hip_atomic_store(progress, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __device__ __forceinline__ void report_progress(GmresState* gs, int k, int done) {
-    const uint64_t word = ((uint64_t)gs->gen << 32) | ((uint64_t)k << 1) | (uint64_t)(done ? 1 : 0);
-    __hip_atomic_store(gs->progress, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    report_progress(gs->progress, gs->gen, k, done);
 }
 
 // norm of a vector -> gs->beta, initialises the cycle (g = beta e_1, k = 0, done flag).
@@ -550,12 +555,14 @@ __global__ void coarse_column_kernel(int n_rows, const int32_t* __restrict__ row
 //   dots         slots per (chunk, y): y < j -> (q_y . u_j, q_y . w);  y = j -> (u_j . u_j,
 //                u_j . w);  y = j + 1 -> (w . w, S(w))                          -> part
 //   reduce       (one workgroup) s = Q^T u_j, rho = sqrt(u_j . u_j - |s|^2):  q_j = (u_j - Q s)/rho
-//                is u_j's second pass, so column j-1 becomes final: H(0:j-1, j-1) += hh s,
-//                H(j, j-1) = hh rho (hh: its provisional subdiagonal); Givens rotation, residual
-//                estimate, done flag.  Then column j from the same sums: with t = Q^T w and
-//                c = (t, (u_j . w - s . t) / rho) = Q_j^T w,  H(0:j, j) = (c - H s) / rho, and the
-//                provisional subdiagonal hh = sqrt(w . w - |c|^2) / rho (Pythagoras).
+//                is u_j's second pass.  With t = Q^T w and c = (t, c_j),
+//                c_j = (u_j . w - s . t) / rho = q_j . w, the provisional subdiagonal of column j
+//                is hh = sqrt(w . w - |c|^2) / rho (Pythagoras).
 //   update       q_j = (u_j - Q s) / rho over V[j];  u_{j+1} = (w - Q t - c_j q_j) / (rho hh) to V[j+1]
+//                and, in one extra workgroup, the Hessenberg columns: column j-1 becomes final,
+//                H(0:j-1, j-1) += hh' s and H(j, j-1) = hh' rho (hh': its provisional
+//                subdiagonal), with its Givens rotation, residual estimate and done flag; then
+//                H(0:j, j) = (c - H s) / rho and H(j+1, j) = hh.
 // An estimate that loses digits to cancellation only scales u_{j+1}; the next step measures
 // its norm directly (u . u), so the final subdiagonal hh rho is exact to rounding.  With
 // reorthogonalisation off, s is taken as 0 (one Gram-Schmidt pass, the norm still measured).
@@ -609,33 +616,41 @@ __global__ __launch_bounds__(kDotThreads) void dots_kernel(int n_nodes, int j, c
     }
 }
 
+// Values the Givens rotations read from the cycle state, loaded ahead of the chain.
+struct GivensCtx {
+    double tol_abs;
+    uint64_t* progress;
+    unsigned gen;
+};
+
 // Givens rotation of column jc (held in LDS, rows 0 .. jc+1), with the rotations of columns
-// 0 .. jc-1 in LDS (cl, sl) and gj the rotated right-hand side entry jc; updates R, g, the
-// residual estimate, k and the done flag, and publishes the progress.  Returns 1 when the
-// cycle stops.  Called by one thread; the LDS operands are fetched eight at a time so that
-// only the rotation chain itself is sequential.
-__device__ int givens_column(int jc, const double* col, double* cl, double* sl, double gj, GmresState* gs) {
-    constexpr int ld = kMaxRestart + 1;
-    double* Rj = gs->R + (size_t)jc * ld;
+// 0 .. jc-1 in LDS (cl, sl) and gj the rotated right-hand side entry jc.  The rotated column
+// (rows 0 .. jc) goes to Rl in LDS, for the workgroup to store; the rotation, g, the residual
+// estimate, k and the done flag go to the cycle state, and the progress is published.
+// Returns 1 when the cycle stops.  Called by one thread, which issues no memory access in the
+// chain (inside a launch that streams vectors, every such access would queue behind the
+// stream); the LDS operands are fetched four at a time.
+__device__ int givens_column(int jc, const double* col, double* cl, double* sl, double gj, double* Rl,
+                             const GivensCtx& gc, GmresState* gs) {
     double x = col[0];
     int i = 0;
-    for (; i + 8 <= jc; i += 8) {
-        double c8[8], s8[8], y8[8];
+    for (; i + 4 <= jc; i += 4) {
+        double c4[4], s4[4], y4[4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            c8[q] = cl[i + q];
-            s8[q] = sl[i + q];
-            y8[q] = col[i + q + 1];
+        for (int q = 0; q < 4; ++q) {
+            c4[q] = cl[i + q];
+            s4[q] = sl[i + q];
+            y4[q] = col[i + q + 1];
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            Rj[i + q] = c8[q] * x + s8[q] * y8[q];
-            x = -s8[q] * x + c8[q] * y8[q];
+        for (int q = 0; q < 4; ++q) {
+            Rl[i + q] = c4[q] * x + s4[q] * y4[q];
+            x = -s4[q] * x + c4[q] * y4[q];
         }
     }
     for (; i < jc; ++i) {
         const double yv = col[i + 1];
-        Rj[i] = cl[i] * x + sl[i] * yv;
+        Rl[i] = cl[i] * x + sl[i] * yv;
         x = -sl[i] * x + cl[i] * yv;
     }
     const double hn = col[jc + 1];
@@ -643,9 +658,9 @@ __device__ int givens_column(int jc, const double* col, double* cl, double* sl, 
     const double cs = d > 0.0 ? x / d : 1.0;
     const double sn = d > 0.0 ? hn / d : 0.0;
     const double gnext = -sn * gj;
-    const bool conv = fabs(gnext) <= gs->tol_abs;
+    const bool conv = fabs(gnext) <= gc.tol_abs;
     const bool breakdown = !(hn > 1e-300 * (fabs(d) + 1e-300)) || !isfinite(hn) || !isfinite(gnext);
-    Rj[jc] = d;
+    Rl[jc] = d;
     gs->cs[jc] = cs;
     gs->sn[jc] = sn;
     cl[jc] = cs;
@@ -655,39 +670,36 @@ __device__ int givens_column(int jc, const double* col, double* cl, double* sl, 
     gs->k = jc + 1;
     const int stop = (conv || breakdown) ? 1 : 0;
     if (stop) gs->done = 1;
-    report_progress(gs, jc + 1, stop);
+    report_progress(gc.progress, gc.gen, jc + 1, stop);
     return stop;
 }
 
 
-// Step j's reduction (one workgroup of kRedThreads).  last = 1 at the end of a cycle: only
-// column j-1 is finalised.  Every global value the step needs (the dot slots, columns
-// 0 .. j-1 of H, rotations, pressure sums, flags) is loaded in one predicated round before
-// any is used, so the kernel pays the memory latency about once; slot sums use eight lanes
-// per slot (eight chunks each), H s eight lanes per row.
+// Step j's reduction (one workgroup of kRedThreads): only what the update of step j needs.
+// The dot slots are summed (eight lanes per slot, eight chunks each, all loaded in one
+// predicated round), then one wave forms rho, c_j, the provisional subdiagonal hh, and the
+// free-pressure sums S(q_j), S(u_{j+1}).  The Hessenberg columns and the Givens rotations are
+// left to arnoldi_columns, which runs beside the update.  last = 1 at the end of a cycle: only
+// rho and s (the second pass of the last vector) are produced.
+// eps_dot: relative accuracy of the dot products (precision of the stored vectors); a squared
+// norm that cancels below eps_dot times its input is a numerical breakdown.  A vanished or
+// non-finite rho is stored as 0, which tells the update to write nothing and arnoldi_columns
+// to close the cycle at column j-1.
 constexpr int kRedThreads = 1024;
-constexpr int kHLoads = ((kMaxRestart + 1) * kMaxRestart + kRedThreads - 1) / kRedThreads;
 constexpr int kSlotLanes = 8;                               // lanes per dot slot
 constexpr int kSlotChunks = 64 / kSlotLanes;                // chunks per lane
 constexpr int kSlotGroups = kRedThreads / kSlotLanes;       // slots per round
 constexpr int kSlotRounds = (2 * (kMaxRestart + 2) + kSlotGroups - 1) / kSlotGroups;
 static_assert(kDotChunks <= 64, "a slot has at most 64 chunks");
 
-// eps_dot: relative accuracy of the dot products (precision of the stored vectors); a squared
-// norm that cancels below eps_dot times its input is a numerical breakdown.
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks, const double* __restrict__ part,
                                                              GmresState* gs, int last, double eps_dot) {
-    constexpr int ld = kMaxRestart + 1;
-    const int lh = j + 1;                                  // rows 0 .. j of H in LDS
     __shared__ double sums[2 * (kMaxRestart + 2)];
-    __shared__ double Hl[(kMaxRestart + 1) * kMaxRestart];
-    __shared__ double colj[kMaxRestart + 2];
-    __shared__ double cl[kMaxRestart], sl[kMaxRestart], svl[kMaxRestart + 1];
-    __shared__ double sc[8];
+    __shared__ double svl[kMaxRestart + 1];
+    __shared__ double su_l;
     __shared__ int flags[2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ns = 2 * (j + 2);
-    const int nh = lh * j;
     const int grp = tid / kSlotLanes, sub = tid % kSlotLanes;
     double pv[kSlotRounds][kSlotChunks];
 #pragma unroll
@@ -699,34 +711,11 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks,
             pv[r][c] = (slot < ns && ch < nchunks) ? part[(size_t)slot * kDotChunks + ch] : 0.0;
         }
     }
-    double hv[kHLoads];
-#pragma unroll
-    for (int q = 0; q < kHLoads; ++q) {
-        const int idx = tid + kRedThreads * q;
-        if (idx < nh) {
-            const int l = idx / lh, i = idx - l * lh;
-            hv[q] = gs->H[(size_t)l * ld + i];
-        } else {
-            hv[q] = 0.0;
-        }
-    }
-    if (tid < j) {
-        svl[tid] = gs->svs[tid];
-        if (tid + 1 < j) {
-            cl[tid] = gs->cs[tid];
-            sl[tid] = gs->sn[tid];
-        }
-    }
+    if (tid < j) svl[tid] = gs->svs[tid];
     if (tid == 0) {
         flags[0] = gs->done;
         flags[1] = gs->reorth;
-        sc[5] = j > 0 ? gs->gin[j - 1] : 0.0;
-        sc[6] = gs->su;
-    }
-#pragma unroll
-    for (int q = 0; q < kHLoads; ++q) {
-        const int idx = tid + kRedThreads * q;
-        if (idx < nh) Hl[idx] = hv[q];
+        su_l = gs->su;
     }
 #pragma unroll
     for (int r = 0; r < kSlotRounds; ++r) {
@@ -740,110 +729,205 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks,
     __syncthreads();
     if (flags[0]) return;
     const int reorth = flags[1];
-    // sums: s_i = sums[2i], t_i = sums[2i+1] (i < j); then u.u, u.w, w.w, S(w).
-    // Wave 0 forms |s|^2, s.t, s.S(q), |t|^2, t.S(q) over i < j.
-    if (wave == 0) {
-        double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int i = lane; i < j; i += 64) {
-            const double si = reorth ? sums[2 * i] : 0.0, ti = sums[2 * i + 1], pi = svl[i];
-            a[0] += si * si;
-            a[1] += si * ti;
-            a[2] += si * pi;
-            a[3] += ti * ti;
-            a[4] += ti * pi;
-        }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
-        if (lane == 0) {
-            const double r2 = sums[2 * j] - a[0];
-            sc[0] = j > 0 ? (r2 > eps_dot * sums[2 * j] ? sqrt(r2) : 0.0) : 1.0;     // rho
-            sc[1] = a[1];
-            sc[2] = a[2];
-            sc[3] = a[3];
-            sc[4] = a[4];
-        }
-    }
-    __syncthreads();
-    const double rho = sc[0];
-    if (j > 0) {
-        // u_j's second pass completes column j-1
-        double* Hc = Hl + (size_t)(j - 1) * lh;
-        const double hh = Hc[j];
-        if (reorth)
-            for (int i = tid; i < j; i += kRedThreads) Hc[i] += hh * sums[2 * i];
-        __syncthreads();
-        if (tid == 0) {
-            Hc[j] = hh * rho;
-            int st = givens_column(j - 1, Hc, cl, sl, sc[5], gs);
-            if (!(rho > 0.0) || !isfinite(rho)) {
-                st = 1;                  // u_j vanished: column j-1 closes the cycle
-                gs->done = 1;
-                report_progress(gs, j, 1);
-            }
-            svl[j] = rho > 0.0 ? (sc[6] - sc[2]) / rho : 0.0;     // S(q_j)
-            gs->svs[j] = svl[j];
-            flags[0] = st;
-        }
-        __syncthreads();
-        for (int i = tid; i <= j; i += kRedThreads) gs->H[(size_t)(j - 1) * ld + i] = Hc[i];
-        if (flags[0] || last) return;
-    } else {
-        if (tid == 0) {
-            svl[0] = sc[6];
-            gs->svs[0] = sc[6];
-        }
-        if (last) return;
-    }
-    // column j: c = (t, c_j) = Q_j^T w, H(0:j, j) = (c - H s) / rho
-    const double cj = (sums[2 * j + 1] - sc[1]) / rho;
-    for (int i0 = 0; i0 <= j; i0 += kSlotGroups) {
-        const int i = i0 + grp;
-        double hs = 0.0;
-        if (reorth && i <= j)
-            for (int l = max(0, i - 1) + sub; l < j; l += kSlotLanes) hs += Hl[(size_t)l * lh + i] * sums[2 * l];
-        hs = group8_sum(hs);
-        if (sub == 0 && i <= j) {
-            const double ci = i < j ? sums[2 * i + 1] : cj;
-            const double h = (ci - hs) / rho;
-            colj[i] = h;
-            gs->H[(size_t)j * ld + i] = h;
-        }
-    }
+    // sums: s_i = sums[2i], t_i = sums[2i+1] (i < j); then u.u, u.w, w.w, S(w)
     for (int i = tid; i < j; i += kRedThreads) {
         gs->tcoef[i] = sums[2 * i + 1];
         gs->scoef[i] = reorth ? sums[2 * i] : 0.0;
     }
-    __syncthreads();
-    if (tid == 0) {
-        const double cc = sc[3] + cj * cj;                 // |c|^2
-        const double pw = sums[2 * j + 3] - sc[4] - cj * svl[j];
-        const double h2 = sums[2 * j + 2] - cc;
-        const double hh = h2 > eps_dot * sums[2 * j + 2] ? sqrt(h2) / rho : 0.0;
-        gs->H[(size_t)j * ld + j + 1] = hh;
-        gs->rho = rho;
-        gs->cj = cj;
-        gs->hh = hh;
-        gs->su = hh > 0.0 ? pw / (rho * hh) : 0.0;     // S(u_{j+1})
-        if (!(hh > 0.0) || !isfinite(hh)) {
-            // the Krylov space is invariant: column j is final with a zero subdiagonal
-            colj[j + 1] = 0.0;
-            givens_column(j, colj, cl, sl, gs->gin[j], gs);
-            gs->done = 1;
-            report_progress(gs, j + 1, 1);
-        }
+    if (wave != 0) return;
+    // |s|^2, s.t, s.S(q), |t|^2, t.S(q) over i < j
+    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = lane; i < j; i += 64) {
+        const double si = reorth ? sums[2 * i] : 0.0, ti = sums[2 * i + 1], pi = svl[i];
+        a[0] += si * si;
+        a[1] += si * ti;
+        a[2] += si * pi;
+        a[3] += ti * ti;
+        a[4] += ti * pi;
     }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
+    if (lane != 0) return;
+    const double r2 = sums[2 * j] - a[0];
+    double rho = j > 0 ? (r2 > eps_dot * sums[2 * j] ? sqrt(r2) : 0.0) : 1.0;
+    if (!(rho > 0.0) || !isfinite(rho)) rho = 0.0;
+    const double svj = j == 0 ? su_l : (rho > 0.0 ? (su_l - a[2]) / rho : 0.0);     // S(q_j)
+    gs->svs[j] = svj;
+    gs->rho = rho;
+    if (last || rho == 0.0) return;
+    // c = (t, c_j) = Q_j^T w; hh = sqrt(w.w - |c|^2) / rho (Pythagoras)
+    const double cj = (sums[2 * j + 1] - a[1]) / rho;
+    const double cc = a[3] + cj * cj;
+    const double pw = sums[2 * j + 3] - a[4] - cj * svj;
+    const double h2 = sums[2 * j + 2] - cc;
+    double hh = h2 > eps_dot * sums[2 * j + 2] ? sqrt(h2) / rho : 0.0;
+    if (!isfinite(hh)) hh = 0.0;
+    gs->cj = cj;
+    gs->hh = hh;
+    gs->su = hh > 0.0 ? pw / (rho * hh) : 0.0;     // S(u_{j+1})
 }
 
-// q_j = (u_j - Q s) / rho written over V[j];  u_{j+1} = (w - Q t - c_j q_j) / (rho hh) to V[j+1].
-// One element per thread; the basis is read once, in batches of eight vectors.  The
-// coefficients are uniform across the grid and come through scalar loads.
+// Sum over the four lanes of an aligned group (every lane gets it; all lanes active).
+__device__ __forceinline__ double group4_sum(double v) {
+    v += dpp_mov<0xB1>(v);
+    return v + dpp_mov<0x4E>(v);
+}
+
+// The Hessenberg bookkeeping of step j, for one workgroup of kBlock threads.  It needs the
+// outputs of step j's reduction, and nothing of the Arnoldi recurrence waits for it, so it
+// runs as an extra workgroup of the update launch (and, for the tail, as a launch of its own).
+//  * u_j's second pass makes column j-1 final: H(0:j-1, j-1) += hh' s and H(j, j-1) = hh' rho,
+//    hh' being the provisional subdiagonal stored at step j-1; its Givens rotation gives the
+//    residual estimate, k = j and, on convergence or breakdown, the done flag.
+//  * column j: H(0:j, j) = (c - H s) / rho with c = (t, c_j), H(j+1, j) = hh.  A zero hh means
+//    an invariant Krylov space: column j is final and closes the cycle.
+// Every value is loaded in one round before the first test, the columns 0 .. j-2 that H s needs
+// included (lane = row, wave w = the columns l = w mod 4, kFirst of them per lane; more in
+// batches).  Column j is written even when column j-1 closes the cycle: it lies beyond the
+// final basis and the next cycle rebuilds it.  last = 1: only column j-1.
+__device__ void arnoldi_columns(int j, GmresState* gs, int last) {
+    constexpr int ld = kMaxRestart + 1;
+    constexpr int kWaves = kBlock / 64;
+    constexpr int kFirst = 12;                          // H loads per lane in the first round
+    constexpr int kBatch = 4;                           // then per batch
+    static_assert(kMaxRestart <= 128 && kBlock >= 64 + kMaxRestart, "two row passes; rows on waves 1..");
+    __shared__ double Hc[kMaxRestart + 2];              // column j-1, final
+    __shared__ double colj[kMaxRestart + 2];            // column j
+    __shared__ double sv[kMaxRestart];                  // s
+    __shared__ double cl[kMaxRestart], sl[kMaxRestart];
+    __shared__ double hpart[kWaves][kMaxRestart];       // H s, per column class
+    __shared__ double Rl[2][kMaxRestart + 1];           // rotated columns j-1 and j
+    __shared__ int flags[1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = tid - 64;                             // row of column j (waves 1 ..)
+    const bool hs_on = !last && j > 1;                  // columns 0 .. j-2 take part in H s
+    const int done = gs->done;
+    const int reorth = gs->reorth;
+    const double rho = gs->rho, hh = gs->hh, cj = gs->cj;
+    const double gprev = j > 0 ? gs->gin[j - 1] : 0.0;
+    const double hprev = j > 0 ? gs->H[(size_t)(j - 1) * ld + j] : 0.0;
+    const GivensCtx gc{gs->tol_abs, gs->progress, gs->gen};
+    double s_t = 0.0, hp = 0.0, cs_t = 0.0, sn_t = 0.0, t_r = 0.0;
+    if (tid < j) {
+        s_t = gs->scoef[tid];
+        hp = gs->H[(size_t)(j - 1) * ld + tid];
+    }
+    if (tid + 1 < j) {
+        cs_t = gs->cs[tid];
+        sn_t = gs->sn[tid];
+    }
+    if (!last && r >= 0 && r < j) t_r = gs->tcoef[r];
+    double hv[kFirst];
+#pragma unroll
+    for (int q = 0; q < kFirst; ++q) {
+        const int l = wave + kWaves * q;
+        hv[q] = (hs_on && l <= j - 2 && lane <= l + 1) ? gs->H[(size_t)l * ld + lane] : 0.0;
+    }
+    if (done) return;                                   // uniform: written by an earlier launch
+    if (tid < j) sv[tid] = reorth ? s_t : 0.0;
+    if (tid + 1 < j) {
+        cl[tid] = cs_t;
+        sl[tid] = sn_t;
+    }
+    __syncthreads();
+    if (j > 0 && tid <= j) {
+        const double h = tid < j ? hp + hprev * sv[tid] : hprev * rho;
+        Hc[tid] = h;
+        gs->H[(size_t)(j - 1) * ld + tid] = h;
+    }
+    if (hs_on) {
+        double acc[2] = {0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < kFirst; ++q) {
+            const int l = wave + kWaves * q;
+            if (l <= j - 2) acc[0] += hv[q] * sv[l];
+        }
+        for (int p = 0; p < 2; ++p) {
+            const int i = lane + 64 * p;
+            if (i > j) break;
+            const int lbeg = wave + (p == 0 ? kWaves * kFirst : kWaves * (63 / kWaves));
+            for (int l0 = lbeg; l0 <= j - 2; l0 += kWaves * kBatch) {
+                double hb[kBatch];
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    const int l = l0 + kWaves * q;
+                    hb[q] = (l <= j - 2 && i <= l + 1) ? gs->H[(size_t)l * ld + i] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    const int l = l0 + kWaves * q;
+                    if (l <= j - 2) acc[p] += hb[q] * sv[l];
+                }
+            }
+        }
+        if (lane <= j) hpart[wave][lane] = acc[0];
+        if (lane + 64 <= j) hpart[wave][lane + 64] = acc[1];
+    }
+    __syncthreads();
+    // wave 0: the rotation of column j-1;  waves 1 ..: column j
+    if (tid == 0) {
+        int st = 0;
+        if (j > 0) {
+            st = givens_column(j - 1, Hc, cl, sl, gprev, Rl[0], gc, gs);
+            if (!(rho > 0.0)) {
+                st = 1;                      // u_j vanished: column j-1 closes the cycle
+                gs->done = 1;
+                report_progress(gc.progress, gc.gen, j, 1);
+            }
+        }
+        flags[0] = st;
+    }
+    const bool col_on = !last && rho > 0.0;
+    if (col_on && r >= 0 && r <= j) {
+        double hs = 0.0;
+        if (j > 0 && reorth) {
+            if (hs_on)
+                for (int w = 0; w < kWaves; ++w) hs += hpart[w][r];
+            hs += Hc[r] * sv[j - 1];
+        }
+        const double h = ((r < j ? t_r : cj) - hs) / rho;
+        colj[r] = h;
+        gs->H[(size_t)j * ld + r] = h;
+        if (r == j) gs->H[(size_t)j * ld + j + 1] = hh;
+    }
+    __syncthreads();
+    if (j > 0 && tid < j) gs->R[(size_t)(j - 1) * ld + tid] = Rl[0][tid];
+    if (!(col_on && !flags[0] && !(hh > 0.0))) return;  // uniform
+    // the Krylov space is invariant: column j is final with a zero subdiagonal
+    if (tid == 0) {
+        colj[j + 1] = 0.0;
+        givens_column(j, colj, cl, sl, gs->gin[j], Rl[1], gc, gs);
+        gs->done = 1;
+        report_progress(gc.progress, gc.gen, j + 1, 1);
+    }
+    __syncthreads();
+    if (tid <= j) gs->R[(size_t)j * ld + tid] = Rl[1][tid];
+}
+
+// The tail of a cycle: column j-1 from the last vector's second pass.
+__global__ __launch_bounds__(kBlock) void columns_kernel(int j, GmresState* gs) { arnoldi_columns(j, gs, 1); }
+
+// Workgroup 0 runs arnoldi_columns for step j.  The others: q_j = (u_j - Q s) / rho written
+// over V[j];  u_{j+1} = (w - Q t - c_j q_j) / (rho hh) to V[j+1], one element per thread; the
+// basis is read once, in batches of eight vectors.  The coefficients ss = s, ts = t and
+// rcj = (rho, c_j, hh) are uniform across the grid and read-only in this launch (workgroup 0
+// writes other fields of the cycle state), so they come through scalar loads.  Nothing is
+// written once the cycle is done or rho has vanished, and u_{j+1} not when hh has (invariant
+// space: q_j is the last basis vector).  The done flag that workgroup 0 may set during this
+// launch only decides whether vectors beyond the final basis are written.
+static_assert(offsetof(GmresState, cj) == offsetof(GmresState, rho) + sizeof(double) &&
+                  offsetof(GmresState, hh) == offsetof(GmresState, rho) + 2 * sizeof(double),
+              "rho, c_j, hh are read as one array");
 template <typename T>
 __global__ __launch_bounds__(kBlock) void update_kernel(int n, int j, T* __restrict__ V, const T* __restrict__ w,
-                                                        const GmresState* gs) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+                                                        const double* __restrict__ ss, const double* __restrict__ ts,
+                                                        const double* __restrict__ rcj, GmresState* gs) {
+    if (blockIdx.x == 0) {
+        arnoldi_columns(j, gs, 0);
+        return;
+    }
+    const int idx = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
     if (idx >= n) return;
-    const double* __restrict__ ss = gs->scoef;
-    const double* __restrict__ ts = gs->tcoef;
     const size_t N = (size_t)n;
     T* uj = V + (size_t)j * N;
     double aq = double(uj[idx]), aw = double(w[idx]);
@@ -863,11 +947,12 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int n, int j, T* __restr
         aq -= ss[i] * v;
         aw -= ts[i] * v;
     }
-    if (gs->done) return;
-    const double rho = gs->rho;
+    const double rho = rcj[0];
+    if (gs->done || !(rho > 0.0)) return;
     const double q = aq / rho;
     uj[idx] = T(q);
-    V[(size_t)(j + 1) * N + idx] = T((aw - gs->cj * q) / (rho * gs->hh));
+    const double hh = rcj[2];
+    if (hh > 0.0) V[(size_t)(j + 1) * N + idx] = T((aw - rcj[1] * q) / (rho * hh));
 }
 
 // y = R^{-1} g for the k x k triangle of the rotated Hessenberg matrix (one workgroup): the
@@ -1123,13 +1208,15 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
             });
             reduce_kernel<<<1, kRedThreads, 0, st>>>(j, nch, part, c->gs, 0, eps_dot);
             timed(VMS_PH_UPDATE, (j + 4) * vb, j, st, [&] {
-                update_kernel<T><<<grid_for(n), kBlock, 0, st>>>(n, j, V, w, c->gs);
+                update_kernel<T><<<1 + grid_for(n), kBlock, 0, st>>>(n, j, V, w, c->gs->scoef, c->gs->tcoef,
+                                                                      &c->gs->rho, c->gs);
             });
         }
         // the second pass of the last vector completes the last column
         dots_kernel<T><<<dim3(nch, steps_ + 2), kDotThreads, 0, st>>>(c->n_nodes, steps_, V, w, c->dmask, part,
                                                                       c->gs);
         reduce_kernel<<<1, kRedThreads, 0, st>>>(steps_, nch, part, c->gs, 1, eps_dot);
+        columns_kernel<<<1, kBlock, 0, st>>>(steps_, c->gs);
         return VMS_OK;
     };
     // With the phase timers on, every prof_every-th cycle is launched directly and every launch
