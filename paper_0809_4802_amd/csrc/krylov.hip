@@ -27,6 +27,15 @@ namespace {
 
 inline int grid_for(int64_t n, int block = kBlock) { return (int)((n + block - 1) / block); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id, and each XCD has its own
+// L2, which keeps its lines across kernel boundaries.  The Arnoldi kernels (SpMV, dots, update)
+// give XCD k the k-th eighth of the rows, so that the slices of a vector one of them writes
+// and the next one reads (and most SpMV gathers, the mesh being numbered brick by brick) stay
+// in the same XCD's L2: slot of workgroup b in a grid of g (a multiple of 8).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_slot(int b, int g) { return (b % kXcds) * (g / kXcds) + b / kXcds; }
+inline int xcd_round(int g) { return (g + kXcds - 1) / kXcds * kXcds; }
+
 // Lane exchanges of a double by DPP (two 32-bit moves; no LDS round trip).  CTRL: a
 // quad_perm pattern, or 0x140 (row_mirror: lane i <-> 15 - i in a row of 16) and 0x141
 // (row_half_mirror: lane i <-> 7 - i in a group of 8).  Every lane of the wave must be active.
@@ -84,7 +93,8 @@ __global__ void fill_kernel(uint4* p, size_t n16) {
 // any is used, so that its loads are in flight together (a row of this mesh has at most 15
 // blocks, i.e. 8 per lane); the two halves of a row are summed with one lane exchange.
 // MODE 0: y = A x.  MODE 1: y = b - A x.  MODE 2: y = A x + (kappa S) b with kappa and S (the
-// coarse pressure scale and the free-pressure sum of x) taken from the GMRES state.
+// coarse pressure scale and the free-pressure sum of x) taken from the GMRES state.  Workgroups
+// take their rows through xcd_slot (grid from spmv_grid, a multiple of 8).
 constexpr int kSpmvLanes = 8;
 constexpr int kSpmvUnroll = 8;
 template <typename TA, typename TX, typename TY, typename TACC, int MODE, typename TB = double>
@@ -99,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
     constexpr int Q = kSpmvLanes / 4;
     using VA = typename Vec4<TA>::type;
     using VX = typename Vec4<TX>::type;
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tid = xcd_slot(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int row = tid / kSpmvLanes, sub = tid % kSpmvLanes;
     const int q = sub >> 2, r = sub & 3;
     TACC acc = TACC(0);
@@ -145,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
     }
 }
 
-inline int spmv_grid(int n_rows) { return (int)(((int64_t)kSpmvLanes * n_rows + kBlock - 1) / kBlock); }
+inline int spmv_grid(int n_rows) { return xcd_round((int)(((int64_t)kSpmvLanes * n_rows + kBlock - 1) / kBlock)); }
 
 // --------------------------------------------------------------------------- block-Jacobi
 // Inverse of each 4x4 diagonal block in FP64 (Gauss-Jordan, partial pivoting),
@@ -566,6 +576,8 @@ __global__ void coarse_column_kernel(int n_rows, const int32_t* __restrict__ row
 // An estimate that loses digits to cancellation only scales u_{j+1}; the next step measures
 // its norm directly (u . u), so the final subdiagonal hh rho is exact to rounding.  With
 // reorthogonalisation off, s is taken as 0 (one Gram-Schmidt pass, the norm still measured).
+// The chunks of a slot go to the XCDs through xcd_slot (when their count is a multiple of 8),
+// matching the rows the update and the SpMV give each XCD.
 constexpr int kDotChunks = VMS_DOT_CHUNKS;       // workgroups per dot product
 constexpr int kDotThreads = 256;
 static_assert(2 * (kMaxRestart + 2) * kDotChunks <= kRedBlocks * (kMaxRestart + 1), "dot slots exceed scratch");
@@ -584,7 +596,8 @@ __global__ __launch_bounds__(kDotThreads) void dots_kernel(int n_nodes, int j, c
     const V4* w4 = reinterpret_cast<const V4*>(w);
     const V4* q4 = reinterpret_cast<const V4*>(V) + (size_t)(kind == 0 ? y : 0) * N4;
     const int per = (n_nodes + gridDim.x - 1) / gridDim.x;
-    const int i0 = blockIdx.x * per, i1 = min(n_nodes, i0 + per);
+    const int chunk = gridDim.x % kXcds == 0 ? xcd_slot(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int i0 = chunk * per, i1 = min(n_nodes, i0 + per);
     double a0 = 0.0, a1 = 0.0;
     for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         const V4 b = w4[i];
@@ -612,7 +625,7 @@ __global__ __launch_bounds__(kDotThreads) void dots_kernel(int n_nodes, int j, c
     if (threadIdx.x < 2 && !skip) {
         double t = 0.0;
         for (int k = 0; k < kDotThreads / 64; ++k) t += lds[threadIdx.x][k];
-        part[(size_t)(2 * y + threadIdx.x) * kDotChunks + blockIdx.x] = t;
+        part[(size_t)(2 * y + threadIdx.x) * kDotChunks + chunk] = t;
     }
 }
 
@@ -926,7 +939,11 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int n, int j, T* __restr
         arnoldi_columns(j, gs, 0);
         return;
     }
-    const int idx = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+    // workgroup b >= 1 runs on XCD b % 8; slot ((b - 1) % 8 + 1) % 8 * g8 + (b - 1) / 8 is a
+    // bijection onto 0 .. 8 g8 - 1 that gives XCD k the k-th eighth (as xcd_slot)
+    const int g8 = (gridDim.x - 1) / kXcds, bb = blockIdx.x - 1;
+    const int slot = ((bb % kXcds + 1) % kXcds) * g8 + bb / kXcds;
+    const int idx = slot * blockDim.x + threadIdx.x;
     if (idx >= n) return;
     const size_t N = (size_t)n;
     T* uj = V + (size_t)j * N;
@@ -1208,7 +1225,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
             });
             reduce_kernel<<<1, kRedThreads, 0, st>>>(j, nch, part, c->gs, 0, eps_dot);
             timed(VMS_PH_UPDATE, (j + 4) * vb, j, st, [&] {
-                update_kernel<T><<<1 + grid_for(n), kBlock, 0, st>>>(n, j, V, w, c->gs->scoef, c->gs->tcoef,
+                update_kernel<T><<<1 + xcd_round(grid_for(n)), kBlock, 0, st>>>(n, j, V, w, c->gs->scoef, c->gs->tcoef,
                                                                       &c->gs->rho, c->gs);
             });
         }
