@@ -973,27 +973,30 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int n, int j, T* __restr
 }
 
 // y = R^{-1} g for the k x k triangle of the rotated Hessenberg matrix (one workgroup): the
-// triangle is staged in LDS, then one wave eliminates column by column, lane l holding entries
-// l and l + 64 of the right-hand side.
+// triangle and the reciprocals of its diagonal are staged in LDS, then one wave eliminates
+// column by column, lane l holding entries l and l + 64 of the right-hand side; the pivot
+// entry is broadcast with readlane, so the sequential chain is a multiply and an FMA per column.
 __global__ __launch_bounds__(kBlock) void backsub_kernel(GmresState* gs) {
     const int k = gs->k;
     if (k == 0) return;
     constexpr int ld = kMaxRestart + 1;
     __shared__ double Rl[kMaxRestart * kMaxRestart];
-    __shared__ double gl[kMaxRestart];
+    __shared__ double rinv[kMaxRestart];
     for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
         const int col = idx / k, row = idx - col * k;
         if (row <= col) Rl[idx] = gs->R[(size_t)col * ld + row];
     }
-    for (int i = threadIdx.x; i < k; i += blockDim.x) gl[i] = gs->g[i];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) rinv[i] = 1.0 / gs->R[(size_t)i * ld + i];
+    double g0 = 0.0, g1 = 0.0;
+    if (threadIdx.x < 64) {
+        g0 = threadIdx.x < k ? gs->g[threadIdx.x] : 0.0;
+        g1 = threadIdx.x + 64 < k ? gs->g[threadIdx.x + 64] : 0.0;
+    }
     __syncthreads();
     if (threadIdx.x >= 64) return;
     const int l = threadIdx.x;
-    double g0 = l < k ? gl[l] : 0.0;
-    double g1 = l + 64 < k ? gl[l + 64] : 0.0;
     for (int col = k - 1; col >= 0; --col) {
-        const double gc = __shfl(col < 64 ? g0 : g1, col & 63, 64);
-        const double yc = gc / Rl[col * k + col];
+        const double yc = read_lane(col < 64 ? g0 : g1, col & 63) * rinv[col];
         if (l == 0) gs->y[col] = yc;
         if (l < col) g0 -= Rl[col * k + l] * yc;
         if (l + 64 < col) g1 -= Rl[col * k + l + 64] * yc;
@@ -1009,7 +1012,7 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(int n, const T* __restr
     __shared__ double ys[kMaxRestart];
     for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = gs->y[i];
     __syncthreads();
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = xcd_slot(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;   // basis slices in this XCD's L2
     if (idx >= n) return;
     const size_t N = (size_t)n;
     double sacc = 0.0;
@@ -1276,7 +1279,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     }
     // y = R^{-1} g on the device
     backsub_kernel<<<1, kBlock, 0, s>>>(c->gs);
-    combine_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, V, c->gs, z);
+    combine_kernel<T><<<xcd_round(grid_for(n)), kBlock, 0, s>>>(n, V, c->gs, z);
     free_pressure_sum_kernel<T><<<red_grid(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, z, c->dmask, c->red, c->gs);
     precond_accumulate_kernel<T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, c->dmask, c->zfull, c->gs,
                                                                     x);
