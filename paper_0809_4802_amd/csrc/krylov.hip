@@ -580,7 +580,49 @@ __global__ void coarse_column_kernel(int n_rows, const int32_t* __restrict__ row
 // matching the rows the update and the SpMV give each XCD.
 constexpr int kDotChunks = VMS_DOT_CHUNKS;       // workgroups per dot product
 constexpr int kDotThreads = 256;
+constexpr int kDotUnrollF32 = 3;     // strides per pass for FP32 vectors (FP64: 1, register-bound)
 static_assert(2 * (kMaxRestart + 2) * kDotChunks <= kRedBlocks * (kMaxRestart + 1), "dot slots exceed scratch");
+
+// One thread's share of a chunk [i0, i1) of one dot slot: KIND 0 (q . u, q . w), 1 (u . u, u . w),
+// 2 (w . w, S(w)).  kDotUnroll strides per pass, all loaded before any is used; indices past
+// the chunk are clamped to its last node and weighted 0 (no branch around a load).  Three
+// strides for FP32 vectors (the slot's loads then take one memory round at 32^3); FP64 keeps
+// one, where nine 32-byte loads in flight cost more occupancy than they save.
+template <int KIND, typename V4>
+__device__ __forceinline__ void dot_chunk(const V4* __restrict__ q4, const V4* __restrict__ u4,
+                                          const V4* __restrict__ w4, const uint8_t* __restrict__ dmask, int i0,
+                                          int i1, double& a0, double& a1) {
+    constexpr int kDotUnroll = sizeof(V4) <= 16 ? kDotUnrollF32 : 1;
+    for (int ib = i0 + (int)threadIdx.x; ib < i1; ib += kDotUnroll * (int)blockDim.x) {
+        V4 bv[kDotUnroll], xv[kDotUnroll], uv[kDotUnroll];
+        uint8_t mk[kDotUnroll];
+#pragma unroll
+        for (int r = 0; r < kDotUnroll; ++r) {
+            const int i = min(ib + r * (int)blockDim.x, i1 - 1);
+            bv[r] = w4[i];
+            if (KIND == 0) xv[r] = q4[i];
+            if (KIND <= 1) uv[r] = u4[i];
+            if (KIND == 2) mk[r] = dmask[i];
+        }
+#pragma unroll
+        for (int r = 0; r < kDotUnroll; ++r) {
+            const double wt = ib + r * (int)blockDim.x < i1 ? 1.0 : 0.0;
+            const V4 b = bv[r];
+            if (KIND == 0) {
+                const V4 q = xv[r], u = uv[r];
+                a0 += wt * double(q.x * u.x + q.y * u.y + q.z * u.z + q.w * u.w);
+                a1 += wt * double(q.x * b.x + q.y * b.y + q.z * b.z + q.w * b.w);
+            } else if (KIND == 1) {
+                const V4 u = uv[r];
+                a0 += wt * double(u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w);
+                a1 += wt * double(u.x * b.x + u.y * b.y + u.z * b.z + u.w * b.w);
+            } else {
+                a0 += wt * double(b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w);
+                a1 += (mk[r] & 8u) ? 0.0 : wt * double(b.w);
+            }
+        }
+    }
+}
 
 template <typename T>
 __global__ __launch_bounds__(kDotThreads) void dots_kernel(int n_nodes, int j, const T* __restrict__ V,
@@ -599,21 +641,12 @@ __global__ __launch_bounds__(kDotThreads) void dots_kernel(int n_nodes, int j, c
     const int chunk = gridDim.x % kXcds == 0 ? xcd_slot(blockIdx.x, gridDim.x) : blockIdx.x;
     const int i0 = chunk * per, i1 = min(n_nodes, i0 + per);
     double a0 = 0.0, a1 = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        const V4 b = w4[i];
-        if (kind == 0) {
-            const V4 q = q4[i], u = u4[i];
-            a0 += double(q.x * u.x + q.y * u.y + q.z * u.z + q.w * u.w);
-            a1 += double(q.x * b.x + q.y * b.y + q.z * b.z + q.w * b.w);
-        } else if (kind == 1) {
-            const V4 u = u4[i];
-            a0 += double(u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w);
-            a1 += double(u.x * b.x + u.y * b.y + u.z * b.z + u.w * b.w);
-        } else {
-            a0 += double(b.x * b.x + b.y * b.y + b.z * b.z + b.w * b.w);
-            if (!(dmask[i] & 8u)) a1 += double(b.w);
-        }
-    }
+    if (kind == 0)
+        dot_chunk<0>(q4, u4, w4, dmask, i0, i1, a0, a1);
+    else if (kind == 1)
+        dot_chunk<1>(q4, u4, w4, dmask, i0, i1, a0, a1);
+    else
+        dot_chunk<2>(q4, u4, w4, dmask, i0, i1, a0, a1);
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
     __shared__ double lds[2][kDotThreads / 64];
