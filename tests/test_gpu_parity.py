@@ -135,6 +135,38 @@ def test_gmres_fp64_true_residual_and_direct(vms_lib):
     assert np.all(xs[bc.dofs] == 0.0)
 
 
+def test_gmres_long_restart_and_single_pass(vms_lib):
+    """Cavity 8^3, FP64 and mixed: GMRES(128) (cycles longer than 64 steps: the Hessenberg
+    bookkeeping's second row pass and its batched column loads) and GMRES(50) with one
+    Gram-Schmidt pass reach the requested true residual of the assembled matrix (checked on
+    the host in FP64); FP64 matches a sparse direct solve of the same matrix within
+    kappa * rtol (kappa_1 ~ 1.3e5)."""
+    import scipy.sparse.linalg as spl
+    B = vms_lib
+    m = cavity_mesh(8)
+    bc = cavity_bc(m)
+    u = np.zeros((m.n_nodes, 4))
+    apply_dirichlet(u, bc)
+    beta = np.zeros((m.n_elems, 3))
+    for prec, rtol in ((B.VMS_FP64, 1e-11), (B.VMS_MIXED, 1e-10)):
+        ctx = make_context(B, m, bc.dofs, prec, max_restart=128)
+        A_g, b_g, _ = B.vms_condense_assemble(ctx, to_dev(u), to_dev(beta), 100.0)
+        A_m = bsr_to_csr(ctx, A_g)
+        b_m = b_g.cpu().numpy().ravel()
+        x_d = spl.splu(A_m.tocsc()).solve(b_m)
+        for restart, cgs2 in ((128, 1), (50, 0)):
+            x = ctx.new_vec()
+            rc, info = B.vms_gmres_solve(ctx, A_g, b_g, x, B.solve_opts(restart=restart, rtol=rtol, max_iters=20000,
+                                                                        cgs2=cgs2))
+            xs = x.cpu().numpy().ravel()
+            assert rc == B.VMS_OK and info.true_rel_res <= rtol, (prec, restart, cgs2, info.true_rel_res)
+            assert np.linalg.norm(b_m - A_m @ xs) <= 1.01 * rtol * np.linalg.norm(b_m), (prec, restart, cgs2)
+            if restart == 128:
+                assert info.iters > 64, info.iters
+            if prec == B.VMS_FP64:
+                assert np.linalg.norm(xs - x_d) <= 1e-5 * np.linalg.norm(x_d), (restart, cgs2)
+
+
 def test_gmres_mixed_refinement(vms_lib):
     B = vms_lib
     m, bc, u, ctx = _cavity(4, 100.0, B.VMS_MIXED, B)
