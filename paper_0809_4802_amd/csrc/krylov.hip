@@ -567,16 +567,20 @@ __global__ void coarse_column_kernel(int n_rows, const int32_t* __restrict__ row
 //   arnoldi_pc   z = P u_j (block inverse + coarse pressure term, S(u_j) carried in gs)
 //   spmv         w = A z = B u_j
 //   dots         slots per (chunk, y): y < j -> (q_y . u_j, q_y . w);  y = j -> (u_j . u_j,
-//                u_j . w);  y = j + 1 -> (w . w, S(w))                          -> part
-//   reduce       (one workgroup) s = Q^T u_j, rho = sqrt(u_j . u_j - |s|^2):  q_j = (u_j - Q s)/rho
-//                is u_j's second pass.  With t = Q^T w and c = (t, c_j),
-//                c_j = (u_j . w - s . t) / rho = q_j . w, the provisional subdiagonal of column j
-//                is hh = sqrt(w . w - |c|^2) / rho (Pythagoras).
-//   update       q_j = (u_j - Q s) / rho over V[j];  u_{j+1} = (w - Q t - c_j q_j) / (rho hh) to V[j+1]
-//                and, in one extra workgroup, the Hessenberg columns: column j-1 becomes final,
+//                u_j . w);  y = j + 1 -> (w . w, S(w))    -> part[slot][chunk], stride = chunks
+//   update       every workgroup sums the slots itself (step_scalars, same order everywhere):
+//                s = Q^T u_j, rho = sqrt(u_j . u_j - |s|^2), so that q_j = (u_j - Q s)/rho is
+//                u_j's second pass; with t = Q^T w and c = (t, c_j), c_j = (u_j . w - s . t) / rho
+//                = q_j . w, and the provisional subdiagonal of column j is
+//                hh = sqrt(w . w - |c|^2) / rho (Pythagoras).  Then q_j = (u_j - Q s) / rho over
+//                V[j] and u_{j+1} = (w - Q t - c_j q_j) / (rho hh) to V[j+1].  Workgroup 0
+//                instead does the Hessenberg columns (arnoldi_columns): column j-1 becomes final,
 //                H(0:j-1, j-1) += hh' s and H(j, j-1) = hh' rho (hh': its provisional
 //                subdiagonal), with its Givens rotation, residual estimate and done flag; then
 //                H(0:j, j) = (c - H s) / rho and H(j+1, j) = hh.
+// Three launches per step (a separate one-workgroup reduction cost more than every update
+// workgroup summing the partials of kFusedChunks chunks again).  The tail of a cycle, the
+// second pass of the last vector, is dots + reduce_kernel + columns_kernel.
 // An estimate that loses digits to cancellation only scales u_{j+1}; the next step measures
 // its norm directly (u . u), so the final subdiagonal hh rho is exact to rounding.  With
 // reorthogonalisation off, s is taken as 0 (one Gram-Schmidt pass, the norm still measured).
@@ -586,6 +590,7 @@ constexpr int kDotChunks = VMS_DOT_CHUNKS;       // workgroups per dot product
 constexpr int kDotThreads = 256;
 constexpr int kDotUnrollF32 = 3;     // strides per pass for FP32 vectors (FP64: 1, register-bound)
 static_assert(2 * (kMaxRestart + 2) * kDotChunks <= kRedBlocks * (kMaxRestart + 1), "dot slots exceed scratch");
+
 
 // One thread's share of a chunk [i0, i1) of one dot slot: KIND 0 (q . u, q . w), 1 (u . u, u . w),
 // 2 (w . w, S(w)).  kDotUnroll strides per pass, all loaded before any is used; indices past
@@ -662,7 +667,7 @@ __global__ __launch_bounds__(kDotThreads) void dots_kernel(int n_nodes, int j, c
     if (threadIdx.x < 2 && !skip) {
         double t = 0.0;
         for (int k = 0; k < kDotThreads / 64; ++k) t += lds[threadIdx.x][k];
-        part[(size_t)(2 * y + threadIdx.x) * kDotChunks + chunk] = t;
+        part[(size_t)(2 * y + threadIdx.x) * gridDim.x + chunk] = t;
     }
 }
 
@@ -725,16 +730,14 @@ __device__ int givens_column(int jc, const double* col, double* cl, double* sl, 
 }
 
 
-// Step j's reduction (one workgroup of kRedThreads): only what the update of step j needs.
-// The dot slots are summed (eight lanes per slot, eight chunks each, all loaded in one
-// predicated round), then one wave forms rho, c_j, the provisional subdiagonal hh, and the
-// free-pressure sums S(q_j), S(u_{j+1}).  The Hessenberg columns and the Givens rotations are
-// left to arnoldi_columns, which runs beside the update.  last = 1 at the end of a cycle: only
-// rho and s (the second pass of the last vector) are produced.
-// eps_dot: relative accuracy of the dot products (precision of the stored vectors); a squared
-// norm that cancels below eps_dot times its input is a numerical breakdown.  A vanished or
-// non-finite rho is stored as 0, which tells the update to write nothing and arnoldi_columns
-// to close the cycle at column j-1.
+// The tail of a cycle (one workgroup of kRedThreads): the dot slots of the last vector u_m are
+// summed (eight lanes per slot, eight chunks each, loaded in one predicated round), and one wave
+// forms rho (the norm of u_m after its second pass), S(q_m) and s, which arnoldi_columns needs
+// to make column m-1 final.  eps_dot: relative accuracy of the dot products (precision of the
+// stored vectors); a squared norm that cancels below eps_dot times its input is a numerical
+// breakdown.  A vanished or non-finite rho is stored as 0, which makes arnoldi_columns close
+// the cycle at column m-1.  (Inside a cycle the update launch forms the same sums itself,
+// step_scalars below.)
 constexpr int kRedThreads = 1024;
 constexpr int kSlotLanes = 8;                               // lanes per dot slot
 constexpr int kSlotChunks = 64 / kSlotLanes;                // chunks per lane
@@ -743,7 +746,7 @@ constexpr int kSlotRounds = (2 * (kMaxRestart + 2) + kSlotGroups - 1) / kSlotGro
 static_assert(kDotChunks <= 64, "a slot has at most 64 chunks");
 
 __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks, const double* __restrict__ part,
-                                                             GmresState* gs, int last, double eps_dot) {
+                                                             GmresState* gs, double eps_dot) {
     __shared__ double sums[2 * (kMaxRestart + 2)];
     __shared__ double svl[kMaxRestart + 1];
     __shared__ double su_l;
@@ -758,7 +761,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks,
 #pragma unroll
         for (int c = 0; c < kSlotChunks; ++c) {
             const int ch = sub * kSlotChunks + c;
-            pv[r][c] = (slot < ns && ch < nchunks) ? part[(size_t)slot * kDotChunks + ch] : 0.0;
+            pv[r][c] = (slot < ns && ch < nchunks) ? part[(size_t)slot * nchunks + ch] : 0.0;
         }
     }
     if (tid < j) svl[tid] = gs->svs[tid];
@@ -779,42 +782,24 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(int j, int nchunks,
     __syncthreads();
     if (flags[0]) return;
     const int reorth = flags[1];
-    // sums: s_i = sums[2i], t_i = sums[2i+1] (i < j); then u.u, u.w, w.w, S(w)
-    for (int i = tid; i < j; i += kRedThreads) {
-        gs->tcoef[i] = sums[2 * i + 1];
-        gs->scoef[i] = reorth ? sums[2 * i] : 0.0;
-    }
+    // sums: s_i = sums[2i] (i < j), then u.u at 2j (the t slots are not used here)
+    for (int i = tid; i < j; i += kRedThreads) gs->scoef[i] = reorth ? sums[2 * i] : 0.0;
     if (wave != 0) return;
-    // |s|^2, s.t, s.S(q), |t|^2, t.S(q) over i < j
-    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // |s|^2 and s.S(q) over i < j
+    double a[2] = {0.0, 0.0};
     for (int i = lane; i < j; i += 64) {
-        const double si = reorth ? sums[2 * i] : 0.0, ti = sums[2 * i + 1], pi = svl[i];
+        const double si = reorth ? sums[2 * i] : 0.0;
         a[0] += si * si;
-        a[1] += si * ti;
-        a[2] += si * pi;
-        a[3] += ti * ti;
-        a[4] += ti * pi;
+        a[1] += si * svl[i];
     }
-#pragma unroll
-    for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
+    a[0] = wave_sum(a[0]);
+    a[1] = wave_sum(a[1]);
     if (lane != 0) return;
     const double r2 = sums[2 * j] - a[0];
     double rho = j > 0 ? (r2 > eps_dot * sums[2 * j] ? sqrt(r2) : 0.0) : 1.0;
     if (!(rho > 0.0) || !isfinite(rho)) rho = 0.0;
-    const double svj = j == 0 ? su_l : (rho > 0.0 ? (su_l - a[2]) / rho : 0.0);     // S(q_j)
-    gs->svs[j] = svj;
+    gs->svs[j] = j == 0 ? su_l : (rho > 0.0 ? (su_l - a[1]) / rho : 0.0);     // S(q_j)
     gs->rho = rho;
-    if (last || rho == 0.0) return;
-    // c = (t, c_j) = Q_j^T w; hh = sqrt(w.w - |c|^2) / rho (Pythagoras)
-    const double cj = (sums[2 * j + 1] - a[1]) / rho;
-    const double cc = a[3] + cj * cj;
-    const double pw = sums[2 * j + 3] - a[4] - cj * svj;
-    const double h2 = sums[2 * j + 2] - cc;
-    double hh = h2 > eps_dot * sums[2 * j + 2] ? sqrt(h2) / rho : 0.0;
-    if (!isfinite(hh)) hh = 0.0;
-    gs->cj = cj;
-    gs->hh = hh;
-    gs->su = hh > 0.0 ? pw / (rho * hh) : 0.0;     // S(u_{j+1})
 }
 
 // Sum over the four lanes of an aligned group (every lane gets it; all lanes active).
@@ -824,8 +809,10 @@ __device__ __forceinline__ double group4_sum(double v) {
 }
 
 // The Hessenberg bookkeeping of step j, for one workgroup of kBlock threads.  It needs the
-// outputs of step j's reduction, and nothing of the Arnoldi recurrence waits for it, so it
-// runs as an extra workgroup of the update launch (and, for the tail, as a launch of its own).
+// step's sums, and nothing of the Arnoldi recurrence waits for it, so it runs as workgroup 0 of
+// the update launch, with the sums that workgroup formed in LDS (in), and, for the cycle's
+// tail, as a launch of its own after reduce_kernel (in = nullptr: column j-1 only, inputs from
+// the cycle state).
 //  * u_j's second pass makes column j-1 final: H(0:j-1, j-1) += hh' s and H(j, j-1) = hh' rho,
 //    hh' being the provisional subdiagonal stored at step j-1; its Givens rotation gives the
 //    residual estimate, k = j and, on convergence or breakdown, the done flag.
@@ -834,8 +821,14 @@ __device__ __forceinline__ double group4_sum(double v) {
 // Every value is loaded in one round before the first test, the columns 0 .. j-2 that H s needs
 // included (lane = row, wave w = the columns l = w mod 4, kFirst of them per lane; more in
 // batches).  Column j is written even when column j-1 closes the cycle: it lies beyond the
-// final basis and the next cycle rebuilds it.  last = 1: only column j-1.
-__device__ void arnoldi_columns(int j, GmresState* gs, int last) {
+// final basis and the next cycle rebuilds it.
+struct StepIn {
+    const double* sums;     // s_i = sums[2i] (before the reorthogonalisation switch), t_i = sums[2i+1]
+    double rho, cj, hh;
+    int reorth;
+};
+
+__device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
     constexpr int ld = kMaxRestart + 1;
     constexpr int kWaves = kBlock / 64;
     constexpr int kFirst = 12;                          // H loads per lane in the first round
@@ -850,23 +843,24 @@ __device__ void arnoldi_columns(int j, GmresState* gs, int last) {
     __shared__ int flags[1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = tid - 64;                             // row of column j (waves 1 ..)
+    const bool last = in == nullptr;                    // the tail: column j-1 only
     const bool hs_on = !last && j > 1;                  // columns 0 .. j-2 take part in H s
-    const int done = gs->done;
-    const int reorth = gs->reorth;
-    const double rho = gs->rho, hh = gs->hh, cj = gs->cj;
+    const int done = in ? 0 : gs->done;                 // the fused update has tested it
+    const int reorth = in ? in->reorth : gs->reorth;
+    const double rho = in ? in->rho : gs->rho, hh = in ? in->hh : gs->hh, cj = in ? in->cj : gs->cj;
     const double gprev = j > 0 ? gs->gin[j - 1] : 0.0;
     const double hprev = j > 0 ? gs->H[(size_t)(j - 1) * ld + j] : 0.0;
     const GivensCtx gc{gs->tol_abs, gs->progress, gs->gen};
     double s_t = 0.0, hp = 0.0, cs_t = 0.0, sn_t = 0.0, t_r = 0.0;
     if (tid < j) {
-        s_t = gs->scoef[tid];
+        s_t = in ? in->sums[2 * tid] : gs->scoef[tid];
         hp = gs->H[(size_t)(j - 1) * ld + tid];
     }
     if (tid + 1 < j) {
         cs_t = gs->cs[tid];
         sn_t = gs->sn[tid];
     }
-    if (!last && r >= 0 && r < j) t_r = gs->tcoef[r];
+    if (!last && r >= 0 && r < j) t_r = in->sums[2 * r + 1];
     double hv[kFirst];
 #pragma unroll
     for (int q = 0; q < kFirst; ++q) {
@@ -955,58 +949,173 @@ __device__ void arnoldi_columns(int j, GmresState* gs, int last) {
 }
 
 // The tail of a cycle: column j-1 from the last vector's second pass.
-__global__ __launch_bounds__(kBlock) void columns_kernel(int j, GmresState* gs) { arnoldi_columns(j, gs, 1); }
+__global__ __launch_bounds__(kBlock) void columns_kernel(int j, GmresState* gs) { arnoldi_columns(j, gs, nullptr); }
 
-// Workgroup 0 runs arnoldi_columns for step j.  The others: q_j = (u_j - Q s) / rho written
-// over V[j];  u_{j+1} = (w - Q t - c_j q_j) / (rho hh) to V[j+1], one element per thread; the
-// basis is read once, in batches of eight vectors.  The coefficients ss = s, ts = t and
-// rcj = (rho, c_j, hh) are uniform across the grid and read-only in this launch (workgroup 0
-// writes other fields of the cycle state), so they come through scalar loads.  Nothing is
-// written once the cycle is done or rho has vanished, and u_{j+1} not when hh has (invariant
-// space: q_j is the last basis vector).  The done flag that workgroup 0 may set during this
-// launch only decides whether vectors beyond the final basis are written.
-static_assert(offsetof(GmresState, cj) == offsetof(GmresState, rho) + sizeof(double) &&
-                  offsetof(GmresState, hh) == offsetof(GmresState, rho) + 2 * sizeof(double),
-              "rho, c_j, hh are read as one array");
+// ------------------------------------------------------------- fused step (3 launches per step)
+// The update launch forms the step's sums itself: every workgroup reads the dot partials
+// (kFusedChunks per slot, four lanes per slot) and forms rho, c_j, hh exactly as the reduction
+// kernel does, in the same order everywhere, so all workgroups agree bitwise.  The basis loads
+// of the first batch are issued before, and wait out, that work.  Workgroup 0 also stores the
+// free-pressure sums S(q_j), S(u_{j+1}) for later steps and runs arnoldi_columns from LDS.
+constexpr int kFusedChunks = 16;                                     // dot partials per slot
+constexpr int kFusedLanes = 4;                                       // lanes per slot
+constexpr int kFusedPer = kFusedChunks / kFusedLanes;                // partials per lane
+constexpr int kFusedSlots = kBlock / kFusedLanes;                    // slots per round
+constexpr int kFusedRounds = (2 * (kMaxRestart + 2) + kFusedSlots - 1) / kFusedSlots;
+static_assert(kFusedChunks % kXcds == 0 && kFusedChunks <= kDotChunks, "fused dot chunks");
+
+struct StepLds {
+    double sums[2 * (kMaxRestart + 2)];
+    double svl[kMaxRestart + 1];
+    double sc[6];           // rho, c_j, hh, S(u_j) in, S(u_{j+1}), S(q_j)
+    int flags[2];           // done, reorth
+};
+
+// Returns false (uniformly) when the cycle is done.  Every thread of the workgroup calls it.
+__device__ __forceinline__ bool step_scalars(int j, int nchunks, const double* __restrict__ part, const GmresState* gs,
+                             double eps_dot, StepLds& L) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ns = 2 * (j + 2);
+    const int grp = tid / kFusedLanes, sub = tid % kFusedLanes;
+    // part[slot][0 .. nchunks) is contiguous (stride nchunks): lane sub of a slot reads its
+    // kFusedPer consecutive partials.  Only the rounds that hold slots are issued; inside one,
+    // every load is unconditional (slot and chunk clamped to valid ones) and weighted 0 when
+    // absent, since a load under a per-lane condition becomes a branch with a full wait.
+    const int rounds = (ns + kFusedSlots - 1) / kFusedSlots;
+    double pv[kFusedRounds][kFusedPer];
+#pragma unroll
+    for (int r = 0; r < kFusedRounds; ++r) {
+        const int slot = grp + kFusedSlots * r;
+        const size_t base = (size_t)min(slot, ns - 1) * nchunks;
+#pragma unroll
+        for (int c = 0; c < kFusedPer; ++c) pv[r][c] = 0.0;
+        if (r < rounds) {
+#pragma unroll
+            for (int c = 0; c < kFusedPer; ++c) {
+                const int ch = sub * kFusedPer + c;
+                const double wt = (slot < ns && ch < nchunks) ? 1.0 : 0.0;
+                pv[r][c] = wt * part[base + min(ch, nchunks - 1)];
+            }
+        }
+    }
+    if (tid < j) L.svl[tid] = gs->svs[tid];
+    if (tid == 0) {
+        L.flags[0] = gs->done;
+        L.flags[1] = gs->reorth;
+        L.sc[3] = gs->su;
+    }
+#pragma unroll
+    for (int r = 0; r < kFusedRounds; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int c = 0; c < kFusedPer; ++c) a += pv[r][c];
+        a = group4_sum(a);
+        const int slot = grp + kFusedSlots * r;
+        if (sub == 0 && slot < ns) L.sums[slot] = a;
+    }
+    __syncthreads();
+    if (L.flags[0]) return false;
+    const int reorth = L.flags[1];
+    if (wave == 0) {
+        double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int i = lane; i < j; i += 64) {
+            const double si = reorth ? L.sums[2 * i] : 0.0, ti = L.sums[2 * i + 1], pi = L.svl[i];
+            a[0] += si * si;
+            a[1] += si * ti;
+            a[2] += si * pi;
+            a[3] += ti * ti;
+            a[4] += ti * pi;
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
+        if (lane == 0) {
+            const double su = L.sc[3];
+            const double r2 = L.sums[2 * j] - a[0];
+            double rho = j > 0 ? (r2 > eps_dot * L.sums[2 * j] ? sqrt(r2) : 0.0) : 1.0;
+            if (!(rho > 0.0) || !isfinite(rho)) rho = 0.0;
+            const double svj = j == 0 ? su : (rho > 0.0 ? (su - a[2]) / rho : 0.0);
+            double cj = 0.0, hh = 0.0, sun = 0.0;
+            if (rho > 0.0) {
+                cj = (L.sums[2 * j + 1] - a[1]) / rho;
+                const double cc = a[3] + cj * cj;
+                const double pw = L.sums[2 * j + 3] - a[4] - cj * svj;
+                const double h2 = L.sums[2 * j + 2] - cc;
+                hh = h2 > eps_dot * L.sums[2 * j + 2] ? sqrt(h2) / rho : 0.0;
+                if (!isfinite(hh)) hh = 0.0;
+                sun = hh > 0.0 ? pw / (rho * hh) : 0.0;
+            }
+            L.sc[0] = rho;
+            L.sc[1] = cj;
+            L.sc[2] = hh;
+            L.sc[4] = sun;
+            L.sc[5] = svj;
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void update_kernel(int n, int j, T* __restrict__ V, const T* __restrict__ w,
-                                                        const double* __restrict__ ss, const double* __restrict__ ts,
-                                                        const double* __restrict__ rcj, GmresState* gs) {
+__global__ __launch_bounds__(kBlock) void update_fused_kernel(int n, int j, T* __restrict__ V,
+                                                              const T* __restrict__ w, int nchunks,
+                                                              const double* __restrict__ part, GmresState* gs,
+                                                              double eps_dot) {
+    __shared__ StepLds L;
     if (blockIdx.x == 0) {
-        arnoldi_columns(j, gs, 0);
+        if (!step_scalars(j, nchunks, part, gs, eps_dot, L)) return;
+        if (threadIdx.x == 0) {
+            gs->rho = L.sc[0];
+            gs->cj = L.sc[1];
+            gs->hh = L.sc[2];
+            gs->su = L.sc[4];       // S(u_{j+1}); the other workgroups read only S(u_j), unused there
+            gs->svs[j] = L.sc[5];
+        }
+        const StepIn in{L.sums, L.sc[0], L.sc[1], L.sc[2], L.flags[1]};
+        arnoldi_columns(j, gs, &in);
         return;
     }
-    // workgroup b >= 1 runs on XCD b % 8; slot ((b - 1) % 8 + 1) % 8 * g8 + (b - 1) / 8 is a
-    // bijection onto 0 .. 8 g8 - 1 that gives XCD k the k-th eighth (as xcd_slot)
     const int g8 = (gridDim.x - 1) / kXcds, bb = blockIdx.x - 1;
     const int slot = ((bb % kXcds + 1) % kXcds) * g8 + bb / kXcds;
     const int idx = slot * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
+    const bool live = idx < n;
+    const int ix = live ? idx : n - 1;            // every thread takes part in the step's sums
     const size_t N = (size_t)n;
     T* uj = V + (size_t)j * N;
-    double aq = double(uj[idx]), aw = double(w[idx]);
-    int i = 0;
+    const double u0 = double(uj[ix]), w0 = double(w[ix]);
+    T v0[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v0[q] = V[(size_t)min(q, max(j - 1, 0)) * N + ix];
+    if (!step_scalars(j, nchunks, part, gs, eps_dot, L)) return;
+    const bool reorth = L.flags[1] != 0;
+    double aq = u0, aw = w0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        if (q < j) {
+            aq -= (reorth ? L.sums[2 * q] : 0.0) * double(v0[q]);
+            aw -= L.sums[2 * q + 1] * double(v0[q]);
+        }
+    }
+    int i = 8;
     for (; i + 8 <= j; i += 8) {
         double vv[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) vv[q] = double(V[(size_t)(i + q) * N + idx]);
+        for (int q = 0; q < 8; ++q) vv[q] = double(V[(size_t)(i + q) * N + ix]);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            aq -= ss[i + q] * vv[q];
-            aw -= ts[i + q] * vv[q];
+            aq -= (reorth ? L.sums[2 * (i + q)] : 0.0) * vv[q];
+            aw -= L.sums[2 * (i + q) + 1] * vv[q];
         }
     }
     for (; i < j; ++i) {
-        const double v = double(V[(size_t)i * N + idx]);
-        aq -= ss[i] * v;
-        aw -= ts[i] * v;
+        const double v = double(V[(size_t)i * N + ix]);
+        aq -= (reorth ? L.sums[2 * i] : 0.0) * v;
+        aw -= L.sums[2 * i + 1] * v;
     }
-    const double rho = rcj[0];
-    if (gs->done || !(rho > 0.0)) return;
+    const double rho = L.sc[0], cj = L.sc[1], hh = L.sc[2];
+    if (!live || !(rho > 0.0)) return;
     const double q = aq / rho;
     uj[idx] = T(q);
-    const double hh = rcj[2];
-    if (hh > 0.0) V[(size_t)(j + 1) * N + idx] = T((aw - rcj[1] * q) / (rho * hh));
+    if (hh > 0.0) V[(size_t)(j + 1) * N + idx] = T((aw - cj * q) / (rho * hh));
 }
 
 // y = R^{-1} g for the k x k triangle of the rotated Hessenberg matrix (one workgroup): the
@@ -1228,7 +1337,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     const int steps = std::min(m, budget);
     const double vb = (double)n * sizeof(T);      // bytes of one Krylov vector
     const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 3.0 * vb;
-    const int nch = std::max(1, std::min(kDotChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
+    const int nch = std::max(1, std::min(kFusedChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
     double* part = c->red->partial;
     const double eps_dot = sizeof(T) == 8 ? 1e-14 : 1e-6;
     // timed launches per step, so that steps issued after convergence (their kernels return
@@ -1263,16 +1372,15 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
                 dots_kernel<T><<<dim3(nch, j + 2), kDotThreads, 0, st>>>(c->n_nodes, j, V, w, c->dmask, part,
                                                                          c->gs);
             });
-            reduce_kernel<<<1, kRedThreads, 0, st>>>(j, nch, part, c->gs, 0, eps_dot);
             timed(VMS_PH_UPDATE, (j + 4) * vb, j, st, [&] {
-                update_kernel<T><<<1 + xcd_round(grid_for(n)), kBlock, 0, st>>>(n, j, V, w, c->gs->scoef, c->gs->tcoef,
-                                                                      &c->gs->rho, c->gs);
+                update_fused_kernel<T><<<1 + xcd_round(grid_for(n)), kBlock, 0, st>>>(n, j, V, w, nch, part, c->gs,
+                                                                                    eps_dot);
             });
         }
         // the second pass of the last vector completes the last column
         dots_kernel<T><<<dim3(nch, steps_ + 2), kDotThreads, 0, st>>>(c->n_nodes, steps_, V, w, c->dmask, part,
                                                                       c->gs);
-        reduce_kernel<<<1, kRedThreads, 0, st>>>(steps_, nch, part, c->gs, 1, eps_dot);
+        reduce_kernel<<<1, kRedThreads, 0, st>>>(steps_, nch, part, c->gs, eps_dot);
         columns_kernel<<<1, kBlock, 0, st>>>(steps_, c->gs);
         return VMS_OK;
     };

@@ -59,8 +59,7 @@ struct GmresState {
     double g[kMaxRestart + 1];     // rotated right-hand side (final entries)
     double gin[kMaxRestart + 1];   // entry i before rotation i (gin[k] = residual estimate)
     double y[kMaxRestart];
-    double scoef[kMaxRestart];     // s = Q^T u_j: second-pass coefficients of the current step
-    double tcoef[kMaxRestart];     // t = Q^T w: first-pass coefficients of the current step
+    double scoef[kMaxRestart];     // s = Q^T u_m: second-pass coefficients of a cycle's last vector
     double svs[kMaxRestart + 1];   // free-pressure sum of every final basis vector
     double tol_abs;                // stop when |g[k]| <= tol_abs
     double beta;                   // norm of the cycle's initial residual
