@@ -967,14 +967,20 @@ static_assert(kFusedChunks % kXcds == 0 && kFusedChunks <= kDotChunks, "fused do
 struct StepLds {
     double sums[2 * (kMaxRestart + 2)];
     double svl[kMaxRestart + 1];
-    double sc[6];           // rho, c_j, hh, S(u_j) in, S(u_{j+1}), S(q_j)
+    double su;              // S(u_j)
     int flags[2];           // done, reorth
+};
+
+struct StepOut {
+    double rho, cj, hh;
+    double su_next;         // S(u_{j+1})
+    double svj;             // S(q_j)
 };
 
 // Returns false (uniformly) when the cycle is done.  Every thread of the workgroup calls it.
 __device__ __forceinline__ bool step_scalars(int j, int nchunks, const double* __restrict__ part, const GmresState* gs,
-                             double eps_dot, StepLds& L) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+                                             double eps_dot, StepLds& L, StepOut& o) {
+    const int tid = threadIdx.x, lane = tid & 63;
     const int ns = 2 * (j + 2);
     const int grp = tid / kFusedLanes, sub = tid % kFusedLanes;
     // part[slot][0 .. nchunks) is contiguous (stride nchunks): lane sub of a slot reads its
@@ -1002,7 +1008,7 @@ __device__ __forceinline__ bool step_scalars(int j, int nchunks, const double* _
     if (tid == 0) {
         L.flags[0] = gs->done;
         L.flags[1] = gs->reorth;
-        L.sc[3] = gs->su;
+        L.su = gs->su;
     }
 #pragma unroll
     for (int r = 0; r < kFusedRounds; ++r) {
@@ -1015,43 +1021,36 @@ __device__ __forceinline__ bool step_scalars(int j, int nchunks, const double* _
     }
     __syncthreads();
     if (L.flags[0]) return false;
+    // every wave forms the scalars itself (the wave sums leave them in every lane), so that no
+    // second barrier is needed; all lanes and workgroups do the same operations in the same order
     const int reorth = L.flags[1];
-    if (wave == 0) {
-        double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int i = lane; i < j; i += 64) {
-            const double si = reorth ? L.sums[2 * i] : 0.0, ti = L.sums[2 * i + 1], pi = L.svl[i];
-            a[0] += si * si;
-            a[1] += si * ti;
-            a[2] += si * pi;
-            a[3] += ti * ti;
-            a[4] += ti * pi;
-        }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
-        if (lane == 0) {
-            const double su = L.sc[3];
-            const double r2 = L.sums[2 * j] - a[0];
-            double rho = j > 0 ? (r2 > eps_dot * L.sums[2 * j] ? sqrt(r2) : 0.0) : 1.0;
-            if (!(rho > 0.0) || !isfinite(rho)) rho = 0.0;
-            const double svj = j == 0 ? su : (rho > 0.0 ? (su - a[2]) / rho : 0.0);
-            double cj = 0.0, hh = 0.0, sun = 0.0;
-            if (rho > 0.0) {
-                cj = (L.sums[2 * j + 1] - a[1]) / rho;
-                const double cc = a[3] + cj * cj;
-                const double pw = L.sums[2 * j + 3] - a[4] - cj * svj;
-                const double h2 = L.sums[2 * j + 2] - cc;
-                hh = h2 > eps_dot * L.sums[2 * j + 2] ? sqrt(h2) / rho : 0.0;
-                if (!isfinite(hh)) hh = 0.0;
-                sun = hh > 0.0 ? pw / (rho * hh) : 0.0;
-            }
-            L.sc[0] = rho;
-            L.sc[1] = cj;
-            L.sc[2] = hh;
-            L.sc[4] = sun;
-            L.sc[5] = svj;
-        }
+    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = lane; i < j; i += 64) {
+        const double si = reorth ? L.sums[2 * i] : 0.0, ti = L.sums[2 * i + 1], pi = L.svl[i];
+        a[0] += si * si;
+        a[1] += si * ti;
+        a[2] += si * pi;
+        a[3] += ti * ti;
+        a[4] += ti * pi;
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 5; ++q) a[q] = wave_sum(a[q]);
+    const double su = L.su;
+    const double r2 = L.sums[2 * j] - a[0];
+    double rho = j > 0 ? (r2 > eps_dot * L.sums[2 * j] ? sqrt(r2) : 0.0) : 1.0;
+    if (!(rho > 0.0) || !isfinite(rho)) rho = 0.0;
+    const double svj = j == 0 ? su : (rho > 0.0 ? (su - a[2]) / rho : 0.0);
+    double cj = 0.0, hh = 0.0, sun = 0.0;
+    if (rho > 0.0) {
+        cj = (L.sums[2 * j + 1] - a[1]) / rho;
+        const double cc = a[3] + cj * cj;
+        const double pw = L.sums[2 * j + 3] - a[4] - cj * svj;
+        const double h2 = L.sums[2 * j + 2] - cc;
+        hh = h2 > eps_dot * L.sums[2 * j + 2] ? sqrt(h2) / rho : 0.0;
+        if (!isfinite(hh)) hh = 0.0;
+        sun = hh > 0.0 ? pw / (rho * hh) : 0.0;
+    }
+    o = StepOut{rho, cj, hh, sun, svj};
     return true;
 }
 
@@ -1061,16 +1060,17 @@ __global__ __launch_bounds__(kBlock) void update_fused_kernel(int n, int j, T* _
                                                               const double* __restrict__ part, GmresState* gs,
                                                               double eps_dot) {
     __shared__ StepLds L;
+    StepOut o;
     if (blockIdx.x == 0) {
-        if (!step_scalars(j, nchunks, part, gs, eps_dot, L)) return;
+        if (!step_scalars(j, nchunks, part, gs, eps_dot, L, o)) return;
         if (threadIdx.x == 0) {
-            gs->rho = L.sc[0];
-            gs->cj = L.sc[1];
-            gs->hh = L.sc[2];
-            gs->su = L.sc[4];       // S(u_{j+1}); the other workgroups read only S(u_j), unused there
-            gs->svs[j] = L.sc[5];
+            gs->rho = o.rho;
+            gs->cj = o.cj;
+            gs->hh = o.hh;
+            gs->su = o.su_next;     // S(u_{j+1}); the other workgroups read only S(u_j), unused there
+            gs->svs[j] = o.svj;
         }
-        const StepIn in{L.sums, L.sc[0], L.sc[1], L.sc[2], L.flags[1]};
+        const StepIn in{L.sums, o.rho, o.cj, o.hh, L.flags[1]};
         arnoldi_columns(j, gs, &in);
         return;
     }
@@ -1085,7 +1085,7 @@ __global__ __launch_bounds__(kBlock) void update_fused_kernel(int n, int j, T* _
     T v0[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) v0[q] = V[(size_t)min(q, max(j - 1, 0)) * N + ix];
-    if (!step_scalars(j, nchunks, part, gs, eps_dot, L)) return;
+    if (!step_scalars(j, nchunks, part, gs, eps_dot, L, o)) return;
     const bool reorth = L.flags[1] != 0;
     double aq = u0, aw = w0;
 #pragma unroll
@@ -1111,7 +1111,7 @@ __global__ __launch_bounds__(kBlock) void update_fused_kernel(int n, int j, T* _
         aq -= (reorth ? L.sums[2 * i] : 0.0) * v;
         aw -= L.sums[2 * i + 1] * v;
     }
-    const double rho = L.sc[0], cj = L.sc[1], hh = L.sc[2];
+    const double rho = o.rho, cj = o.cj, hh = o.hh;
     if (!live || !(rho > 0.0)) return;
     const double q = aq / rho;
     uj[idx] = T(q);
