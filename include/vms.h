@@ -290,7 +290,9 @@ enum {
     VMS_PH_PCAPPLY = 4,        /* A P formed once per solve (the Arnoldi SpMV applies P)  */
     VMS_PH_SPMV = 5,           /* block-CSR SpMV with A P in the Arnoldi step             */
     VMS_PH_DOTS = 6,           /* Gram-Schmidt dot products (Q^T u, Q^T w, norms)         */
-    VMS_PH_UPDATE = 7,         /* Gram-Schmidt update (q_j and the next vector)           */
+    VMS_PH_UPDATE = 7,         /* Gram-Schmidt update (q_j and the next vector), with the
+                                  step's sums of the dot partials and the Hessenberg
+                                  columns and Givens rotations in one of its workgroups     */
     VMS_PH_FILL = 8,           /* zero fill of the assembled outputs                      */
     VMS_NPHASES = 9
 };
