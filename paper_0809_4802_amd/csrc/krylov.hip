@@ -1119,7 +1119,8 @@ __global__ __launch_bounds__(kBlock) void update_fused_kernel(int n, int j, T* _
 }
 
 // y = R^{-1} g for the k x k triangle of the rotated Hessenberg matrix (one workgroup): the
-// triangle and the reciprocals of its diagonal are staged in LDS, then one wave eliminates
+// triangle and the reciprocals of its diagonal are staged in LDS (column batches, loads in
+// flight together), then one wave eliminates
 // column by column, lane l holding entries l and l + 64 of the right-hand side; the pivot
 // entry is broadcast with readlane, so the sequential chain is a multiply and an FMA per column.
 __global__ __launch_bounds__(kBlock) void backsub_kernel(GmresState* gs) {
@@ -1128,11 +1129,28 @@ __global__ __launch_bounds__(kBlock) void backsub_kernel(GmresState* gs) {
     constexpr int ld = kMaxRestart + 1;
     __shared__ double Rl[kMaxRestart * kMaxRestart];
     __shared__ double rinv[kMaxRestart];
-    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-        const int col = idx / k, row = idx - col * k;
-        if (row <= col) Rl[idx] = gs->R[(size_t)col * ld + row];
+    // staging: lane = row (two halves), wave w = the columns col = w mod 4, eight columns of a
+    // lane loaded before any is stored (clamped column, so no branch around a load)
+    constexpr int kWaves = kBlock / 64, kCols = 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c0 = wave; c0 < k; c0 += kWaves * kCols) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int row = lane + 64 * half;
+            if (row >= k) break;
+            double rv[kCols];
+#pragma unroll
+            for (int q = 0; q < kCols; ++q) rv[q] = gs->R[(size_t)min(c0 + kWaves * q, k - 1) * ld + row];
+#pragma unroll
+            for (int q = 0; q < kCols; ++q) {
+                const int col = c0 + kWaves * q;
+                if (col < k && row <= col) {
+                    Rl[col * k + row] = rv[q];
+                    if (row == col) rinv[col] = 1.0 / rv[q];
+                }
+            }
+        }
     }
-    for (int i = threadIdx.x; i < k; i += blockDim.x) rinv[i] = 1.0 / gs->R[(size_t)i * ld + i];
     double g0 = 0.0, g1 = 0.0;
     if (threadIdx.x < 64) {
         g0 = threadIdx.x < k ? gs->g[threadIdx.x] : 0.0;
