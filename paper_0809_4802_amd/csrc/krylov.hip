@@ -586,7 +586,7 @@ __global__ void coarse_column_kernel(int n_rows, const int32_t* __restrict__ row
 // reorthogonalisation off, s is taken as 0 (one Gram-Schmidt pass, the norm still measured).
 // The chunks of a slot go to the XCDs through xcd_slot (when their count is a multiple of 8),
 // matching the rows the update and the SpMV give each XCD.
-constexpr int kDotChunks = VMS_DOT_CHUNKS;       // workgroups per dot product
+constexpr int kDotChunks = VMS_DOT_CHUNKS;       // bound on the chunks (partials) per dot slot
 constexpr int kDotThreads = 256;
 constexpr int kDotUnrollF32 = 3;     // strides per pass for FP32 vectors (FP64: 1, register-bound)
 static_assert(2 * (kMaxRestart + 2) * kDotChunks <= kRedBlocks * (kMaxRestart + 1), "dot slots exceed scratch");

@@ -18,7 +18,7 @@ constexpr int kBlock = 256;          // threads per workgroup for streaming kern
 constexpr int kRedBlocks = 1024;     // workgroups of the grid-wide reductions
 constexpr int kMaxRestart = 128;
 #ifndef VMS_DOT_CHUNKS
-#define VMS_DOT_CHUNKS 64          // workgroups per GMRES dot product
+#define VMS_DOT_CHUNKS 64          // upper bound on the workgroups (partials) per GMRES dot slot
 #endif
 constexpr int kTileNodes = 64;           // max nodes owned by one assembly tile
 #ifndef VMS_TILE_BLOCKS_FP64
