@@ -263,11 +263,14 @@ static int create_full_system(vms_ctx* c, const std::vector<int32_t>& tets, cons
     FTRY(dev_alloc(f, &f->tvec, 3 * N * sizeof(float), "alloc full tvec"));
     FTRY(dev_alloc(f, &f->gs, sizeof(GmresState), "alloc full gmres state"));
     FTRY(dev_alloc(f, &f->red, sizeof(RedScratch), "alloc full reduction scratch"));
-    FTRY(check_hip(f, hipHostMalloc(reinterpret_cast<void**>(&f->progress_host), 64,
+    FTRY(check_hip(f, hipHostMalloc(reinterpret_cast<void**>(&f->progress_host), 128,
                                     hipHostMallocMapped | hipHostMallocCoherent), "alloc progress word"));
     FTRY(check_hip(f, hipHostGetDevicePointer(reinterpret_cast<void**>(&f->progress_dev), f->progress_host, 0),
                    "map progress word"));
     *f->progress_host = 0;
+    f->scal_host = reinterpret_cast<double*>(f->progress_host + 8);
+    f->scal_dev = reinterpret_cast<double*>(f->progress_dev + 8);
+    for (int i = 0; i < 8; ++i) f->scal_host[i] = 0.0;
     FTRY(check_hip(c, hipMemcpy(c->full_cc, fcc.data(), c->nb * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     FTRY(check_hip(c, hipMemcpy(c->full_epos, fepos.data(), 9 * ne * sizeof(int32_t), hipMemcpyHostToDevice),
                    "upload"));
@@ -500,11 +503,14 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->tvec, 3 * N * sizeof(float), "alloc tvec"));
     TRY(dev_alloc(c, &c->wgrad, (size_t)kRedBlocks * VMS_PC_NWEIGHTS * sizeof(float), "alloc wgrad"));
     TRY(dev_alloc(c, &c->fscal, 8 * sizeof(float), "alloc fscal"));
-    TRY(check_hip(c, hipHostMalloc(reinterpret_cast<void**>(&c->progress_host), 64,
+    TRY(check_hip(c, hipHostMalloc(reinterpret_cast<void**>(&c->progress_host), 128,
                                    hipHostMallocMapped | hipHostMallocCoherent), "alloc progress word"));
     TRY(check_hip(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->progress_dev), c->progress_host, 0),
                   "map progress word"));
     *c->progress_host = 0;
+    c->scal_host = reinterpret_cast<double*>(c->progress_host + 8);
+    c->scal_dev = reinterpret_cast<double*>(c->progress_dev + 8);
+    for (int i = 0; i < 8; ++i) c->scal_host[i] = 0.0;
     TRY(check_hip(c, hipEventCreate(&c->ev0), "event"));
     TRY(check_hip(c, hipEventCreate(&c->ev1), "event"));
 

@@ -1255,7 +1255,8 @@ __global__ __launch_bounds__(kBlock) void norm_kernel(int n, const T* __restrict
     reduce_partials(red->partial, kRedBlocks, 1, gridDim.x, &tot);
     __syncthreads();
     if (threadIdx.x == 0) {
-        out[0] = sqrt(tot);
+        // out is pinned host memory (the context's mapped scalars), read after a synchronisation
+        __hip_atomic_store(out, sqrt(tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         red->counter = 0u;
     }
 }
@@ -1281,10 +1282,13 @@ static_assert(VMS_RED_GRID_MAX <= kRedBlocks, "reduction grid exceeds the partia
 inline int red_grid(int64_t n) { return std::max(1, std::min(VMS_RED_GRID_MAX, grid_for(n))); }
 
 // Reads a device double with a stream sync.
-int read_scalar(vms_ctx* c, const double* dptr, double* h, hipStream_t s) {
-    int rc = check_hip(c, hipMemcpyAsync(h, dptr, sizeof(double), hipMemcpyDeviceToHost, s), "read scalar");
+// Synchronises the stream, then reads mapped scalar k (written by norm_kernel into c->scal_dev[k]).
+int read_scalar(vms_ctx* c, int k, double* h, hipStream_t s) {
+    const int rc = check_hip(c, hipStreamSynchronize(s), "sync");
     if (rc) return rc;
-    return check_hip(c, hipStreamSynchronize(s), "sync");
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    *h = *reinterpret_cast<volatile const double*>(c->scal_host + k);
+    return VMS_OK;
 }
 
 #ifndef VMS_LEAD_STEPS
@@ -1553,8 +1557,8 @@ static int true_residual(vms_ctx* c, const void* A, const double* b, const doubl
     else
         spmv_kernel<float, double, double, double, 1><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
             c->n_nodes, c->rowptr, c->colidx, (const float*)A, x, b, c->r64, nullptr, nullptr);
-    norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, c->r64, c->red, c->rnorm + 2);
-    return read_scalar(c, c->rnorm + 2, rn, s);
+    norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, c->r64, c->red, c->scal_dev + 0);
+    return read_scalar(c, 0, rn, s);
 }
 
 int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms_solve_opts* o,
@@ -1603,9 +1607,9 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, o->coarse_pressure, c->red, c->gs);
     }
     if ((rc = launch_ap_setup(c, A, s))) return rc;
-    norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, b, c->red, c->rnorm + 3);
+    norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, b, c->red, c->scal_dev + 1);
     double bn = 0.0;
-    if ((rc = read_scalar(c, c->rnorm + 3, &bn, s))) return rc;
+    if ((rc = read_scalar(c, 1, &bn, s))) return rc;
     if (!std::isfinite(bn)) return set_error(c, VMS_ENONFINITE, "gmres: non-finite right-hand side");
     if (bn == 0.0) {
         if ((rc = launch_fill(x, n * sizeof(double), s))) return rc;
@@ -1684,9 +1688,9 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
                     return rc;
                 spmv_kernel<float, float, float, float, 1, float><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
                     c->n_nodes, c->rowptr, c->colidx, (const float*)A, d, rr, q, nullptr, nullptr);
-                norm_kernel<float><<<red_grid(n), kBlock, 0, s>>>(n, q, c->red, c->rnorm + 2);
+                norm_kernel<float><<<red_grid(n), kBlock, 0, s>>>(n, q, c->red, c->scal_dev + 2);
                 double qn = 0.0;
-                if ((rc = read_scalar(c, c->rnorm + 2, &qn, s))) return rc;     // synchronises
+                if ((rc = read_scalar(c, 2, &qn, s))) return rc;     // synchronises
                 int stopped = 0;
                 const int k = finish_cycle(c, &stopped);
                 iters += k;

@@ -142,6 +142,11 @@ struct vms_ctx {
     // that the host can follow it without synchronising the stream
     uint64_t* progress_host = nullptr;
     uint64_t* progress_dev = nullptr;
+    // GMRES norms the host reads after a stream synchronisation (the true residual, the inner
+    // residual, the right-hand side), written by the device into the same pinned allocation,
+    // 64 bytes after the progress word: no copy kernel per read
+    double* scal_host = nullptr;
+    double* scal_dev = nullptr;
     uint32_t cycle_gen = 0;
     std::vector<int64_t> cycle_timed;    // timed launches of the cycle: (step, slot, generation)
     // a full restart cycle's Arnoldi steps recorded once as a graph (replayed with one launch)
