@@ -174,9 +174,10 @@ __global__ void spmv_f32_kernel(int n, const int32_t* __restrict__ rowptr, const
     y[tid] = MODE == 0 ? b[tid] - acc : acc;
 }
 
-// sums of squares of two vectors -> out[0], out[1] (atomic FP64 accumulation, zeroed by the host)
+// sums of squares of two vectors, per workgroup: part[b] and part[gridDim.x + b] (no atomics,
+// so that training is reproducible run to run; sumsq2_finalize_kernel adds them in order)
 __global__ __launch_bounds__(kBlock) void sumsq2_kernel(int n, const float* __restrict__ a,
-                                                        const float* __restrict__ b, double* out) {
+                                                        const float* __restrict__ b, double* __restrict__ part) {
     double sa = 0.0, sb = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         sa += double(a[i]) * double(a[i]);
@@ -198,8 +199,34 @@ __global__ __launch_bounds__(kBlock) void sumsq2_kernel(int n, const float* __re
             ta += ls[0][w];
             tb += ls[1][w];
         }
-        unsafeAtomicAdd(&out[0], ta);
-        unsafeAtomicAdd(&out[1], tb);
+        part[blockIdx.x] = ta;
+        part[gridDim.x + blockIdx.x] = tb;
+    }
+}
+
+// out[0], out[1] = the sums of the nb partials of sumsq2_kernel, in a fixed order (one
+// workgroup of kBlock threads: strided serial sums, then a pairwise tree in LDS)
+__global__ __launch_bounds__(kBlock) void sumsq2_finalize_kernel(int nb, const double* __restrict__ part,
+                                                                 double* __restrict__ out) {
+    __shared__ double ls[2][kBlock];
+    double sa = 0.0, sb = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) {
+        sa += part[i];
+        sb += part[nb + i];
+    }
+    ls[0][threadIdx.x] = sa;
+    ls[1][threadIdx.x] = sb;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            ls[0][threadIdx.x] += ls[0][threadIdx.x + h];
+            ls[1][threadIdx.x] += ls[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = ls[0][0];
+        out[1] = ls[1][0];
     }
 }
 
@@ -319,9 +346,6 @@ __global__ void zero_f32_kernel(float* p, size_t n) {
         p[i] = 0.f;
 }
 
-__global__ void zero_f64_kernel(double* p, int n) {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
-}
 
 __global__ void reset_pc_flags_kernel(int32_t* flags) {
     if (threadIdx.x == 0) {
@@ -403,7 +427,7 @@ extern "C" int vms_pc_train_step(vms_ctx* c, const void* bsr_vals, const float* 
     float* e = c->tvec + N;            // r - A P r
     float* g = c->tvec + 2 * (size_t)N;  // A^T e
     float* gdelta = (float*)c->V;      // [n][16]: the Krylov basis is idle during training
-    double* sums = c->rnorm + 4;       // two FP64 accumulators
+    double* sums = c->rnorm + 4;       // the two FP64 sums of the loss
     float* loss = c->fscal;
     int rc = features(c, bsr_vals, c->feats, dinv, s);
     if (rc) return rc;
@@ -412,7 +436,6 @@ extern "C" int vms_pc_train_step(vms_ctx* c, const void* bsr_vals, const float* 
     zero_f32_kernel<<<1, 64, 0, s>>>(loss, 1);
     for (int b = 0; b < nbatch; ++b) {
         const float* r = r_batch + (size_t)b * N;
-        zero_f64_kernel<<<1, 64, 0, s>>>(sums, 2);
         block_apply_kernel<<<grid_for(N), kBlock, 0, s>>>(n, P, r, t);
         if (c->prec == VMS_FP64) {
             spmv_f32_kernel<double, 0><<<grid_for(N), kBlock, 0, s>>>(n, c->rowptr, c->colidx, c->tpos,
@@ -425,7 +448,9 @@ extern "C" int vms_pc_train_step(vms_ctx* c, const void* bsr_vals, const float* 
             spmv_f32_kernel<float, 1><<<grid_for(N), kBlock, 0, s>>>(n, c->rowptr, c->colidx, c->tpos,
                                                                     (const float*)bsr_vals, e, nullptr, g);
         }
-        sumsq2_kernel<<<std::min(grid_for(N), 1024), kBlock, 0, s>>>(N, e, r, sums);
+        const int nb = std::min(grid_for(N), 1024);
+        sumsq2_kernel<<<nb, kBlock, 0, s>>>(N, e, r, c->red->partial);      // reduction scratch: idle here
+        sumsq2_finalize_kernel<<<1, kBlock, 0, s>>>(nb, c->red->partial, sums);
         grad_delta_kernel<<<grid_for((int64_t)16 * n), kBlock, 0, s>>>(n, dinv, g, r, sums, nbatch, gdelta, loss);
     }
     const int nparts = std::min(kBwdBlocks, std::max(1, (n + kBwdNodes - 1) / kBwdNodes));
