@@ -267,7 +267,7 @@ static int create_full_system(vms_ctx* c, const std::vector<int32_t>& tets, cons
                                     hipHostMallocMapped | hipHostMallocCoherent), "alloc progress word"));
     FTRY(check_hip(f, hipHostGetDevicePointer(reinterpret_cast<void**>(&f->progress_dev), f->progress_host, 0),
                    "map progress word"));
-    *f->progress_host = 0;
+    for (int i = 0; i < 8; ++i) f->progress_host[i] = 0;      // progress word, norm tags
     f->scal_host = reinterpret_cast<double*>(f->progress_host + 8);
     f->scal_dev = reinterpret_cast<double*>(f->progress_dev + 8);
     for (int i = 0; i < 8; ++i) f->scal_host[i] = 0.0;
@@ -507,7 +507,7 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
                                    hipHostMallocMapped | hipHostMallocCoherent), "alloc progress word"));
     TRY(check_hip(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->progress_dev), c->progress_host, 0),
                   "map progress word"));
-    *c->progress_host = 0;
+    for (int i = 0; i < 8; ++i) c->progress_host[i] = 0;      // progress word, norm tags
     c->scal_host = reinterpret_cast<double*>(c->progress_host + 8);
     c->scal_dev = reinterpret_cast<double*>(c->progress_dev + 8);
     for (int i = 0; i < 8; ++i) c->scal_host[i] = 0.0;

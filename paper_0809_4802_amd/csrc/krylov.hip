@@ -1240,7 +1240,7 @@ __global__ void precond_accumulate_kernel(int n_nodes, const T* __restrict__ Min
 // FP64 norm of a vector of any precision into out (device) via partials.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void norm_kernel(int n, const T* __restrict__ r, RedScratch* red,
-                                                      double* out) {
+                                                      double* out, uint64_t* tag_out, uint64_t tag) {
     __shared__ double lds[kBlock / 64];
     double v[1] = {0.0};
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1255,9 +1255,11 @@ __global__ __launch_bounds__(kBlock) void norm_kernel(int n, const T* __restrict
     reduce_partials(red->partial, kRedBlocks, 1, gridDim.x, &tot);
     __syncthreads();
     if (threadIdx.x == 0) {
-        // out is pinned host memory (the context's mapped scalars), read after a synchronisation
+        // out and tag_out are pinned host memory (the context's mapped page): the value, then its
+        // tag with release order, which the host polls for
         __hip_atomic_store(out, sqrt(tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         red->counter = 0u;
+        __hip_atomic_store(tag_out, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -1282,11 +1284,30 @@ static_assert(VMS_RED_GRID_MAX <= kRedBlocks, "reduction grid exceeds the partia
 inline int red_grid(int64_t n) { return std::max(1, std::min(VMS_RED_GRID_MAX, grid_for(n))); }
 
 // Reads a device double with a stream sync.
-// Synchronises the stream, then reads mapped scalar k (written by norm_kernel into c->scal_dev[k]).
+// Launches the norm of r (n entries) into mapped scalar k with a fresh tag.
+template <typename T>
+void launch_norm(vms_ctx* c, int n, const T* r, int k, hipStream_t s) {
+    norm_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, r, c->red, c->scal_dev + k, c->progress_dev + 1 + k,
+                                                  ++c->scal_seq);
+}
+
+// Waits for mapped scalar k of the last launch_norm: spins on its tag in pinned memory (the
+// launches after it on the stream are already ordered), with a stream query every 256 spins so
+// that a failed or drained stream ends the wait.
 int read_scalar(vms_ctx* c, int k, double* h, hipStream_t s) {
-    const int rc = check_hip(c, hipStreamSynchronize(s), "sync");
-    if (rc) return rc;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    const uint64_t want = c->scal_seq;
+    const uint64_t* tag = c->progress_host + 1 + k;
+    for (unsigned spin = 0;; ++spin) {
+        if (__atomic_load_n(tag, __ATOMIC_ACQUIRE) == want) break;
+        if ((spin & 255u) == 255u) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {
+                if (__atomic_load_n(tag, __ATOMIC_ACQUIRE) == want) break;
+                return set_error(c, VMS_EHIP, "read scalar: the stream finished without the value");
+            }
+            if (q != hipErrorNotReady) return check_hip(c, q, "read scalar: stream query");
+        }
+    }
     *h = *reinterpret_cast<volatile const double*>(c->scal_host + k);
     return VMS_OK;
 }
@@ -1557,7 +1578,7 @@ static int true_residual(vms_ctx* c, const void* A, const double* b, const doubl
     else
         spmv_kernel<float, double, double, double, 1><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
             c->n_nodes, c->rowptr, c->colidx, (const float*)A, x, b, c->r64, nullptr, nullptr);
-    norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, c->r64, c->red, c->scal_dev + 0);
+    launch_norm<double>(c, n, c->r64, 0, s);
     return read_scalar(c, 0, rn, s);
 }
 
@@ -1607,7 +1628,7 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, o->coarse_pressure, c->red, c->gs);
     }
     if ((rc = launch_ap_setup(c, A, s))) return rc;
-    norm_kernel<double><<<red_grid(n), kBlock, 0, s>>>(n, b, c->red, c->scal_dev + 1);
+    launch_norm<double>(c, n, b, 1, s);
     double bn = 0.0;
     if ((rc = read_scalar(c, 1, &bn, s))) return rc;
     if (!std::isfinite(bn)) return set_error(c, VMS_ENONFINITE, "gmres: non-finite right-hand side");
@@ -1688,7 +1709,7 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
                     return rc;
                 spmv_kernel<float, float, float, float, 1, float><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
                     c->n_nodes, c->rowptr, c->colidx, (const float*)A, d, rr, q, nullptr, nullptr);
-                norm_kernel<float><<<red_grid(n), kBlock, 0, s>>>(n, q, c->red, c->scal_dev + 2);
+                launch_norm<float>(c, n, q, 2, s);
                 double qn = 0.0;
                 if ((rc = read_scalar(c, 2, &qn, s))) return rc;     // synchronises
                 int stopped = 0;
@@ -1716,6 +1737,8 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             }
         }
     }
+    // the per-cycle reads above wait only for their norms; the call returns with the stream drained
+    if (int rs = check_hip(c, hipStreamSynchronize(s), "sync")) return rs;
     inf.iters = iters;
     inf.true_rel_res = rn / bn;
     if (info) *info = inf;

@@ -147,6 +147,7 @@ struct vms_ctx {
     // 64 bytes after the progress word: no copy kernel per read
     double* scal_host = nullptr;
     double* scal_dev = nullptr;
+    uint64_t scal_seq = 0;               // tag of the last norm launched (words 1 .. 3 of the progress page)
     uint32_t cycle_gen = 0;
     std::vector<int64_t> cycle_timed;    // timed launches of the cycle: (step, slot, generation)
     // a full restart cycle's Arnoldi steps recorded once as a graph (replayed with one launch)
