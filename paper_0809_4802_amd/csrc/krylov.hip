@@ -638,7 +638,9 @@ __global__ __launch_bounds__(kDotThreads) void dots_kernel(int n_nodes, int j, c
                                                            const T* __restrict__ w,
                                                            const uint8_t* __restrict__ dmask,
                                                            double* __restrict__ part, const GmresState* gs) {
-    const int skip = gs->done;
+    // a finished cycle reads nothing (the replayed steps after convergence cost only their
+    // launches); its partials are left as they are, and the update and the tail test the flag too
+    if (gs->done) return;
     using V4 = typename Vec4<T>::type;
     const int y = blockIdx.y;
     const int kind = y < j ? 0 : (y == j ? 1 : 2);
@@ -664,7 +666,7 @@ __global__ __launch_bounds__(kDotThreads) void dots_kernel(int n_nodes, int j, c
         lds[1][threadIdx.x >> 6] = a1;
     }
     __syncthreads();
-    if (threadIdx.x < 2 && !skip) {
+    if (threadIdx.x < 2) {
         double t = 0.0;
         for (int k = 0; k < kDotThreads / 64; ++k) t += lds[threadIdx.x][k];
         part[(size_t)(2 * y + threadIdx.x) * gridDim.x + chunk] = t;
