@@ -158,6 +158,10 @@ def main():
         r = solve(ctxs[ctx_name], w)
         forms[name] = {"seconds": r.seconds, "newton_steps": len(r.rnorms) - 1,
                        "gmres_iters": int(sum(d["iters"] for d in r.lin)),
+                       # GMRES cycles (inner FP32 cycles in the mixed form); a cycle replayed
+                       # from its graph launches all `restart` steps, those after convergence
+                       # return at once
+                       "gmres_cycles": int(sum(d["restarts"] for d in r.lin)),
                        "fell_back_to_bj": int(sum(d["fell_back_to_bj"] for d in r.lin)),
                        "final_rel_residual": r.rnorms[-1] / r.rnorms[0]}
         log(f"time-to-1e-8 {name}: {forms[name]}")
