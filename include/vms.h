@@ -158,7 +158,10 @@ typedef struct {
     int32_t coarse_pressure;   /* 1: add the coarse correction on the constant pressure
                                   mode, P v = M v + z (z^T v) / (z^T A z), z = 1 on every
                                   free pressure dof.  With one pinned pressure dof that mode
-                                  is nearly singular and restarted GMRES stalls on it.     */
+                                  is nearly singular and restarted GMRES stalls on it.
+                                  Without any prescribed pressure dof (open or traction-free
+                                  boundaries) the mode does not exist and the option has no
+                                  effect.                                                  */
     float* log_residuals;      /* device float [log_max][n_nodes][4] or NULL: the true
                                   residual b - A x at the start of every restart cycle
                                   (refinement sweep in the mixed ctx) is copied here, as

@@ -224,6 +224,7 @@ static int create_full_system(vms_ctx* c, const std::vector<int32_t>& tets, cons
     f->device = c->device;
     f->prec = c->prec;
     f->max_restart = c->max_restart;
+    f->n_pressure_pins = c->n_pressure_pins;
     f->n_nodes = (int32_t)nr;
     f->full_nodes = c->n_nodes;
     f->n_elems = 0;
@@ -360,6 +361,7 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
         }
         dmask[d >> 2] |= (uint8_t)(1u << (d & 3));
     }
+    for (int32_t i = 0; i < nn; ++i) c->n_pressure_pins += (dmask[i] >> 3) & 1;
 
     // node -> elements
     std::vector<int32_t> n2e_ptr(nn + 1, 0), n2e;

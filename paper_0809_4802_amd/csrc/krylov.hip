@@ -351,9 +351,11 @@ __device__ __forceinline__ bool free_pressure(const uint8_t* __restrict__ dmask,
 // that couple two free pressure dofs (= 1 / (z^T A z) for z = 1 on the free pressure dofs).
 // That sum is the Galerkin coarse operator of the mode.  It is only meaningful when the mode
 // is nearly singular because one pressure dof is pinned: there the sum is the coupling to the
-// pinned dof, about 1 / (2 n_nodes) of the summed magnitudes.  Without a pin (an open outlet)
-// the pressure-pressure block annihilates constants, the sum is rounding noise, and the
-// correction is switched off (kappa = 0) when |sum| <= 1e-8 x the summed magnitudes.
+// pinned dof, about 1 / (2 n_nodes) of the summed magnitudes.  Without a pin (open or
+// traction-free boundaries) the pressure-pressure block annihilates constants and the sum is
+// rounding noise: the caller then passes enabled = 0 (the noise of FP32-stored entries can
+// exceed any fixed fraction of the magnitudes, and kappa = 1 / noise would swamp the Krylov
+// space).  As a guard, the correction is also off when |sum| <= 1e-8 x the summed magnitudes.
 template <typename TA>
 __global__ __launch_bounds__(kBlock) void coarse_setup_kernel(int n_nodes, const int32_t* __restrict__ rowptr,
                                                               const int32_t* __restrict__ colidx,
@@ -1594,6 +1596,8 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     const int refine_max = o->refine_max > 0 ? o->refine_max : 30;
     const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-4;
     int rc;
+    // the constant-pressure coarse mode exists only when a pressure dof is prescribed
+    const int coarse_pressure = o->coarse_pressure && c->n_pressure_pins > 0;
 
     // preconditioner blocks
     if (o->pc == VMS_PC_LEARNED && o->pc_weights) {
@@ -1615,19 +1619,19 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             full_coarse_vector_kernel<double, double><<<grid_for(c->n_nodes), kBlock, 0, s>>>(
                 nn, c->n_nodes, c->rowptr, c->colidx, (const double*)A, (const double*)c->Minv, c->dmask, c->zfull);
             full_coarse_setup_kernel<double><<<red_grid(nn), kBlock, 0, s>>>(
-                nn, c->rowptr, c->colidx, (const double*)A, c->dmask, c->zfull, o->coarse_pressure, c->red, c->gs);
+                nn, c->rowptr, c->colidx, (const double*)A, c->dmask, c->zfull, coarse_pressure, c->red, c->gs);
         } else {
             full_coarse_vector_kernel<float, float><<<grid_for(c->n_nodes), kBlock, 0, s>>>(
                 nn, c->n_nodes, c->rowptr, c->colidx, (const float*)A, (const float*)c->Minv, c->dmask, c->zfull);
             full_coarse_setup_kernel<float><<<red_grid(nn), kBlock, 0, s>>>(
-                nn, c->rowptr, c->colidx, (const float*)A, c->dmask, c->zfull, o->coarse_pressure, c->red, c->gs);
+                nn, c->rowptr, c->colidx, (const float*)A, c->dmask, c->zfull, coarse_pressure, c->red, c->gs);
         }
     } else if (c->prec == VMS_FP64) {
         coarse_setup_kernel<double><<<red_grid(c->n_nodes), kBlock, 0, s>>>(
-            c->n_nodes, c->rowptr, c->colidx, (const double*)A, c->dmask, o->coarse_pressure, c->red, c->gs);
+            c->n_nodes, c->rowptr, c->colidx, (const double*)A, c->dmask, coarse_pressure, c->red, c->gs);
     } else {
         coarse_setup_kernel<float><<<red_grid(c->n_nodes), kBlock, 0, s>>>(
-            c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, o->coarse_pressure, c->red, c->gs);
+            c->n_nodes, c->rowptr, c->colidx, (const float*)A, c->dmask, coarse_pressure, c->red, c->gs);
     }
     if ((rc = launch_ap_setup(c, A, s))) return rc;
     launch_norm<double>(c, n, b, 1, s);

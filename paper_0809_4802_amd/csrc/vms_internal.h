@@ -95,6 +95,7 @@ struct vms_ctx {
     vms_precision prec = VMS_FP64;
     int32_t max_restart = 50;
     int32_t n_dir = 0;
+    int32_t n_pressure_pins = 0;     // Dirichlet pressure dofs (the coarse pressure mode needs one)
 
     // mesh (device, library-owned copies)
     double4* xyz4 = nullptr;         // [n_nodes] (x, y, z, 0)

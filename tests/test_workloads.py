@@ -12,8 +12,8 @@ import os
 import numpy as np
 import pytest
 
-from workloads import (cavity_mesh, jittered_cube, backward_facing_step, boundary_nodes,
-                       count_edges, tet_volumes6, cavity_bc, bfs_bc, ethier_steinman_bc,
+from workloads import (cavity_mesh, jittered_cube, backward_facing_step, jet_box, boundary_nodes,
+                       count_edges, tet_volumes6, cavity_bc, bfs_bc, jet_bc, ethier_steinman_bc,
                        es_velocity, es_pressure, CONFIGS)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -43,6 +43,24 @@ def test_bfs_sizes_and_volume():
     bc = bfs_bc(m)
     assert np.isclose(bc.values.max(), 1.0)
     assert not np.any(bc.dofs % 4 == 3)          # no pressure pin: open outlet
+
+
+def test_jet_sizes_and_orifice():
+    m = jet_box(8)
+    assert (m.n_elems, m.n_nodes) == (196608, 35937)
+    assert np.isclose(tet_volumes6(m.xyz, m.tets).sum() / 6, 64.0)
+    bc = jet_bc(m)
+    assert not np.any(bc.dofs % 4 == 3)          # traction-free elsewhere: no pressure pin
+    nodes = np.unique(bc.dofs // 4)
+    wall = np.nonzero(np.abs(m.xyz[:, 0]) < 1e-12)[0]
+    assert np.array_equal(nodes, wall) and bc.n == 3 * wall.size
+    vals = bc.values.reshape(-1, 3)               # dofs sorted: node by node, components 0..2
+    assert np.all(vals[:, 1:] == 0.0)
+    r2 = m.xyz[nodes, 1] ** 2 + m.xyz[nodes, 2] ** 2
+    inside = r2 < 0.25
+    assert np.allclose(vals[inside, 0], 1.0 - 4.0 * r2[inside])
+    assert np.all(vals[~inside, 0] == 0.0)
+    assert vals[:, 0].max() == 1.0 and inside.sum() == 45   # grid nodes strictly inside r = 1/2, h = 1/8
 
 
 def test_jitter_valid_and_seeded():
@@ -116,6 +134,7 @@ def test_ethier_steinman_solves_navier_stokes():
 
 
 def test_configs_are_consistent():
-    assert set(CONFIGS) == {"cavity4", "cavity32", "es64", "bfs8", "bfs16"}
+    assert set(CONFIGS) == {"cavity4", "cavity32", "es64", "bfs8", "bfs16", "jet8"}
+    assert CONFIGS["jet8"].re == 1000.0 and CONFIGS["jet8"].dt == 0.01
     assert CONFIGS["es64"].dt == 0.01 and CONFIGS["es64"].steps == 10
     assert CONFIGS["bfs16"].steps == 50

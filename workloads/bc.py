@@ -1,4 +1,4 @@
-"""Dirichlet data for the three workload families.
+"""Dirichlet data for the four workload families.
 
 A Dirichlet dof is 4*node + c with c = 0, 1, 2 the velocity components and
 c = 3 the pressure.  The solvers work on Newton increments, so the
@@ -84,6 +84,19 @@ def bfs_bc(mesh: Mesh, u_max: float = 1.0) -> DirichletData:
     vel = np.zeros((nodes.size, 3))
     y, z = xn[inlet, 1], xn[inlet, 2]
     vel[inlet, 0] = u_max * 4.0 * (y - 1.0) * (2.0 - y) * z * (4.0 - z) / 4.0
+    return _pack(np.repeat(nodes, 3), np.tile(np.arange(3), nodes.size), vel.ravel())
+
+
+def jet_bc(mesh: Mesh, radius: float = 0.5, u_max: float = 1.0) -> DirichletData:
+    """Jet from an orifice: every node of the wall x = 0 has its velocity prescribed, the
+    paraboloid u_x = u_max (1 - r^2 / radius^2) inside the orifice (r = distance from the
+    orifice centre, the origin; zero on its rim) and no slip elsewhere.  The other five
+    faces are traction-free: no Dirichlet dof there and no pressure pin."""
+    x = mesh.xyz
+    nodes = np.nonzero(np.abs(x[:, 0]) < 1e-9)[0]
+    r2 = x[nodes, 1] ** 2 + x[nodes, 2] ** 2
+    vel = np.zeros((nodes.size, 3))
+    vel[:, 0] = u_max * np.maximum(0.0, 1.0 - r2 / radius ** 2)
     return _pack(np.repeat(nodes, 3), np.tile(np.arange(3), nodes.size), vel.ravel())
 
 

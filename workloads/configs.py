@@ -1,4 +1,4 @@
-"""The five synthetic workloads (meshes, physics and tolerances).
+"""The six synthetic workloads (meshes, physics and tolerances).
 
   cavity4   steady lid-driven cavity, 4^3 cells x 6 tets, Re 1, FP64,
             Newton to 1e-10, linear rtol 1e-12 (small parity case)
@@ -11,6 +11,9 @@
             the learned preconditioner
   bfs16     backward-facing step, (16,10,10) (2,496,000 tets), Re 800,
             dt 0.05, 50 steps, learned vs plain block-Jacobi
+  jet8      jet from an orifice (diameter 1) in a no-slip wall, box 4^3 with 8
+            cells per unit length (32^3 x 6 = 196,608 tets), traction-free
+            elsewhere, Re 1000, backward Euler dt 0.01 from rest, mixed
 Velocity and length scales are 1 everywhere, so nu = 1 / Re.
 """
 from __future__ import annotations
@@ -19,15 +22,15 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .mesh import cavity_mesh, jittered_cube, backward_facing_step
-from .bc import cavity_bc, ethier_steinman_bc, bfs_bc, apply_dirichlet
+from .mesh import cavity_mesh, jittered_cube, backward_facing_step, jet_box
+from .bc import cavity_bc, ethier_steinman_bc, bfs_bc, jet_bc, apply_dirichlet
 from .ethier_steinman import es_nodal
 
 
 @dataclass(frozen=True)
 class WorkloadConfig:
     name: str
-    family: str                  # "cavity" | "es" | "bfs"
+    family: str                  # "cavity" | "es" | "bfs" | "jet"
     mesh_args: tuple
     re: float
     dt: float                    # <= 0: steady
@@ -45,6 +48,7 @@ CONFIGS = {
     "bfs8": WorkloadConfig("bfs8", "bfs", (8, 10, 10), 800.0, 0.0, 1, 1e-8, 1e-8, "mixed",
                            re_sweep=(400.0, 500.0, 600.0, 700.0, 800.0)),
     "bfs16": WorkloadConfig("bfs16", "bfs", (16, 10, 10), 800.0, 0.05, 50, 1e-8, 1e-8, "mixed"),
+    "jet8": WorkloadConfig("jet8", "jet", (8,), 1000.0, 0.01, 100, 1e-8, 1e-8, "mixed"),
 }
 
 
@@ -56,6 +60,8 @@ def make_mesh(cfg: WorkloadConfig):
         return jittered_cube(n, seed=seed)
     if cfg.family == "bfs":
         return backward_facing_step(*cfg.mesh_args)
+    if cfg.family == "jet":
+        return jet_box(*cfg.mesh_args)
     raise ValueError(cfg.family)
 
 
@@ -68,6 +74,9 @@ def initial_state(cfg: WorkloadConfig, mesh, t: float = 0.0):
     elif cfg.family == "es":
         bc = ethier_steinman_bc(mesh, t, nu_l)
         u = es_nodal(mesh.xyz, t, nu_l)
+    elif cfg.family == "jet":
+        bc = jet_bc(mesh)
+        u = np.zeros((mesh.n_nodes, 4))
     else:
         bc = bfs_bc(mesh)
         u = np.zeros((mesh.n_nodes, 4))

@@ -184,6 +184,14 @@ def backward_facing_step(cx: int, cy: int, cz: int) -> Mesh:
                     name=f"bfs_{cx}_{cy}_{cz}")
 
 
+def jet_box(c: int) -> Mesh:
+    """Jet from an orifice: the box x in [0, 4], y, z in [-2, 2] with c cells per unit
+    length (4c x 4c x 4c cells x 6 tets).  The orifice (diameter 1) is centred at the
+    origin, in the wall x = 0."""
+    n = 4 * c
+    return kuhn_box((n, n, n), (0, -2, -2), (4, 2, 2), name=f"jet_{c}")
+
+
 def boundary_nodes(tets: np.ndarray, n_nodes: int) -> np.ndarray:
     """Bool mask of nodes lying on a boundary face (a face owned by one tet)."""
     faces = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]],
