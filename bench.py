@@ -40,11 +40,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle sample (0: every element of the workload)")
-    ap.add_argument("--study", choices=["bfs", "nr", "picard"], default=None,
+    ap.add_argument("--study", choices=["bfs", "nr", "picard", "jet"], default=None,
                     help="bfs: the learned-correction study on the backward-facing step (train on the steady "
                          "Re 400..800 continuation of bfs8, compare with block-Jacobi over the transient bfs16 "
                          "run); prints its own JSON report instead of the bench line")
-    ap.add_argument("--study-steps", type=int, default=2, help="bfs16 time steps in --study bfs")
+    ap.add_argument("--study-steps", type=int, default=2,
+                    help="time steps of the transient run in --study bfs (bfs16) and --study jet (jet8)")
     ap.add_argument("--study-restart", type=int, default=128,
                     help="GMRES restart length of the bfs16 evaluation in --study bfs (its long-wavelength "
                          "pressure modes stall GMRES(50): 25,472 -> 10,160 iterations on the first bfs8 step)")
@@ -80,6 +81,9 @@ def main():
         return
     if args.study == "picard":
         picard_study(B, driver, build_workload, dev, args.workload)
+        return
+    if args.study == "jet":
+        jet_study(B, driver, build_workload, dev, args.study_steps)
         return
     cfg, mesh, u0, beta0, bc = build_workload(args.workload)
     if args.counters:
@@ -300,6 +304,38 @@ def picard_study(B, driver, build_workload, dev, workload, reynolds=(100.0, 400.
             report[key] = out
             log(f"{key}: " + json.dumps({k: v for k, v in out.items() if k != "rel_residuals"}))
     B.vms_set_linearization(ctx, B.VMS_LIN_NEWTON)
+    print(json.dumps(report), flush=True)
+
+
+def jet_study(B, driver, build_workload, dev, steps):
+    """The jet from an orifice (jet8: 196,608 tets, Re 1000, backward Euler dt 0.01 from rest):
+    `steps` time steps in each precision, Newton to 1e-8 per step with GMRES(50) + block-Jacobi;
+    per step the Newton iterations, GMRES iterations, seconds and the largest velocity."""
+    import numpy as np
+    import torch
+    cfg, mesh, u0, beta0, bc = build_workload("jet8")
+    dofs = torch.from_numpy(bc.dofs.astype(np.int64)).to(dev)
+    vals = torch.from_numpy(bc.values).to(dev)
+    report = {"study": "jet", "workload": "jet8", "n_elems": mesh.n_elems, "re": cfg.re, "dt": cfg.dt,
+              "steps": steps}
+    for name, prec in (("fp64_bj", B.VMS_FP64), ("mixed_bj", B.VMS_MIXED)):
+        ctx = B.Context(torch.from_numpy(mesh.xyz).to(dev), torch.from_numpy(mesh.tets).to(dev),
+                        torch.from_numpy(bc.dofs).to(dev), precision=prec)
+        u = torch.from_numpy(u0).to(dev)
+        beta = torch.from_numpy(beta0).to(dev)
+        u_prev = torch.empty_like(u)
+        per_step = []
+        for _ in range(steps):
+            u_prev.copy_(u)
+            driver.set_dirichlet(u, dofs, vals)
+            r = driver.newton_solve(ctx, u, beta, cfg.re, cfg.dt, u_prev, None, tol=cfg.newton_tol,
+                                    lin=B.solve_opts(restart=50, rtol=1e-9, max_iters=40000))
+            per_step.append({"newton": len(r.rnorms) - 1, "gmres_iters": int(sum(d["iters"] for d in r.lin)),
+                             "seconds": r.seconds, "max_speed": float(u[:, :3].norm(dim=1).max())})
+        report[name] = {"seconds": sum(p["seconds"] for p in per_step),
+                        "gmres_iters": sum(p["gmres_iters"] for p in per_step), "per_step": per_step}
+        log(f"jet {name}: {report[name]['seconds']:.3f} s, {report[name]['gmres_iters']} GMRES iterations")
+        ctx.close()
     print(json.dumps(report), flush=True)
 
 
