@@ -1,22 +1,31 @@
 """Benchmark: condensed tangents/s and time-to-1e-8 Newton solve, FP64 vs mixed precision.
 
 Workload: steady lid-driven cavity, 32^3 cells x 6 tets (196,608 tets, 35,937 nodes),
-Re 100, Newton to ||R|| <= 1e-8 ||R_0|| (FP64 residual), GMRES(50) with 4x4
-block-Jacobi (+ learned correction when trained weights are available).
+Re 100, Newton to ||R|| <= 1e-8 ||R_0|| (FP64 residual), inexact Newton (Eisenstat-Walker
+forcing), GMRES(50) right-preconditioned by 4x4 block-Jacobi (or its learned correction)
+with the constant-pressure coarse correction.
 
-One step = one complete Newton-Schur solve from the initial state (every assembly,
-preconditioner setup, GMRES iteration, recovery and residual evaluation), all on the
-GPU through the C ABI; inputs are resident on the device before the timed region.
-value = condensed tangents processed per second over the timed steps
-        (elements x Newton iterations / wall time); ms_per_step = time to 1e-8.
-Also reported: the other precision forms, assembly-only throughput, the dominant
-kernel's roofline (HIP events on its stream), and the CPU oracle on a bounded sample.
+value        = condensed tangents/s: n_elems / t(vms_condense_assemble), the median of 20
+               calls after 3 warm-ups, each call bracketed by HIP events on its stream
+               (element residual + tangent + FP64 K_ff^-1 + Schur condensation + scatter into
+               4x4 block-CSR + Dirichlet elimination + residual norm), mixed precision,
+               at the workload's initial state; cpu_baseline measures the same on the oracle.
+ms_per_step  = time to 1e-8 of the headline form (mixed + learned correction): one step is a
+               complete Newton-Schur solve from the initial state (every assembly,
+               preconditioner setup, GMRES iteration, recovery and residual evaluation), all on
+               the GPU through the C ABI, inputs resident on the device before the timed region.
+The learned correction is trained and selected on Newton systems of other Reynolds numbers
+(cavity 32^3 at Re 50 and 75); the timed Re 100 solve is never seen in training.
+Also reported: every form's time to 1e-8, the assembly and Arnoldi-SpMV rooflines (HIP events on
+the launch stream), the 64^3 jittered cube (the HBM-resident size) and the CPU oracle.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -24,11 +33,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6      # vector FP64
+FP32_PEAK_TFLOPS = 78.6      # vector FP32 without packed instructions (packed FP32 is not used)
 PROFILE_EVERY = 8            # timed region: HIP events on the dominant kernel's launches in every 8th GMRES cycle
 COUNTER_ITERS = 64           # --counters: Arnoldi steps (SpMV launches) in the counter run
 COPY_MIB = 256               # --counters: size of the reference copy
 KERNEL_OF_PHASE = {"condense": "tile_kernel", "spmv": "spmv_kernel", "dots": "dots_kernel",
-                   "update": "update_kernel", "pc_apply": "ap_blocks_kernel"}
+                   "update": "update_fused_kernel", "pc_apply": "ap_blocks_kernel"}
+TRAIN_RE = (50.0, 75.0)      # Reynolds numbers of the learned correction's training systems
+WORKLOAD_TEXT = ("lid-driven cavity 32^3 cells x 6 tets ({ne} tets, {nn} nodes), Re {re:g}, steady Newton to "
+                 "1e-8 with Eisenstat-Walker forcing, GMRES(50) right-preconditioned by 4x4 block-Jacobi "
+                 "(learned correction in the headline form) plus the constant-pressure coarse correction; "
+                 "value = n_elems / t(vms_condense_assemble), mixed; ms_per_step = time to 1e-8, "
+                 "mixed + learned")
 
 
 def parse():
@@ -38,26 +55,109 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cavity32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm-config", action="store_true", help="skip the 64^3 jittered-cube measurements")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle sample (0: every element of the workload)")
     ap.add_argument("--study", choices=["bfs", "nr", "picard", "jet"], default=None,
                     help="bfs: the learned-correction study on the backward-facing step (train on the steady "
-                         "Re 400..800 continuation of bfs8, compare with block-Jacobi over the transient bfs16 "
-                         "run); prints its own JSON report instead of the bench line")
+                         "Re 400..800 continuation of bfs8, compare block-Jacobi FP64, block-Jacobi mixed and "
+                         "the learned correction over the transient bfs16 run); prints its own JSON report "
+                         "instead of the bench line")
     ap.add_argument("--study-steps", type=int, default=2,
                     help="time steps of the transient run in --study bfs (bfs16) and --study jet (jet8)")
-    ap.add_argument("--study-restart", type=int, default=128,
-                    help="GMRES restart length of the bfs16 evaluation in --study bfs (its long-wavelength "
-                         "pressure modes stall GMRES(50): 25,472 -> 10,160 iterations on the first bfs8 step)")
+    ap.add_argument("--study-restart", type=int, default=50,
+                    help="GMRES restart length of the bfs16 evaluation in --study bfs")
+    ap.add_argument("--study-forms", default="fp64_bj,mixed_bj,mixed_learned",
+                    help="comma-separated forms of the bfs16 evaluation in --study bfs")
     ap.add_argument("--counters", action="store_true",
-                    help="short run for hardware-counter passes: GMRES on the workload's mixed-precision "
-                         "tangent capped at COUNTER_ITERS Arnoldi steps, then a COPY_MIB device-to-device copy "
-                         "(the scale reference for the counters)")
+                    help="short run for hardware-counter passes: one condensed assembly and GMRES on the "
+                         "workload's mixed-precision tangent capped at COUNTER_ITERS Arnoldi steps, then a "
+                         "COPY_MIB device-to-device copy (the scale reference for the counters)")
     return ap.parse_args()
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def event_median_us(fn, reps=20, warm=3):
+    """Median duration of fn() over reps calls, each bracketed by HIP events on the current stream."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+    return ts[len(ts) // 2]
+
+
+def assembly_bench(B, ctx, mesh, u, beta, re, dt=0.0, u_prev=None):
+    """n_elems / t(vms_condense_assemble) (median of 20 event-timed calls after 3 warm-ups) and
+    the tile kernel's own time and algorithmic bytes from the phase timers."""
+    import torch
+    A = ctx.new_bsr()
+    rhs = ctx.new_vec()
+    rn = torch.zeros(1, dtype=torch.float64, device=ctx.device)
+
+    def call():
+        B.vms_condense_assemble(ctx, u, beta, re, dt, u_prev, None, A, rhs, rn)
+
+    t_us = event_median_us(call)
+    B.vms_profile(ctx, True, phases=["condense"])
+    for _ in range(20):
+        call()
+    ms, cnt, byt = B.vms_profile_read(ctx)["condense"]
+    B.vms_profile(ctx, False)
+    kern_us = 1e3 * ms / cnt
+    return {"tangents_per_s": mesh.n_elems / (t_us * 1e-6), "call_us": t_us, "kernel_us": kern_us,
+            "alg_bytes_per_launch": byt / cnt, "alg_GBps": byt / cnt / (kern_us * 1e-6) / 1e9}
+
+
+# Algorithmic flops of one element's condensed tangent and residual (closed-form element),
+# counted from the formulas of the tile kernel with each element's shared work counted once:
+# geometry 87, fields 77, R_f 45, K_ff and its inverse 72 (FP64); per row vertex R_c 66,
+# K_cf 30, Y = K_cf K_ff^-1 36, R* 24 (FP64); per (row, column) block 48 (precision T).
+ELEM_FLOPS_FP64 = 87 + 77 + 45 + 72 + 4 * (66 + 30 + 36 + 24)
+ELEM_FLOPS_T = 16 * 48
+
+
+def assembly_roofline(res, n_elems, mixed):
+    alg = res["alg_bytes_per_launch"]
+    t = res["kernel_us"] * 1e-6
+    f64 = ELEM_FLOPS_FP64 * n_elems
+    ft = ELEM_FLOPS_T * n_elems
+    # both precisions run at the same vector rate here (FP32 without packed instructions)
+    valu_frac = (f64 + ft) / t / 1e12 / FP64_PEAK_TFLOPS
+    return {"bound": "hbm", "kernel": "tile_kernel", "achieved": round(alg / t / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(alg / t / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg,
+            "avg_launch_us": round(res["kernel_us"], 3),
+            "alu": {"flops_per_elem_fp64": ELEM_FLOPS_FP64, "flops_per_elem_" + ("fp32" if mixed else "fp64_blocks"):
+                    ELEM_FLOPS_T, "achieved_tflops": round((f64 + ft) / t / 1e12, 2),
+                    "peak_tflops": FP64_PEAK_TFLOPS, "frac": round(valu_frac, 4)}}
+
+
+def cache_probe_gbps(nbytes):
+    """Device copy of nbytes (read nbytes + write nbytes) repeated, so that it stays in the caches:
+    the bandwidth a working set of this size sees (median of 20, HIP events)."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    t_us = event_median_us(lambda: dst.copy_(src), reps=20, warm=5)
+    return 2 * src.numel() * 4 / (t_us * 1e-6) / 1e9
+
+
+def spmv_roofline(prof, phase):
+    ms, cnt, byt = prof[phase]
+    achieved = byt / cnt / (ms / cnt / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": KERNEL_OF_PHASE.get(phase, phase), "phase": phase,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_us": round(1e3 * ms / cnt, 3),
+            "launches_timed": cnt, "timed_every": PROFILE_EVERY, "alg_bytes_per_launch": byt / cnt}
 
 
 def main():
@@ -74,7 +174,8 @@ def main():
 
     dev = "cuda:0"
     if args.study == "bfs":
-        bfs_study(B, driver, learned, build_workload, dev, args.study_steps, args.study_restart)
+        bfs_study(B, driver, learned, build_workload, dev, args.study_steps, args.study_restart,
+                  args.study_forms.split(","))
         return
     if args.study == "nr":
         nr_study(B, driver, build_workload, dev, args.workload)
@@ -101,57 +202,47 @@ def main():
                             pc=B.VMS_PC_LEARNED if weights is not None else B.VMS_PC_BLOCK_JACOBI,
                             pc_weights=weights)
 
-    def solve(ctx, weights=None):
+    def solve(ctx, weights=None, re=cfg.re):
         u = u0d.clone()
         beta = b0d.clone()
         torch.cuda.synchronize()
-        return driver.newton_solve(ctx, u, beta, cfg.re, tol=cfg.newton_tol, lin=lin_opts(weights), forcing="ew",
+        return driver.newton_solve(ctx, u, beta, re, tol=cfg.newton_tol, lin=lin_opts(weights), forcing="ew",
                                    max_newton=30)
 
     ctxs = {"fp64": B.Context(xyz, tets, dd, precision=B.VMS_FP64),
             "mixed": B.Context(xyz, tets, dd, precision=B.VMS_MIXED)}
     headline = "mixed"
 
-    # ---- assembly-only throughput (kernel time from HIP events on the launch stream)
+    # ---- metric 1: condensed tangents/s = n_elems / t(vms_condense_assemble)
     assembly = {}
     for name, ctx in ctxs.items():
-        A = ctx.new_bsr()
-        rhs = ctx.new_vec()
-        rn = torch.zeros(1, dtype=torch.float64, device=dev)
-        for _ in range(3):
-            B.vms_condense_assemble(ctx, u0d, b0d, cfg.re, 0.0, None, None, A, rhs, rn)
-        B.vms_profile(ctx, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = 20
-        for _ in range(reps):
-            B.vms_condense_assemble(ctx, u0d, b0d, cfg.re, 0.0, None, None, A, rhs, rn)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / reps
-        ms, cnt, byt = B.vms_profile_read(ctx)["condense"]
-        B.vms_profile(ctx, False)
-        assembly[name] = {"tangents_per_s": mesh.n_elems / (ms / cnt / 1e3),
-                          "kernel_us": 1e3 * ms / cnt, "call_us": 1e6 * wall,
-                          "alg_GBps": byt / ms / 1e6}
-        del A, rhs
+        assembly[name] = assembly_bench(B, ctx, mesh, u0d, b0d, cfg.re)
+        assembly[name]["roofline"] = assembly_roofline(assembly[name], mesh.n_elems, name == "mixed")
         log(f"assembly {name}: {assembly[name]}")
 
-    # ---- learned block-Jacobi correction: trained on the method's own condensed tangents and
-    # GMRES restart residuals (a mixed-precision Newton solve of this workload), checkpoints
-    # selected by GMRES iterations on the held-out last Newton system
+    # ---- learned block-Jacobi correction, held out: trained on the method's own condensed
+    # tangents and GMRES restart residuals from mixed-precision Newton solves of this mesh at
+    # other Reynolds numbers; checkpoints are scored by GMRES iterations on the last Newton
+    # system of each training solve, which are held out of the training batches
     t0 = time.perf_counter()
     ctx = ctxs["mixed"]
-    data, _ = learned.collect_newton_data(ctx, u0d.clone(), b0d.clone(), cfg.re,
-                                          lin=B.solve_opts(restart=50, rtol=1e-4, max_iters=60000), per_step=48)
-    # checkpoints are scored by GMRES iterations on the two last (hardest) Newton systems: the
-    # last one held out of training, the one before it a training system (first logged
-    # residual = the rhs)
-    val = [(A, S[0].contiguous()) for A, S in data[-2:]]
-    weights, train_report = learned.train_select(ctx, data[:-1] or data, val, seeds=(1, 2, 3), steps=200, lr=3e-4)
+    train, val = [], []
+    for re in TRAIN_RE:
+        d, _ = learned.collect_newton_data(ctx, u0d.clone(), b0d.clone(), re,
+                                           lin=B.solve_opts(restart=50, rtol=1e-4, max_iters=60000), per_step=48)
+        train += d[:-1]
+        val.append((d[-1][0], d[-1][1][0].contiguous()))
+    weights, train_report = learned.train_select(ctx, train or [v for v in val], val, seeds=(1, 2, 3), steps=200,
+                                                 lr=3e-4)
     train_report["seconds"] = time.perf_counter() - t0
-    log(f"learned PC: {train_report}")
+    train_report["training_systems"] = (f"cavity32 mixed Newton solves at Re {', '.join(f'{r:g}' for r in TRAIN_RE)}: "
+                                        f"{len(train)} systems for training, the last system of each solve "
+                                        f"({len(val)}) for checkpoint selection; the timed Re {cfg.re:g} solve "
+                                        f"is not among them")
+    log(f"learned PC: { {k: v for k, v in train_report.items() if k != 'runs'} }")
+    del train, val
 
-    # ---- time to 1e-8 in every form (one warm-up + one timed solve each)
+    # ---- metric 2: time to 1e-8 in every form (one warm-up + one timed solve each)
     forms = {}
     for name, ctx_name, w in (("fp64_bj", "fp64", None), ("mixed_bj", "mixed", None),
                               ("mixed_learned", "mixed", weights)):
@@ -194,26 +285,35 @@ def main():
     elapsed = time.perf_counter() - t0
     prof = B.vms_profile_read(ctx)
     B.vms_profile(ctx, False)
-    n_assemblies = sum(len(r.rnorms) - 1 for r in steps)
-    value = mesh.n_elems * n_assemblies / elapsed
 
-    ms, cnt, byt = prof[phase]
-    achieved = byt / cnt / (ms / cnt / 1e3) / 1e9
+    roofline = spmv_roofline(prof, phase)
     traffic, traffic_src = measured_traffic(args.workload, phase)
-    roofline = {"bound": "hbm", "kernel": KERNEL_OF_PHASE.get(phase, phase), "phase": phase,
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
-                "avg_launch_us": round(1e3 * ms / cnt, 3), "launches_timed": cnt, "timed_every": PROFILE_EVERY,
-                "alg_bytes_per_launch": byt / cnt}
+    roofline["traffic"] = traffic
+    roofline["traffic_source"] = traffic_src
+    # the 37 MB matrix of this size stays in the 256 MB Infinity Cache between launches: its
+    # bandwidth is also given against a copy of the same working set
+    probe = cache_probe_gbps(int(roofline["alg_bytes_per_launch"]) // 2)
+    roofline["cache_probe_GBps"] = round(probe, 1)
+    roofline["frac_vs_cache_probe"] = round(roofline["achieved"] / probe, 4)
+    log(f"roofline: {roofline}")
+    for c in ctxs.values():
+        c.close()
+    del ctxs
+    torch.cuda.empty_cache()
+
+    # ---- the 64^3 jittered cube: matrix and basis far beyond the caches
+    hbm = None
+    if not args.no_hbm_config:
+        hbm = hbm_config(B, build_workload, dev)
 
     # ---- CPU oracle baseline on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(mesh, u0, beta0, bc, cfg, args.cpu_sample)
+        cpu = cpu_baseline(mesh, u0, beta0, bc, cfg, args.cpu_sample, forms)
 
     out = {
         "metric": "condensed tangents/s + time-to-1e-8 Newton step, plain FP64 vs mixed+learned-PC",
-        "value": value,
+        "value": assembly[headline]["tangents_per_s"],
         "unit": "condensed tangents/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -224,19 +324,59 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if headline == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: lid-driven cavity 32^3 cells x 6 tets ({mesh.n_elems} tets, "
-                               f"{mesh.n_nodes} nodes), Re {cfg.re:g}, steady Newton to 1e-8, GMRES(50) + 4x4 "
-                               f"block-Jacobi (+ learned correction), form mixed_learned",
+        "config": {"workload": f"{args.workload}: " + WORKLOAD_TEXT.format(ne=mesh.n_elems, nn=mesh.n_nodes,
+                                                                          re=cfg.re),
                    "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes},
         "time_to_1e-8_s": {k: v["seconds"] for k, v in forms.items()},
+        "mixed_learned_speedup_vs_fp64_bj": forms["fp64_bj"]["seconds"] / forms["mixed_learned"]["seconds"],
         "forms": forms,
         "learned_pc": train_report,
         "assembly": assembly,
         "phases": phases,
         "roofline": roofline,
+        "hbm_config": hbm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def hbm_config(B, build_workload, dev, gmres_steps=150):
+    """es64 (64^3 jittered cube, 1,572,864 tets, first backward-Euler step of the Ethier-Steinman
+    flow): condensed assembly (FP64, mixed) and the Arnoldi SpMV (mixed, the first
+    gmres_steps Arnoldi steps of GMRES(50) on the mixed tangent, every launch event-timed)."""
+    import torch
+    cfg, mesh, u0, beta0, bc = build_workload("es64")
+    xyz = torch.from_numpy(mesh.xyz).to(dev)
+    tets = torch.from_numpy(mesh.tets).to(dev)
+    dd = torch.from_numpy(bc.dofs).to(dev)
+    u = torch.from_numpy(u0).to(dev)
+    b = torch.from_numpy(beta0).to(dev)
+    out = {"workload": f"es64: {mesh.n_elems} tets, {mesh.n_nodes} nodes, Re {cfg.re:g}, dt {cfg.dt:g}"}
+    for name, prec in (("fp64", B.VMS_FP64), ("mixed", B.VMS_MIXED)):
+        ctx = B.Context(xyz, tets, dd, precision=prec)
+        res = assembly_bench(B, ctx, mesh, u, b, cfg.re, cfg.dt, u)
+        res["roofline"] = assembly_roofline(res, mesh.n_elems, name == "mixed")
+        out[f"assembly_{name}"] = res
+        log(f"es64 assembly {name}: {res}")
+        if name == "mixed":
+            A, rhs, _ = B.vms_condense_assemble(ctx, u, b, cfg.re, cfg.dt, u)
+            x = ctx.new_vec()
+            B.vms_profile(ctx, True, phases=["spmv", "dots", "update"], every=1)
+            B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=50, rtol=1e-14, max_iters=gmres_steps),
+                              allow_noconv=True)
+            prof = B.vms_profile_read(ctx)
+            B.vms_profile(ctx, False)
+            out["spmv_mixed"] = spmv_roofline(prof, "spmv")
+            out["spmv_mixed"]["timed_every"] = 1
+            for p in ("dots", "update"):
+                ms, cnt, byt = prof[p]
+                out[f"{p}_mixed"] = {"avg_launch_us": round(1e3 * ms / cnt, 3),
+                                     "alg_GBps": round(byt / ms / 1e6, 1), "launches": cnt}
+            log(f"es64 spmv: {out['spmv_mixed']}")
+            del A, rhs, x
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
 
 
 def nr_study(B, driver, build_workload, dev, workload):
@@ -478,25 +618,96 @@ def counter_run(B, cfg, mesh, u0, beta0, bc, dev):
     print(json.dumps({"counter_run": True, "arnoldi_steps": int(info.iters), "copy_bytes": COPY_MIB << 20}))
 
 
-def cpu_baseline(mesh, u0, beta0, bc, cfg, n_sample):
-    """The oracle (quadrature element, condensation, CSR assembly) on the first n_sample
-    elements of the workload, timed on the host cores."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_assembly_rate(n_sample, threads):
+    """Oracle condensed-assembly rate (tangents/s) on the first n_sample elements of cavity32, in a
+    child process with OMP_NUM_THREADS = threads (the OpenMP runtime reads it at load)."""
+    code = ("import sys, time, json; sys.path.insert(0, %r)\n"
+            "from workloads import build_workload\n"
+            "from oracle import vms as O\n"
+            "from oracle.element import element_residual_tangent\n"
+            "cfg, m, u, b, bc = build_workload('cavity32')\n"
+            "t = m.tets[:%d]\n"
+            "t0 = time.perf_counter()\n"
+            "R, K = element_residual_tangent(m.xyz, t, u, b[:%d], 1.0 / cfg.re)\n"
+            "Ks, Rs = O.condense(R, K)\n"
+            "O.assemble_matrix(t, m.n_nodes, Ks, bc.dofs)\n"
+            "O.assemble_vector(t, m.n_nodes, Rs)\n"
+            "print(json.dumps(time.perf_counter() - t0))\n") % (ROOT, n_sample, n_sample)
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    dt = json.loads(out.stdout.strip().splitlines()[-1])
+    return n_sample / dt, dt
+
+
+def cpu_baseline(mesh, u0, beta0, bc, cfg, n_sample, forms):
+    """The oracle (quadrature element, condensation, CSR assembly, GMRES with block-Jacobi and
+    modified Gram-Schmidt, Newton) timed on the host cores.  value: the same metric as the
+    bench line, n_elems / t(condensed assembly), on the first n_sample elements (all by default)
+    with every OpenMP thread; then the same on a smaller sample with one thread, one GMRES(50)
+    cycle on the assembled cavity 32^3 system, the Newton solve of cavity 4^3 (Re 1) to 1e-10
+    measured, and the cavity 32^3 time to 1e-8 extrapolated from the measured per-phase costs and
+    the GPU FP64 solve's Newton and GMRES iteration counts."""
     import numpy as np
     from oracle import vms as O
     from oracle.element import element_residual_tangent
+    from workloads import build_workload
 
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n_sample = mesh.n_elems if n_sample <= 0 else min(n_sample, mesh.n_elems)
     tets = mesh.tets[:n_sample]
     t0 = time.perf_counter()
     R, K = element_residual_tangent(mesh.xyz, tets, u0, beta0[:n_sample], 1.0 / cfg.re)
     Ks, Rs = O.condense(R, K)
-    O.assemble_matrix(tets, mesh.n_nodes, Ks, bc.dofs)
-    O.assemble_vector(tets, mesh.n_nodes, Rs)
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n_sample / dt, "unit": "condensed tangents/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_sample} of {mesh.n_elems} elements, one condensed assembly at the initial state: "
-                      f"quadrature element + condensation + CSR assembly ({dt:.1f} s)"}
+    A = O.assemble_matrix(tets, mesh.n_nodes, Ks, bc.dofs)
+    b = -O.assemble_vector(tets, mesh.n_nodes, Rs)
+    t_asm = time.perf_counter() - t0
+    out = {"value": n_sample / t_asm, "unit": "condensed tangents/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n_sample} of {mesh.n_elems} elements, one condensed assembly at the initial state: "
+                     f"quadrature element + condensation + CSR assembly ({t_asm:.1f} s)",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    st_n = min(8000, mesh.n_elems)
+    rate1, dt1 = oracle_assembly_rate(st_n, 1)
+    out["single_thread"] = {"value": rate1, "unit": "condensed tangents/s", "cores": 1,
+                            "sample": f"{st_n} elements ({dt1:.1f} s)"}
+    extra = {}
+    if n_sample == mesh.n_elems:
+        b[bc.dofs] = 0.0
+        Minv = O.block_jacobi_inverse(A, mesh.n_nodes)
+        t0 = time.perf_counter()
+        res = O.gmres(A, b, restart=50, max_iters=50, rtol=1e-14, Minv_blocks=Minv)
+        t_cyc = time.perf_counter() - t0
+        extra["gmres50_cycle_s"] = t_cyc
+        extra["gmres50_cycle_iters"] = int(res.iters)
+        f = forms.get("fp64_bj")
+        if f:
+            # per Newton step: one assembly (as timed) and one residual evaluation (about the
+            # element part of it); per GMRES iteration: the cycle time / 50
+            per_iter = t_cyc / max(1, res.iters)
+            est = f["newton_steps"] * 2 * t_asm + f["gmres_iters"] * per_iter
+            extra["time_to_1e-8_cavity32_s"] = {
+                "value": est, "kind": "extrapolation",
+                "from": f"{f['newton_steps']} Newton steps x 2 assemblies ({t_asm:.2f} s each) + "
+                        f"{f['gmres_iters']} GMRES iterations x {per_iter * 1e3:.1f} ms (the GPU FP64 solve's counts)"}
+    cfg1, m1, u1, b1, bc1 = build_workload("cavity4")
+    prob = O.Problem(m1.xyz, m1.tets, bc1.dofs, nu=1.0 / cfg1.re)
+    t0 = time.perf_counter()
+    _, _, lg = O.newton_solve(prob, u1, b1, tol=cfg1.newton_tol, linear="gmres", rtol=cfg1.linear_rtol)
+    extra["time_to_1e-10_cavity4_s"] = {"value": time.perf_counter() - t0, "kind": "measured",
+                                        "newton_steps": len(lg.rnorms) - 1,
+                                        "gmres_iters": int(sum(lg.lin_iters))}
+    out["extra"] = extra
+    return out
 
 
 if __name__ == "__main__":

@@ -178,6 +178,9 @@ typedef struct {
                                   continues from its iterate with plain block-Jacobi)     */
     double true_rel_res;       /* final ||b - A x|| / ||b|| recomputed in FP64           */
     int32_t logged;            /* residuals written to log_residuals                      */
+    int32_t singular_blocks;   /* node diagonal blocks found numerically singular by the last
+                                  preconditioner setup; each is applied as the identity (the
+                                  true residual still decides convergence)                */
 } vms_solve_info;
 
 /* Right-preconditioned restarted GMRES(m) on A x = b (Section 6 names a

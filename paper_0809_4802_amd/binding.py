@@ -66,7 +66,7 @@ class SolveOpts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("refinements", ctypes.c_int32),
                 ("fell_back_to_bj", ctypes.c_int32), ("true_rel_res", ctypes.c_double),
-                ("logged", ctypes.c_int32)]
+                ("logged", ctypes.c_int32), ("singular_blocks", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

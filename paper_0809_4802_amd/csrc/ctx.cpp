@@ -124,9 +124,9 @@ static void free_all(vms_ctx* c) {
         c->full = nullptr;
     }
     void* ptrs[] = {c->full_cc, c->full_epos, c->zfull, c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
-                    c->tpos, c->tile_node0, c->tile_iptr, c->item_ea, c->item_pos, c->A, c->rhs, c->du, c->rglob, c->rnorm, c->flags,
+                    c->tpos, c->tile_node0, c->tile_iptr, c->item_ea, c->item_pos, c->bmask, c->tile_part, c->A, c->rhs, c->du, c->rnorm, c->flags,
                     c->V, c->w, c->z, c->d, c->r, c->Minv, c->AP, c->Az, c->x64, c->r64, c->gs, c->red,
-                    c->feats, c->hid, c->pblk, c->gblk, c->tvec, c->wgrad, c->fscal};
+                    c->feats, c->hid, c->pblk, c->gblk, c->gdel, c->tvec, c->wgrad, c->fscal};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto e : c->prof_ev)
@@ -444,8 +444,9 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
             for (auto& it : list) {
                 const int32_t e = it.first, a = it.second;
                 const int32_t row = tets[4 * (int64_t)e + a];
+                // slots in the item's vertex order a, a^1, a^2, a^3 (owned vertex first)
                 uint32_t p[4];
-                for (int b = 0; b < 4; ++b) p[b] = (uint32_t)(find(row, tets[4 * (int64_t)e + b]) - b0);
+                for (int b = 0; b < 4; ++b) p[b] = (uint32_t)(find(row, tets[4 * (int64_t)e + (b ^ a)]) - b0);
                 iea.push_back(4 * e + a);
                 ipos.push_back(make_uint2(p[0] | (p[1] << 16), p[2] | (p[3] << 16)));
             }
@@ -480,10 +481,11 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->tile_iptr, tiptr.size() * sizeof(int32_t), "alloc tiles"));
     TRY(dev_alloc(c, &c->item_ea, iea.size() * sizeof(int32_t), "alloc tile items"));
     TRY(dev_alloc(c, &c->item_pos, ipos.size() * sizeof(uint2), "alloc tile items"));
+    TRY(dev_alloc(c, &c->bmask, c->nb * sizeof(uint16_t), "alloc block masks"));
+    TRY(dev_alloc(c, &c->tile_part, 2 * (size_t)c->n_tiles * sizeof(double), "alloc tile partials"));
     TRY(dev_alloc(c, &c->A, c->nb * 16 * es, "alloc A"));
     TRY(dev_alloc(c, &c->rhs, N * sizeof(double), "alloc rhs"));
     TRY(dev_alloc(c, &c->du, N * sizeof(double), "alloc du"));
-    TRY(dev_alloc(c, &c->rglob, N * sizeof(double), "alloc rglob"));
     TRY(dev_alloc(c, &c->rnorm, 8 * sizeof(double), "alloc rnorm"));
     TRY(dev_alloc(c, &c->flags, 8 * sizeof(int32_t), "alloc flags"));
     TRY(dev_alloc(c, &c->V, (size_t)(c->max_restart + 1) * N * es, "alloc Krylov basis"));
@@ -502,6 +504,7 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->hid, nn * VMS_PC_NHID * sizeof(float), "alloc hidden"));
     TRY(dev_alloc(c, &c->pblk, nn * 16 * sizeof(float), "alloc pblk"));
     TRY(dev_alloc(c, &c->gblk, nn * 16 * sizeof(float), "alloc gblk"));
+    TRY(dev_alloc(c, &c->gdel, nn * 16 * sizeof(float), "alloc gdel"));
     TRY(dev_alloc(c, &c->tvec, 3 * N * sizeof(float), "alloc tvec"));
     TRY(dev_alloc(c, &c->wgrad, (size_t)kRedBlocks * VMS_PC_NWEIGHTS * sizeof(float), "alloc wgrad"));
     TRY(dev_alloc(c, &c->fscal, 8 * sizeof(float), "alloc fscal"));
@@ -532,6 +535,13 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(check_hip(c, hipMemcpy(c->tile_iptr, tiptr.data(), tiptr.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     TRY(check_hip(c, hipMemcpy(c->item_ea, iea.data(), iea.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     TRY(check_hip(c, hipMemcpy(c->item_pos, ipos.data(), ipos.size() * sizeof(uint2), hipMemcpyHostToDevice), "upload"));
+    {
+        std::vector<uint16_t> bm(c->nb);
+        for (int64_t i = 0; i < nn; ++i)
+            for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                bm[k] = (uint16_t)((dmask[colidx[k]] & 0xFu) | ((dmask[i] & 0xFu) << 4) | (colidx[k] == i ? 0x100u : 0u));
+        TRY(check_hip(c, hipMemcpy(c->bmask, bm.data(), c->nb * sizeof(uint16_t), hipMemcpyHostToDevice), "upload"));
+    }
     TRY(check_hip(c, tile_kernels_configure(c), "configure tile kernels"));
     TRY(check_hip(c, hipMemset(c->red, 0, sizeof(RedScratch)), "clear"));
     TRY(check_hip(c, hipMemset(c->gs, 0, sizeof(GmresState)), "clear"));

@@ -317,19 +317,32 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Tiled assembly.  Workgroup t owns the block rows of nodes [n0, n1) (a contiguous range, so
 // its rows are the contiguous block range [rowptr[n0], rowptr[n1])) and stages them, with the
 // rhs and residual rows, in LDS.  Its work items are the pairs (element e, local vertex a)
-// with vertex a owned by the tile; an item evaluates the element's shared quantities
-// (geometry, fields, R_f, K_ff^-1), its rows a:
-//   R*_a = R_cp,a - K_cf(a) K_ff^-1 R_f,   Y(a) = K_cf(a) K_ff^-1,
-//   K*(a,b) = K_cc(a,b) - Y(a) K_fc(b)   for b = 0..3 (column by column),
-// and adds them to the staged rows with LDS atomics.  The tile then sets the Dirichlet unit
-// diagonals and writes its rows once with coalesced stores: no global atomics, no zero fill,
-// every condensed block computed exactly once.  Item slots (tile-local block index of (a, b))
-// come precomputed from the host.
-//   CONDENSE = true : K* into Aval, -R* into rhs, R_cp into rglob, |R_f|^2 into slots
-//   CONDENSE = false: R_cp into rglob, |R_f|^2 into slots (residual only)
+// with vertex a owned by the tile.  An item takes the element's vertices in the order
+// (a, a^1, a^2, a^3), an even permutation (so the orientation and every element integral are
+// unchanged), which puts the owned vertex first: every quantity of "the row's vertex" is then
+// vertex 0's, with no per-lane selection.  The item forms the element's geometry, fields,
+// R_f and K_ff^-1 (FP64), its own rows
+//   R*_0 = R_cp,0 - K_cf(0) K_ff^-1 R_f,   Y = K_cf(0) K_ff^-1 (4x3),
+// and the condensed blocks K*(0, b) = K_cc(0, b) - Y K_fc(b), b = 0..3, which it adds to the
+// staged rows with LDS atomics.  The blocks are factored once per item so that each entry
+// costs two or three FMAs (see block_factors).  After a barrier the tile writes its rows once
+// with coalesced stores, and there the Dirichlet dofs are eliminated: a row or column of a
+// prescribed dof becomes zero, its diagonal entry one, its rhs and residual entries zero (the
+// per-block masks come precomputed from the host).  No global atomics, no zero fill, every
+// condensed block computed exactly once.  Each tile also leaves two partial sums of the Newton
+// residual norm (its free residual rows squared, and |R_f|^2 of the elements whose first
+// vertex it owns), which a one-workgroup kernel adds in a fixed order.
+//   CONDENSE = true : K* into Aval, -R* into rhs, R_cp into rglob (if not null), partials
+//   CONDENSE = false: R_cp into rglob (if not null), partials (residual only)
 //   SCHUR = false (with CONDENSE): the coarse blocks without condensation, K_cc into Aval and
 //   -R_cp into rhs (the node-node part of the uncondensed system)
-constexpr int kTileThreads = 512;
+#ifndef VMS_TILE_THREADS
+#define VMS_TILE_THREADS 256
+#endif
+constexpr int kTileThreads = VMS_TILE_THREADS;
+#ifndef VMS_TILE_WAVES_PER_SIMD
+#define VMS_TILE_WAVES_PER_SIMD 3
+#endif
 
 struct TileArgs {
     const int32_t* __restrict__ node0;
@@ -337,13 +350,64 @@ struct TileArgs {
     const int32_t* __restrict__ ea;
     const uint2* __restrict__ pos;
     const int32_t* __restrict__ rowptr;
-    const int32_t* __restrict__ diagpos;
+    const uint16_t* __restrict__ bmask;   // per block: column node's Dirichlet bits (0..3),
+                                          // row node's (4..7), diagonal block (bit 8)
 };
 
+// Factors of the condensed blocks of one item (row vertex 0), in precision T.  With
+// Gt = adv G, bt = adv beta (the advecting-velocity terms), m_0b = (1 + delta_0b) |T| / 20,
+// for rows r = 0..3 and velocity columns c = 0..2:
+//   K*(0,b)[r][c] = P[r][c] + (r < 3) m_0b Gt[r][c] + q[r] g_b[c] - Y[r][c] d_b + delta_rc s_b
+// with  P[r][c] = -B1 (bt[r] g_0[c] + (Y Gt)[r][c])  (r < 3),  P[3][c] = -B1 (Y Gt)[3][c],
+//       q[r] = -B1 bt[r] + C/2 (Y bt)[r]  (r < 3),          q[3] = -|T|/4 + C/2 (Y bt)[3],
+//       s_b = g_b . (V_0 + 2 nu |T| g_0 + B1 beta) + m_0b / dt,   d_b = g_b . (W + C beta) + B1 / dt,
+// and the pressure column  K*(0,b)[r][3] = pc[r] - B (Y g_b)[r],  pc = (-|T|/4 g_0, 0).
+// This is K_cc(0,b) - Y K_fc(b) with the closed-form blocks written out and regrouped by
+// their dependence on b.
+template <typename T>
+struct BlockFactors {
+    T Y[4][3];
+    T P[4][3];
+    T q[4];
+    T pc[3];
+    T Gt[3][3];
+    T sv[3], dv[3];
+    T g[4][3];
+    T m0, idt, B1idt, Bm;
+};
+
+// One item's four condensed blocks added to the staged rows.
+template <typename T, typename TACC>
+__device__ __forceinline__ void add_blocks(const BlockFactors<T>& F, TACC* __restrict__ blk, const uint32_t slot[4]) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const T* gb = F.g[b];
+        const T mab = b == 0 ? T(2) * F.m0 : F.m0;
+        const T s_b = gb[0] * F.sv[0] + gb[1] * F.sv[1] + gb[2] * F.sv[2] + mab * F.idt;
+        const T d_b = gb[0] * F.dv[0] + gb[1] * F.dv[1] + gb[2] * F.dv[2] + F.B1idt;
+        TACC* dst = blk + (size_t)slot[b] * kLdsBlockStride;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T v = F.P[r][c];
+                if (r < 3) v += mab * F.Gt[r][c];
+                v += F.q[r] * gb[c];
+                v -= F.Y[r][c] * d_b;
+                if (r == c) v += s_b;
+                atomic_add(&dst[r * 4 + c], TACC(v));
+            }
+            const T yg = F.Y[r][0] * gb[0] + F.Y[r][1] * gb[1] + F.Y[r][2] * gb[2];
+            const T vp = (r < 3 ? F.pc[r] : T(0)) - F.Bm * yg;
+            atomic_add(&dst[r * 4 + 3], TACC(vp));
+        }
+    }
+}
+
 template <typename T, typename TACC, bool CONDENSE, bool SCHUR = true>
-__global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, TileArgs ta, T* __restrict__ Aval,
-                                                               double* __restrict__ rhs, double* __restrict__ rglob,
-                                                               double* __restrict__ red_slots) {
+__global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
+    ElemArgs args, TileArgs ta, T* __restrict__ Aval, double* __restrict__ rhs, double* __restrict__ rglob,
+    double* __restrict__ tile_part) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = blockIdx.x;
     const int n0 = ta.node0[t], n1 = ta.node0[t + 1], nn = n1 - n0;
@@ -352,6 +416,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
     const size_t off = CONDENSE ? align16((size_t)nbk * kLdsBlockStride * sizeof(TACC)) : 0;
     double* rr = reinterpret_cast<double*>(smem + off);
     double* rg = rr + (size_t)nn * 4;
+    __shared__ double wsum[kTileThreads / 64][2];
 
     if (CONDENSE)
         for (int i = threadIdx.x; i < nbk * kLdsBlockStride; i += blockDim.x) blk[i] = TACC(0);
@@ -369,7 +434,22 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
     for (int k = ta.iptr[t] + threadIdx.x; k < k_end; k += blockDim.x) {
         const int ea = ta.ea[k];
         const int e = ea >> 2, a = ea & 3;
-        const int4 tv = args.tets[e];
+        int4 tv = args.tets[e];
+        // vertex order (a, a^1, a^2, a^3): the owned vertex first, orientation kept
+        if (a & 1) {
+            const int x = tv.x, z = tv.z;
+            tv.x = tv.y;
+            tv.y = x;
+            tv.z = tv.w;
+            tv.w = z;
+        }
+        if (a & 2) {
+            const int x = tv.x, y = tv.y;
+            tv.x = tv.z;
+            tv.y = tv.w;
+            tv.z = x;
+            tv.w = y;
+        }
         const int nid[4] = {tv.x, tv.y, tv.z, tv.w};
         // geometry
         double X[4][3];
@@ -413,9 +493,9 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
         const double B1 = kB1 * vol, Bm = kB * vol, Cm = kC * vol, Kb = kKb * vol * gg;
         const double m0 = vol * (1.0 / 20.0);
 
-        // fields: G = grad vbar, grad p, sums over vertices; quantities of vertex a
-        double G[3][3] = {}, gp[3] = {}, vs[3] = {}, ps = 0.0, va[3] = {}, ga[3] = {};
-        double dvs[3] = {}, dva[3] = {}, fs[3] = {}, fa[3] = {};
+        // fields: G = grad vbar, grad p, sums over vertices; vertex 0's own values
+        double G[3][3] = {}, gp[3] = {}, vs[3] = {}, ps = 0.0, v0[3] = {};
+        double dvs[3] = {}, dv0[3] = {}, fs[3] = {}, f0[3] = {};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const double4 uu = reinterpret_cast<const double4*>(args.u)[nid[q]];
@@ -426,8 +506,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
                 for (int j = 0; j < 3; ++j) G[i][j] += vq[i] * g[q][j];
                 gp[i] += uu.w * g[q][i];
                 vs[i] += vq[i];
-                va[i] = (q == a) ? vq[i] : va[i];
-                ga[i] = (q == a) ? g[q][i] : ga[i];
+                if (q == 0) v0[i] = vq[i];
             }
             ps += uu.w;
             if (transient) {
@@ -436,7 +515,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     dvs[i] += d[i];
-                    dva[i] = (q == a) ? d[i] : dva[i];
+                    if (q == 0) dv0[i] = d[i];
                 }
             }
             if (args.body) {
@@ -444,7 +523,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
                 for (int i = 0; i < 3; ++i) {
                     const double f = args.body[3 * (size_t)nid[q] + i];
                     fs[i] += f;
-                    fa[i] = (q == a) ? f : fa[i];
+                    if (q == 0) f0[i] = f;
                 }
             }
         }
@@ -455,9 +534,9 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             Wv[i] = B1 * vs[i];
-            Va[i] = m0 * (vs[i] + va[i]);
+            Va[i] = m0 * (vs[i] + v0[i]);
         }
-        // fine-scale residual and block
+        // fine-scale residual (counted in the norm once per element: by its first vertex's item)
         double Rf[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -465,22 +544,25 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
                     Cm * (G[i][0] * be[0] + G[i][1] * be[1] + G[i][2] * be[2] - 0.5 * th * be[i]) +
                     2.0 * nu * Kb * be[i] + Bm * gp[i] - B1 * fs[i] + inv_dt * B1 * dvs[i];
         if (a == 0) rf2 += Rf[0] * Rf[0] + Rf[1] * Rf[1] + Rf[2] * Rf[2];
-        // coarse residual rows of vertex a
-        const double gaW = ga[0] * Wv[0] + ga[1] * Wv[1] + ga[2] * Wv[2];
-        const double bga = be[0] * ga[0] + be[1] * ga[1] + be[2] * ga[2];
+        // coarse residual rows of vertex 0
+        const double g0W = g[0][0] * Wv[0] + g[0][1] * Wv[1] + g[0][2] * Wv[2];
+        const double bg0 = be[0] * g[0][0] + be[1] * g[0][1] + be[2] * g[0][2];
         double Rc[4];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
             Rc[i] = G[i][0] * (Va[0] + B1 * be[0]) + G[i][1] * (Va[1] + B1 * be[1]) + G[i][2] * (Va[2] + B1 * be[2]) -
-                    (gaW + th * B1 + 0.5 * Cm * bga) * be[i] +
-                    2.0 * nu * vol * (G[i][0] * ga[0] + G[i][1] * ga[1] + G[i][2] * ga[2]) - 0.25 * vol * ps * ga[i] -
-                    m0 * (fs[i] + fa[i]) + inv_dt * m0 * (dvs[i] + dva[i]);
-        Rc[3] = -th * vol * 0.25 + Bm * bga;
-        const uint32_t dma = args.dmask[nid[a]];
-        const int la = nid[a] - n0;
-        double Kcf[4][3];
-        double Ki[3][3];
-        if (CONDENSE && SCHUR) {
+                    (g0W + th * B1 + 0.5 * Cm * bg0) * be[i] +
+                    2.0 * nu * vol * (G[i][0] * g[0][0] + G[i][1] * g[0][1] + G[i][2] * g[0][2]) -
+                    0.25 * vol * ps * g[0][i] - m0 * (fs[i] + f0[i]) + inv_dt * m0 * (dvs[i] + dv0[i]);
+        Rc[3] = -th * vol * 0.25 + Bm * bg0;
+        const int la = nid[0] - n0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) atomic_add(&rg[4 * la + r], Rc[r]);
+        if (!CONDENSE) continue;
+
+        // Y = K_cf(0) K_ff^-1 (FP64, stored in T) and R*_0; zero without condensation
+        double Yd[4][3] = {};
+        if (SCHUR) {
             const double dk = 2.0 * nu * Kb - 0.5 * Cm * th;
             double Kff[3][3];
 #pragma unroll
@@ -496,6 +578,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
             for (int i = 0; i < 3; ++i) knrm = fmax(knrm, fabs(Kff[i][0]) + fabs(Kff[i][1]) + fabs(Kff[i][2]));
             if (!(fabs(kdet) > 1e-14 * knrm * knrm * knrm)) atomicMin(&args.flags[1], e);
             const double kid = 1.0 / kdet;
+            double Ki[3][3];
             Ki[0][0] = k00 * kid;
             Ki[0][1] = (Kff[0][2] * Kff[2][1] - Kff[0][1] * Kff[2][2]) * kid;
             Ki[0][2] = (Kff[0][1] * Kff[1][2] - Kff[0][2] * Kff[1][1]) * kid;
@@ -505,113 +588,107 @@ __global__ __launch_bounds__(kTileThreads, 2) void tile_kernel(ElemArgs args, Ti
             Ki[2][0] = k02 * kid;
             Ki[2][1] = (Kff[0][1] * Kff[2][0] - Kff[0][0] * Kff[2][1]) * kid;
             Ki[2][2] = (Kff[0][0] * Kff[1][1] - Kff[0][1] * Kff[1][0]) * kid;
-            // K_cf(a): velocity rows, then the pressure row
-            const double dg = -(gaW + th * B1) - 0.5 * Cm * bga;
+            // K_cf(0): velocity rows, then the pressure row
+            const double dg = -(g0W + th * B1) - 0.5 * Cm * bg0;
+            double Kcf[4][3];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
-                    Kcf[i][j] = args.adv * (B1 * G[i][j] - 0.5 * Cm * be[i] * ga[j]) + (i == j ? dg : 0.0);
+                    Kcf[i][j] = args.adv * (B1 * G[i][j] - 0.5 * Cm * be[i] * g[0][j]) + (i == j ? dg : 0.0);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) Kcf[3][j] = Bm * ga[j];
+            for (int j = 0; j < 3; ++j) Kcf[3][j] = Bm * g[0][j];
             double zf[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) zf[i] = Ki[i][0] * Rf[0] + Ki[i][1] * Rf[1] + Ki[i][2] * Rf[2];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const double rs = Rc[r] - (Kcf[r][0] * zf[0] + Kcf[r][1] * zf[1] + Kcf[r][2] * zf[2]);
-                if (!(dma & (1u << r))) atomic_add(&rr[4 * la + r], -rs);
-            }
-        } else if (CONDENSE) {
+                atomic_add(&rr[4 * la + r], -rs);
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (!(dma & (1u << r))) atomic_add(&rr[4 * la + r], -Rc[r]);
+                for (int j = 0; j < 3; ++j)
+                    Yd[r][j] = Kcf[r][0] * Ki[0][j] + Kcf[r][1] * Ki[1][j] + Kcf[r][2] * Ki[2][j];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) atomic_add(&rr[4 * la + r], -Rc[r]);
+        }
+
+        // block factors in T
+        BlockFactors<T> F;
+        const double av = args.adv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) F.g[q][i] = T(g[q][i]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) F.Gt[i][j] = T(av * G[i][j]);
+        T bt[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            bt[i] = T(av * be[i]);
+            F.sv[i] = T(Va[i] + 2.0 * nu * vol * g[0][i] + B1 * be[i]);
+            F.dv[i] = T(Wv[i] + Cm * be[i]);
+            F.pc[i] = T(-0.25 * vol * g[0][i]);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            if (!(dma & (1u << r))) atomic_add(&rg[4 * la + r], Rc[r]);
-        if (!CONDENSE) continue;
-
-        // Y(a) = K_cf(a) K_ff^-1 (FP64 product, kept in T); zero without condensation
-        T Y[4][3];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+            for (int j = 0; j < 3; ++j) F.Y[r][j] = T(Yd[r][j]);
+        const T B1t = T(B1), hCt = T(0.5 * Cm);
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-                Y[r][j] = SCHUR ? T(Kcf[r][0] * Ki[0][j] + Kcf[r][1] * Ki[1][j] + Kcf[r][2] * Ki[2][j]) : T(0);
-        T keep_r[4];
+        for (int r = 0; r < 4; ++r) {
+            T yb = F.Y[r][0] * bt[0] + F.Y[r][1] * bt[1] + F.Y[r][2] * bt[2];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) keep_r[r] = (dma & (1u << r)) ? T(0) : T(1);
-        // the advecting-velocity terms (weight adv) of K_vv and K_fv
-        const double av = args.adv;
-        const T Gt[3][3] = {{T(av * G[0][0]), T(av * G[0][1]), T(av * G[0][2])},
-                            {T(av * G[1][0]), T(av * G[1][1]), T(av * G[1][2])},
-                            {T(av * G[2][0]), T(av * G[2][1]), T(av * G[2][2])}};
-        const T bt[3] = {T(av * be[0]), T(av * be[1]), T(av * be[2])};
-        const T gat[3] = {T(ga[0]), T(ga[1]), T(ga[2])};
-        const T B1t = T(B1), hCt = T(0.5 * Cm), qv = T(-0.25 * vol);
+            for (int c = 0; c < 3; ++c) {
+                const T yg = F.Y[r][0] * F.Gt[0][c] + F.Y[r][1] * F.Gt[1][c] + F.Y[r][2] * F.Gt[2][c];
+                F.P[r][c] = -B1t * ((r < 3 ? bt[r] * F.g[0][c] : T(0)) + yg);
+            }
+            F.q[r] = (r < 3 ? -B1t * bt[r] : T(-0.25 * vol)) + hCt * yb;
+        }
+        F.m0 = T(m0);
+        F.idt = T(inv_dt);
+        F.B1idt = T(B1 * inv_dt);
+        F.Bm = T(Bm);
         const uint2 pp = ta.pos[k];
         const uint32_t slot[4] = {pp.x & 0xffffu, pp.x >> 16, pp.y & 0xffffu, pp.y >> 16};
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const T gb[3] = {T(g[b][0]), T(g[b][1]), T(g[b][2])};
-            const uint32_t dmb = args.dmask[nid[b]];
-            const double mab = (b == a) ? 2.0 * m0 : m0;
-            // scalar of the K_vv identity part and of the K_fv identity part
-            const T s_ab = T(g[b][0] * Va[0] + g[b][1] * Va[1] + g[b][2] * Va[2] + mab * inv_dt +
-                             2.0 * nu * vol * (ga[0] * g[b][0] + ga[1] * g[b][1] + ga[2] * g[b][2]) +
-                             B1 * (g[b][0] * be[0] + g[b][1] * be[1] + g[b][2] * be[2]));
-            const T d_b = T(g[b][0] * Wv[0] + g[b][1] * Wv[1] + g[b][2] * Wv[2] +
-                            Cm * (g[b][0] * be[0] + g[b][1] * be[1] + g[b][2] * be[2]) + B1 * inv_dt);
-            const T mabt = T(mab);
-            TACC* dst = blk + (size_t)slot[b] * kLdsBlockStride;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                T kfc[3], kcc[4];
-                if (c < 3) {
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        kfc[i] = B1t * Gt[i][c] - hCt * bt[i] * gb[c] + (i == c ? d_b : T(0));
-                        kcc[i] = mabt * Gt[i][c] - B1t * bt[i] * (gat[c] + gb[c]) + (i == c ? s_ab : T(0));
-                    }
-                    kcc[3] = qv * gb[c];
-                } else {
-                    const T Bt = T(Bm);
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        kfc[i] = Bt * gb[i];
-                        kcc[i] = qv * gat[i];
-                    }
-                    kcc[3] = T(0);
-                }
-                const T keep_c = (dmb & (1u << c)) ? T(0) : T(1);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const T val = kcc[r] - (Y[r][0] * kfc[0] + Y[r][1] * kfc[1] + Y[r][2] * kfc[2]);
-                    atomic_add(&dst[r * 4 + c], TACC(val * keep_r[r] * keep_c));
-                }
-            }
-        }
+        add_blocks<T, TACC>(F, blk, slot);
     }
     __syncthreads();
     if (CONDENSE) {
-        // unit diagonal on the Dirichlet dofs of owned nodes
-        for (int i = threadIdx.x; i < nn; i += blockDim.x) {
-            const uint32_t d = args.dmask[n0 + i];
-            if (!d) continue;
-            const int p = ta.diagpos[n0 + i] - b0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (d & (1u << r)) blk[(size_t)p * kLdsBlockStride + r * 5] = TACC(1);
-        }
-        __syncthreads();
+        // write the rows once, eliminating the Dirichlet dofs: zero rows and columns, unit diagonal
         T* gdst = Aval + (size_t)b0 * 16;
-        for (int i = threadIdx.x; i < nbk * 16; i += blockDim.x) gdst[i] = T(blk[(i >> 4) * kLdsBlockStride + (i & 15)]);
-        for (int i = threadIdx.x; i < nn * 4; i += blockDim.x) rhs[4 * (size_t)n0 + i] = rr[i];
+        for (int i = threadIdx.x; i < nbk * 16; i += blockDim.x) {
+            const int kb = i >> 4, r = (i >> 2) & 3, c = i & 3;
+            const uint32_t bm = ta.bmask[b0 + kb];
+            T v = T(blk[kb * kLdsBlockStride + (i & 15)]);
+            if (((bm >> (4 + r)) | (bm >> c)) & 1u) v = ((bm & 0x100u) && r == c) ? T(1) : T(0);
+            gdst[i] = v;
+        }
     }
-    for (int i = threadIdx.x; i < nn * 4; i += blockDim.x) rglob[4 * (size_t)n0 + i] = rg[i];
+    double rg2 = 0.0;
+    for (int i = threadIdx.x; i < nn * 4; i += blockDim.x) {
+        const bool fixed = (args.dmask[n0 + (i >> 2)] >> (i & 3)) & 1u;
+        const double rv = fixed ? 0.0 : rg[i];
+        rg2 += rv * rv;
+        if (rglob) rglob[4 * (size_t)n0 + i] = rv;
+        if (CONDENSE) rhs[4 * (size_t)n0 + i] = fixed ? 0.0 : rr[i];
+    }
+    rg2 = wave_sum(rg2);
     rf2 = wave_sum(rf2);
-    if ((threadIdx.x & 63) == 0 && rf2 != 0.0) atomic_add(&red_slots[(blockIdx.x & 63) * 8], rf2);
+    if ((threadIdx.x & 63) == 0) {
+        wsum[threadIdx.x >> 6][0] = rg2;
+        wsum[threadIdx.x >> 6][1] = rf2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kTileThreads / 64; ++w) s += wsum[w][threadIdx.x];
+        tile_part[2 * (size_t)t + threadIdx.x] = s;
+    }
 }
 
 // Raw element residual and 19x19 tangent (tangent blocks in T, K_ff in FP64).
@@ -715,44 +792,22 @@ __global__ void update_kernel(int n_nodes, const uint8_t* __restrict__ dmask, co
     u[i] += du[i];
 }
 
-// Newton residual norm: free-dof sum of rglob^2 plus the |R_f|^2 slots.
-__global__ __launch_bounds__(kBlock) void norm_finalize_kernel(int n, const double* __restrict__ rglob,
-                                                               const double* __restrict__ slots,
-                                                               RedScratch* red, double* out) {
+// Newton residual norm from the assembly tiles' partial sums (free residual rows squared,
+// |R_f|^2), added in a fixed order by one workgroup: thread i takes partials i, i + 1024, ...,
+// then a fixed tree over the waves.
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void norm_finalize_kernel(int n_tiles, const double* __restrict__ part,
+                                                                     double* __restrict__ out) {
     double s = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        s += rglob[i] * rglob[i];
+    for (int i = threadIdx.x; i < 2 * n_tiles; i += kFinThreads) s += part[i];
     s = wave_sum(s);
-    __shared__ double ws[kBlock / 64];
+    __shared__ double ws[kFinThreads / 64];
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
-    __syncthreads();
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        double b = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) b += ws[w];
-        red->partial[blockIdx.x] = b;
-        __threadfence();
-        const unsigned prev = atomicAdd(&red->counter, 1u);
-        last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // all lanes of the last workgroup sum a strided share of the partials (fixed order)
-    double t = 0.0;
-    for (unsigned k = threadIdx.x; k < gridDim.x; k += blockDim.x)
-        t += __hip_atomic_load(&red->partial[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x < 64) t += __hip_atomic_load(&slots[threadIdx.x * 8], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    double v[1] = {t};
-    v[0] = wave_sum(v[0]);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v[0];
     __syncthreads();
     if (threadIdx.x == 0) {
         double tot = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) tot += ws[w];
+        for (int w = 0; w < kFinThreads / 64; ++w) tot += ws[w];
         out[0] = sqrt(tot);
-        red->counter = 0u;
     }
 }
 
@@ -781,8 +836,6 @@ ElemArgs make_args(vms_ctx* c, const double* u, const double* u_prev, const doub
     return a;
 }
 
-double* slots_of(vms_ctx* c) { return c->red->acc_slots; }
-
 TileArgs tile_args(vms_ctx* c) {
     TileArgs t;
     t.node0 = c->tile_node0;
@@ -790,7 +843,7 @@ TileArgs tile_args(vms_ctx* c) {
     t.ea = c->item_ea;
     t.pos = c->item_pos;
     t.rowptr = c->rowptr;
-    t.diagpos = c->diagpos;
+    t.bmask = c->bmask;
     return t;
 }
 
@@ -893,8 +946,6 @@ __global__ void full_update_kernel(int n_nodes, int n_elems, const double* __res
 
 int launch_full_assemble(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
                          double inv_dt, const double* body, void* vals, double* rhs, hipStream_t s) {
-    int rc;
-    if ((rc = launch_fill(slots_of(c), 64 * 8 * sizeof(double), s))) return rc;
     flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
     ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
     const int64_t nb16 = c->nb * 16;
@@ -902,14 +953,14 @@ int launch_full_assemble(vms_ctx* c, const double* u, const double* u_prev, cons
     const int gcopy = (int)((std::max<int64_t>(nb16, n4) + kBlock - 1) / kBlock);
     if (c->prec == VMS_FP64) {
         tile_kernel<double, double, true, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(
-            a, tile_args(c), (double*)c->A, c->rhs, c->rglob, slots_of(c));
+            a, tile_args(c), (double*)c->A, c->rhs, nullptr, c->tile_part);
         full_element_kernel<double><<<grid_for(c->n_elems), kBlock, 0, s>>>(a, c->n_nodes, c->full_epos,
                                                                             (double*)vals, rhs);
         full_copy_kernel<double><<<gcopy, kBlock, 0, s>>>(c->nb, n4, c->full_cc, (const double*)c->A,
                                                           (double*)vals, c->rhs, rhs);
     } else {
         tile_kernel<float, MixedAcc, true, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(
-            a, tile_args(c), (float*)c->A, c->rhs, c->rglob, slots_of(c));
+            a, tile_args(c), (float*)c->A, c->rhs, nullptr, c->tile_part);
         full_element_kernel<float><<<grid_for(c->n_elems), kBlock, 0, s>>>(a, c->n_nodes, c->full_epos,
                                                                           (float*)vals, rhs);
         full_copy_kernel<float><<<gcopy, kBlock, 0, s>>>(c->nb, n4, c->full_cc, (const float*)c->A, (float*)vals,
@@ -925,52 +976,46 @@ int launch_full_update(vms_ctx* c, const double* dx, double* u, double* beta, hi
 }
 
 int launch_condense(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
-                    double inv_dt, const double* body, void* A, double* rhs, double* rglob,
-                    double* /*red_acc*/, hipStream_t s) {
+                    double inv_dt, const double* body, void* A, double* rhs, double* rglob, hipStream_t s) {
     const size_t es = elt_size(c);
     const double nn = c->n_nodes, ne = c->n_elems;
-    int rc;
     {
-        PhaseScope ph(c, VMS_PH_FILL, 64.0 * 8, s);
-        if ((rc = launch_fill(slots_of(c), 64 * 8 * sizeof(double), s))) return rc;
+        PhaseScope ph(c, VMS_PH_FILL, 0.0, s);
         flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
     }
     ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
     // algorithmic bytes: connectivity + beta per element; coordinates, state (and previous
-    // velocity, body force) per node; block-CSR values, rhs and residual written once
+    // velocity, body force) per node; block-CSR values and rhs written once (and the residual
+    // rows, when asked for)
     const double alg = ne * (16.0 + 24.0) + nn * (24.0 + 32.0 + (a.u_prev ? 24.0 : 0.0) + (body ? 24.0 : 0.0)) +
-                       (double)c->nb * 16 * es + 2 * 32.0 * nn;
+                       (double)c->nb * 16 * es + 32.0 * nn * (rglob ? 2.0 : 1.0);
     PhaseScope ph(c, VMS_PH_CONDENSE, alg, s);
     if (c->prec == VMS_FP64)
-        tile_kernel<double, double, true><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (double*)A, rhs, rglob,
-                                                                         slots_of(c));
+        tile_kernel<double, double, true><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (double*)A,
+                                                                                       rhs, rglob, c->tile_part);
     else
-        tile_kernel<float, MixedAcc, true><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (float*)A, rhs, rglob,
-                                                                        slots_of(c));
+        tile_kernel<float, MixedAcc, true><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (float*)A,
+                                                                                        rhs, rglob, c->tile_part);
     return check_hip(c, hipGetLastError(), "condense launch");
 }
 
 int launch_residual(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
-                    double inv_dt, const double* body, double* rglob, double* /*red_acc*/, hipStream_t s) {
-    int rc;
-    if ((rc = launch_fill(slots_of(c), 64 * 8 * sizeof(double), s))) return rc;
+                    double inv_dt, const double* body, double* rglob, hipStream_t s) {
     flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
     ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
     {
         const double nn = c->n_nodes, ne = c->n_elems;
         PhaseScope ph(c, VMS_PH_RESIDUAL,
-                      ne * 40.0 + nn * (56.0 + (a.u_prev ? 24.0 : 0.0) + (body ? 24.0 : 0.0)) + 32.0 * nn, s);
-        tile_kernel<double, double, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (double*)nullptr,
-                                                                          nullptr, rglob, slots_of(c));
+                      ne * 40.0 + nn * (56.0 + (a.u_prev ? 24.0 : 0.0) + (body ? 24.0 : 0.0)) +
+                          (rglob ? 32.0 * nn : 0.0), s);
+        tile_kernel<double, double, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(
+            a, tile_args(c), (double*)nullptr, nullptr, rglob, c->tile_part);
     }
     return check_hip(c, hipGetLastError(), "residual launch");
 }
 
-int launch_norm_finalize(vms_ctx* c, const double* rglob, const double* /*red_acc*/, double* out,
-                         hipStream_t s) {
-    const int n = 4 * c->n_nodes;
-    const int g = std::min(kRedBlocks, grid_for(n));
-    norm_finalize_kernel<<<g, kBlock, 0, s>>>(n, rglob, slots_of(c), c->red, out);
+int launch_norm_finalize(vms_ctx* c, double* out, hipStream_t s) {
+    norm_finalize_kernel<<<1, kFinThreads, 0, s>>>(c->n_tiles, c->tile_part, out);
     return check_hip(c, hipGetLastError(), "norm launch");
 }
 
@@ -1020,9 +1065,9 @@ extern "C" int vms_condense_assemble(vms_ctx* c, const double* u, const double* 
     if (rc) return rc;
     if (!bsr_vals || !rhs) return set_error(c, VMS_EINVAL, "vms_condense_assemble: NULL output");
     rc = launch_condense(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body,
-                         bsr_vals, rhs, c->rglob, nullptr, s);
+                         bsr_vals, rhs, nullptr, s);
     if (rc) return rc;
-    if (rnorm) return launch_norm_finalize(c, c->rglob, nullptr, rnorm, s);
+    if (rnorm) return launch_norm_finalize(c, rnorm, s);
     return VMS_OK;
 }
 
@@ -1036,7 +1081,7 @@ extern "C" int vms_full_assemble(vms_ctx* c, const double* u, const double* u_pr
     rc = launch_full_assemble(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body,
                               bsr_vals, rhs, s);
     if (rc) return rc;
-    if (rnorm) return launch_norm_finalize(c, c->rglob, nullptr, rnorm, s);
+    if (rnorm) return launch_norm_finalize(c, rnorm, s);
     return VMS_OK;
 }
 
@@ -1044,11 +1089,9 @@ extern "C" int vms_residual(vms_ctx* c, const double* u, const double* u_prev, c
                             double dt, const double* body, double* rglob, double* rnorm, hipStream_t s) {
     int rc = check_state_args(c, u, beta, Re, dt, u_prev, "vms_residual");
     if (rc) return rc;
-    double* rg = rglob ? rglob : c->rglob;
-    rc = launch_residual(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body, rg,
-                         nullptr, s);
+    rc = launch_residual(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body, rglob, s);
     if (rc) return rc;
-    if (rnorm) return launch_norm_finalize(c, rg, nullptr, rnorm, s);
+    if (rnorm) return launch_norm_finalize(c, rnorm, s);
     return VMS_OK;
 }
 

@@ -690,7 +690,7 @@ struct GivensCtx {
 // chain (inside a launch that streams vectors, every such access would queue behind the
 // stream); the LDS operands are fetched four at a time.
 __device__ int givens_column(int jc, const double* col, double* cl, double* sl, double gj, double* Rl,
-                             const GivensCtx& gc, GmresState* gs) {
+                             const GivensCtx& gc, GmresState* gs, int done_val) {
     double x = col[0];
     int i = 0;
     for (; i + 4 <= jc; i += 4) {
@@ -728,7 +728,7 @@ __device__ int givens_column(int jc, const double* col, double* cl, double* sl, 
     gs->gin[jc + 1] = gnext;
     gs->k = jc + 1;
     const int stop = (conv || breakdown) ? 1 : 0;
-    if (stop) gs->done = 1;
+    if (stop) gs->done = done_val;
     report_progress(gc.progress, gc.gen, jc + 1, stop);
     return stop;
 }
@@ -850,6 +850,9 @@ __device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
     const bool last = in == nullptr;                    // the tail: column j-1 only
     const bool hs_on = !last && j > 1;                  // columns 0 .. j-2 take part in H s
     const int done = in ? 0 : gs->done;                 // the fused update has tested it
+    // a stop found by the update launch of step j is stored as j + 2, which that launch's other
+    // workgroups read as "not yet stopped": they still write q_j, which the closing column needs
+    const int done_val = in ? j + 2 : 1;
     const int reorth = in ? in->reorth : gs->reorth;
     const double rho = in ? in->rho : gs->rho, hh = in ? in->hh : gs->hh, cj = in ? in->cj : gs->cj;
     const double gprev = j > 0 ? gs->gin[j - 1] : 0.0;
@@ -916,10 +919,10 @@ __device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
     if (tid == 0) {
         int st = 0;
         if (j > 0) {
-            st = givens_column(j - 1, Hc, cl, sl, gprev, Rl[0], gc, gs);
+            st = givens_column(j - 1, Hc, cl, sl, gprev, Rl[0], gc, gs, done_val);
             if (!(rho > 0.0)) {
                 st = 1;                      // u_j vanished: column j-1 closes the cycle
-                gs->done = 1;
+                gs->done = done_val;
                 report_progress(gc.progress, gc.gen, j, 1);
             }
         }
@@ -944,8 +947,8 @@ __device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
     // the Krylov space is invariant: column j is final with a zero subdiagonal
     if (tid == 0) {
         colj[j + 1] = 0.0;
-        givens_column(j, colj, cl, sl, gs->gin[j], Rl[1], gc, gs);
-        gs->done = 1;
+        givens_column(j, colj, cl, sl, gs->gin[j], Rl[1], gc, gs, done_val);
+        gs->done = done_val;
         report_progress(gc.progress, gc.gen, j + 1, 1);
     }
     __syncthreads();
@@ -1024,7 +1027,10 @@ __device__ __forceinline__ bool step_scalars(int j, int nchunks, const double* _
         if (sub == 0 && slot < ns) L.sums[slot] = a;
     }
     __syncthreads();
-    if (L.flags[0]) return false;
+    // stopped by an earlier launch (cycle start: 1; the update of step j' < j: j' + 2); a stop
+    // that workgroup 0 of this launch publishes (j + 2) does not count, since q_j is still due
+    const int dw = L.flags[0];
+    if (dw != 0 && dw <= j + 1) return false;
     // every wave forms the scalars itself (the wave sums leave them in every lane), so that no
     // second barrier is needed; all lanes and workgroups do the same operations in the same order
     const int reorth = L.flags[1];
@@ -1265,6 +1271,10 @@ __global__ __launch_bounds__(kBlock) void norm_kernel(int n, const T* __restrict
         red->counter = 0u;
         __hip_atomic_store(tag_out, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
+}
+
+__global__ void zero_count_kernel(int32_t* p) {
+    if (threadIdx.x == 0) *p = 0;
 }
 
 template <typename TS, typename TD>
@@ -1517,6 +1527,7 @@ int launch_spmv(vms_ctx* c, const void* A, const void* x, void* y, hipStream_t s
 }
 
 int launch_bj_setup(vms_ctx* c, const void* A, void* Minv, hipStream_t s) {
+    zero_count_kernel<<<1, 64, 0, s>>>(c->flags + 2);      // singular blocks of this setup
     PhaseScope ph(c, VMS_PH_PCSETUP, (double)c->n_nodes * (32.0 * elt_size(c) + 4.0), s);
     if (c->prec == VMS_FP64)
         bj_setup_kernel<double, double><<<grid_for(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, c->diagpos,
@@ -1638,11 +1649,21 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     double bn = 0.0;
     if ((rc = read_scalar(c, 1, &bn, s))) return rc;
     if (!std::isfinite(bn)) return set_error(c, VMS_ENONFINITE, "gmres: non-finite right-hand side");
+    // singular diagonal blocks of the preconditioner setup (applied as the identity), read
+    // once the stream is drained at the end of the call
+    int32_t singular = 0;
+    auto read_singular = [&]() {
+        return check_hip(c, hipMemcpyAsync(&singular, c->flags + 2, sizeof singular, hipMemcpyDeviceToHost, s),
+                         "read singular-block count");
+    };
     if (bn == 0.0) {
         if ((rc = launch_fill(x, n * sizeof(double), s))) return rc;
+        if ((rc = read_singular())) return rc;
+        if ((rc = check_hip(c, hipStreamSynchronize(s), "sync"))) return rc;
         inf.true_rel_res = 0.0;
+        inf.singular_blocks = singular;
         if (info) *info = inf;
-        return check_hip(c, hipStreamSynchronize(s), "sync");
+        return VMS_OK;
     }
     const double tol = rtol * bn;
     double rn = 0.0;
@@ -1687,9 +1708,12 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             using_learned = false;
             inf.fell_back_to_bj = 1;
         }
+        // while the learned blocks are on trial, no cycle runs past half of the budget, so that
+        // the switch to block-Jacobi above happens there
+        const int cap = using_learned ? learned_budget : max_iters;
         if (c->prec == VMS_FP64) {
             // one restart cycle on the FP64 residual; the true residual is recomputed above
-            if ((rc = run_cycle<double, double>(c, c->r64, (const double*)c->Minv, x, tol, m, max_iters - iters,
+            if ((rc = run_cycle<double, double>(c, c->r64, (const double*)c->Minv, x, tol, m, cap - iters,
                                                 o->cgs2, s)))
                 return rc;
             pending = true;
@@ -1709,9 +1733,9 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             const double inner_tol = std::max(inner_rtol, 0.9 * tol / rn);
             const float* cycle_r = rr;
             int progress = 0;
-            while (iters < max_iters) {
+            while (iters < cap) {
                 if ((rc = run_cycle<float, float>(c, cycle_r, (const float*)c->Minv, d, inner_tol, m,
-                                                  max_iters - iters, o->cgs2, s)))
+                                                  cap - iters, o->cgs2, s)))
                     return rc;
                 spmv_kernel<float, float, float, float, 1, float><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
                     c->n_nodes, c->rowptr, c->colidx, (const float*)A, d, rr, q, nullptr, nullptr);
@@ -1744,7 +1768,9 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
         }
     }
     // the per-cycle reads above wait only for their norms; the call returns with the stream drained
+    if (int rs = read_singular()) return rs;
     if (int rs = check_hip(c, hipStreamSynchronize(s), "sync")) return rs;
+    inf.singular_blocks = singular;
     inf.iters = iters;
     inf.true_rel_res = rn / bn;
     if (info) *info = inf;

@@ -426,7 +426,7 @@ extern "C" int vms_pc_train_step(vms_ctx* c, const void* bsr_vals, const float* 
     float* t = c->tvec;                // P r
     float* e = c->tvec + N;            // r - A P r
     float* g = c->tvec + 2 * (size_t)N;  // A^T e
-    float* gdelta = (float*)c->V;      // [n][16]: the Krylov basis is idle during training
+    float* gdelta = c->gdel;           // [n][16]
     double* sums = c->rnorm + 4;       // the two FP64 sums of the loss
     float* loss = c->fscal;
     int rc = features(c, bsr_vals, c->feats, dinv, s);

@@ -19,9 +19,9 @@ extern "C" int vms_newton_step(vms_ctx* c, double* u, double* beta, const double
     const double* up = dt > 0.0 ? u_prev : nullptr;
     const int n = 4 * c->n_nodes;
 
-    int rc = launch_condense(c, u, up, beta, nu, inv_dt, body, c->A, c->rhs, c->rglob, nullptr, s);
+    int rc = launch_condense(c, u, up, beta, nu, inv_dt, body, c->A, c->rhs, nullptr, s);
     if (rc) return rc;
-    if ((rc = launch_norm_finalize(c, c->rglob, nullptr, c->rnorm, s))) return rc;
+    if ((rc = launch_norm_finalize(c, c->rnorm, s))) return rc;
     if ((rc = check_element_flags(c, s))) {
         if (info) *info = inf;
         return rc;
@@ -42,8 +42,8 @@ extern "C" int vms_newton_step(vms_ctx* c, double* u, double* beta, const double
         return lin;
     }
     if ((rc = vms_recover_update(c, u, beta, u_prev, Re, dt, body, c->du, s))) return rc;
-    if ((rc = launch_residual(c, u, up, beta, nu, inv_dt, body, c->rglob, nullptr, s))) return rc;
-    if ((rc = launch_norm_finalize(c, c->rglob, nullptr, c->rnorm + 1, s))) return rc;
+    if ((rc = launch_residual(c, u, up, beta, nu, inv_dt, body, nullptr, s))) return rc;
+    if ((rc = launch_norm_finalize(c, c->rnorm + 1, s))) return rc;
     if ((rc = check_hip(c, hipMemcpyAsync(&inf.rnorm_after, c->rnorm + 1, sizeof(double), hipMemcpyDeviceToHost, s),
                         "read rnorm")))
         return rc;
@@ -78,7 +78,7 @@ extern "C" int vms_full_newton_step(vms_ctx* c, double* u, double* beta, const d
 
     int rc = launch_full_assemble(c, u, up, beta, nu, inv_dt, body, f->A, f->rhs, s);
     if (rc) return rc;
-    if ((rc = launch_norm_finalize(c, c->rglob, nullptr, c->rnorm, s))) return rc;
+    if ((rc = launch_norm_finalize(c, c->rnorm, s))) return rc;
     if ((rc = check_element_flags(c, s))) {
         if (info) *info = inf;
         return rc;
@@ -104,8 +104,8 @@ extern "C" int vms_full_newton_step(vms_ctx* c, double* u, double* beta, const d
         return lrc;
     }
     if ((rc = launch_full_update(c, f->du, u, beta, s))) return rc;
-    if ((rc = launch_residual(c, u, up, beta, nu, inv_dt, body, c->rglob, nullptr, s))) return rc;
-    if ((rc = launch_norm_finalize(c, c->rglob, nullptr, c->rnorm + 1, s))) return rc;
+    if ((rc = launch_residual(c, u, up, beta, nu, inv_dt, body, nullptr, s))) return rc;
+    if ((rc = launch_norm_finalize(c, c->rnorm + 1, s))) return rc;
     if ((rc = check_hip(c, hipMemcpyAsync(&inf.rnorm_after, c->rnorm + 1, sizeof(double), hipMemcpyDeviceToHost, s),
                         "read rnorm")))
         return rc;

@@ -22,7 +22,7 @@ constexpr int kMaxRestart = 128;
 #endif
 constexpr int kTileNodes = 64;           // max nodes owned by one assembly tile
 #ifndef VMS_TILE_BLOCKS_FP64
-#define VMS_TILE_BLOCKS_FP64 420
+#define VMS_TILE_BLOCKS_FP64 300
 #endif
 #ifndef VMS_TILE_BLOCKS_FP32
 #define VMS_TILE_BLOCKS_FP32 870
@@ -72,7 +72,10 @@ struct GmresState {
     double hh;                     // provisional subdiagonal of column j (norm estimate of u_{j+1})
     int reorth;                    // 0: one Gram-Schmidt pass; otherwise a delayed second pass
     int k;                         // Arnoldi steps completed in this cycle
-    int done;                      // 1: converged or breakdown, later kernels idle
+    int done;                      // 0 while the cycle runs; nonzero once it stopped (converged or
+                                   // breakdown), later kernels idle: 1 when the cycle start or the
+                                   // tail stopped it, j + 2 when the update launch of step j did
+                                   // (its other workgroups still finish step j)
     unsigned counter;              // arrival counter of last-block reductions
     unsigned gen;                  // cycle number (host-assigned) reported with the progress word
     uint64_t* progress;            // host-mapped progress word: gen << 32 | k << 1 | done
@@ -81,7 +84,6 @@ struct GmresState {
 // Grid-wide reduction scratch.
 struct RedScratch {
     double partial[kRedBlocks * (kMaxRestart + 1)];
-    double acc_slots[64 * 8];      // atomically accumulated scalars, one per 64-byte line
     unsigned counter;
 };
 
@@ -110,19 +112,21 @@ struct vms_ctx {
     int32_t* tpos = nullptr;         // [nb] position of the transposed block
     // assembly tiles: tile t owns block rows [tile_node0[t], tile_node0[t+1]) and works
     // through work items (element e, owned vertex a): item_ea = 4 e + a, item_pos = the four
-    // tile-local block slots of row a (16 bits each)
+    // tile-local block slots of row a (16 bits each) in the item's vertex order a, a^1, a^2, a^3
     int32_t n_tiles = 0;
     int32_t* tile_node0 = nullptr;   // [n_tiles + 1]
     int32_t* tile_iptr = nullptr;    // [n_tiles + 1]
     int32_t* item_ea = nullptr;      // [4 n_elems]
     uint2* item_pos = nullptr;       // [4 n_elems]
+    uint16_t* bmask = nullptr;       // [nb] Dirichlet bits of the column node (0..3) and the row
+                                     // node (4..7), bit 8 on diagonal blocks
+    double* tile_part = nullptr;     // [n_tiles][2] partial sums of the residual norm
     size_t tile_lds = 0;             // dynamic LDS bytes of the largest tile
 
     // Newton workspaces (device)
     void* A = nullptr;               // [nb][16] of the ctx precision
     double* rhs = nullptr;           // [4 n_nodes]
     double* du = nullptr;            // [4 n_nodes]
-    double* rglob = nullptr;         // [4 n_nodes]
     double* rnorm = nullptr;         // [4] device scalars
     int32_t* flags = nullptr;        // [4] device error flags (bad element, singular K_ff)
 
@@ -172,7 +176,8 @@ struct vms_ctx {
     float* feats = nullptr;          // [n_nodes][25]
     float* hid = nullptr;            // [n_nodes][64]
     float* pblk = nullptr;           // [n_nodes][16]
-    float* gblk = nullptr;           // [n_nodes][16] dL/dDelta
+    float* gblk = nullptr;           // [n_nodes][16] D^-1 blocks (features, training)
+    float* gdel = nullptr;           // [n_nodes][16] dL/dDelta (training)
     float* tvec = nullptr;           // [3][4 n_nodes] training vectors
     float* wgrad = nullptr;          // [kRedBlocks][VMS_PC_NWEIGHTS] partial weight gradients
     float* fscal = nullptr;          // [8] float scalars
@@ -223,14 +228,14 @@ struct PhaseScope {
 
 // element kernels (element.hip)
 hipError_t tile_kernels_configure(vms_ctx* ctx);
+// rglob (may be null) receives the assembled residual rows; every launch leaves the norm's
+// partial sums per tile in ctx->tile_part, which launch_norm_finalize adds into out.
 int launch_condense(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta,
                     double nu, double inv_dt, const double* body, void* A, double* rhs,
-                    double* rglob, double* red_acc, hipStream_t s);
+                    double* rglob, hipStream_t s);
 int launch_residual(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta,
-                    double nu, double inv_dt, const double* body, double* rglob, double* red_acc,
-                    hipStream_t s);
-int launch_norm_finalize(vms_ctx* ctx, const double* rglob, const double* red_acc, double* out,
-                         hipStream_t s);
+                    double nu, double inv_dt, const double* body, double* rglob, hipStream_t s);
+int launch_norm_finalize(vms_ctx* ctx, double* out, hipStream_t s);
 int check_element_flags(vms_ctx* ctx, hipStream_t s);
 // Uncondensed system (ctx->full must exist): assembly into vals / rhs of the full pattern, and
 // the Newton update from its solution dx.
