@@ -479,75 +479,79 @@ def jet_study(B, driver, build_workload, dev, steps):
     print(json.dumps(report), flush=True)
 
 
-def bfs_study(B, driver, learned, build_workload, dev, steps, restart=128):
+def bfs_study(B, driver, learned, build_workload, dev, steps, restart=50, forms=("fp64_bj", "mixed_bj", "mixed_learned")):
     """Learned correction on the backward-facing step.  Training data: the Newton systems of the
     steady bfs8 continuation Re 400 -> 800 and of the first backward-Euler steps of bfs8 at
     Re 800, dt 0.05 from an impulsive start (mixed, GMRES(50) + block-Jacobi, restart residuals
     logged); the last transient system is held out for checkpoint selection.  Evaluation: the
-    transient bfs16 run (Re 800, dt 0.05, impulsive start) for `steps` steps, once with
-    block-Jacobi and once with the learned correction, Newton to 1e-8 per step, GMRES(restart);
-    GMRES iterations and wall time per step."""
+    transient bfs16 run (Re 800, dt 0.05, impulsive start) for `steps` steps in each form --
+    FP64 + block-Jacobi, mixed + block-Jacobi, mixed + learned correction -- Newton to 1e-8 per
+    step, GMRES(restart); Newton steps, GMRES iterations and wall time per step."""
     import numpy as np
     import torch
-    report = {"study": "bfs"}
-    t0 = time.perf_counter()
-    cfg8, m8, u8, b8, bc8 = build_workload("bfs8")
-    ctx8 = B.Context(torch.from_numpy(m8.xyz).to(dev), torch.from_numpy(m8.tets).to(dev),
-                     torch.from_numpy(bc8.dofs).to(dev), precision=B.VMS_MIXED, max_restart=restart)
-    lin8 = B.solve_opts(restart=50, rtol=1e-4, max_iters=20000)
-    u = torch.from_numpy(u8).to(dev)
-    beta = torch.from_numpy(b8).to(dev)
-    data, cont = [], []
-    for re in cfg8.re_sweep:
-        tr = time.perf_counter()
-        d, hist = learned.collect_newton_data(ctx8, u, beta, re, tol=cfg8.newton_tol, max_newton=12, lin=lin8,
-                                              per_step=32, allow_noconv=True)
-        converged = hist[-1] <= cfg8.newton_tol * hist[0]
-        cont.append({"re": re, "newton_steps": len(d), "converged": bool(converged),
-                     "seconds": round(time.perf_counter() - tr, 2),
-                     "rnorms": [float(f"{r:.3e}") for r in hist]})
-        log(f"bfs8 steady Re {re:g}: {cont[-1]}")
-        data += d
-        if not converged:
-            break
-    # transient bfs8 systems, impulsive start
-    u = torch.from_numpy(u8).to(dev)
-    beta = torch.from_numpy(b8).to(dev)
-    u_prev = torch.empty_like(u)
-    trans = []
-    for n in range(2):
-        tr = time.perf_counter()
-        u_prev.copy_(u)
-        d, hist = learned.collect_newton_data(ctx8, u, beta, 800.0, 0.05, u_prev, tol=1e-8, max_newton=8,
-                                              lin=lin8, per_step=32, allow_noconv=True)
-        trans += d
-        log(f"bfs8 transient step {n}: Newton {len(d)}, {time.perf_counter() - tr:.1f} s")
-    report["bfs8"] = {"n_elems": m8.n_elems, "n_nodes": m8.n_nodes, "continuation": cont,
-                      "transient_systems": len(trans), "training_systems": len(data) + len(trans) - 1,
-                      "seconds": time.perf_counter() - t0}
-    t1 = time.perf_counter()
-    train_set = data + trans[:-1]
-    val = [(A, S[0].contiguous()) for A, S in trans[-1:]]
-    weights, train = learned.train_validated(ctx8, train_set, val, steps=300, lr=3e-4, check_every=25,
-                                             val_restart=min(restart, 128), val_max_iters=60000)
-    train["seconds"] = time.perf_counter() - t1
-    report["training"] = train
-    log(f"training: {train}")
-    del data, trans, train_set, val
-    ctx8.close()
-    torch.cuda.empty_cache()
+    report = {"study": "bfs", "forms": list(forms)}
+    weights = None
+    if "mixed_learned" in forms:
+        t0 = time.perf_counter()
+        cfg8, m8, u8, b8, bc8 = build_workload("bfs8")
+        ctx8 = B.Context(torch.from_numpy(m8.xyz).to(dev), torch.from_numpy(m8.tets).to(dev),
+                         torch.from_numpy(bc8.dofs).to(dev), precision=B.VMS_MIXED, max_restart=max(50, restart))
+        lin8 = B.solve_opts(restart=50, rtol=1e-4, max_iters=20000)
+        u = torch.from_numpy(u8).to(dev)
+        beta = torch.from_numpy(b8).to(dev)
+        data, cont = [], []
+        for re in cfg8.re_sweep:
+            tr = time.perf_counter()
+            d, hist = learned.collect_newton_data(ctx8, u, beta, re, tol=cfg8.newton_tol, max_newton=12, lin=lin8,
+                                                  per_step=32, allow_noconv=True)
+            converged = hist[-1] <= cfg8.newton_tol * hist[0]
+            cont.append({"re": re, "newton_steps": len(d), "converged": bool(converged),
+                         "seconds": round(time.perf_counter() - tr, 2),
+                         "rnorms": [float(f"{r:.3e}") for r in hist]})
+            log(f"bfs8 steady Re {re:g}: {cont[-1]}")
+            data += d
+            if not converged:
+                break
+        # transient bfs8 systems, impulsive start
+        u = torch.from_numpy(u8).to(dev)
+        beta = torch.from_numpy(b8).to(dev)
+        u_prev = torch.empty_like(u)
+        trans = []
+        for n in range(2):
+            tr = time.perf_counter()
+            u_prev.copy_(u)
+            d, hist = learned.collect_newton_data(ctx8, u, beta, 800.0, 0.05, u_prev, tol=1e-8, max_newton=8,
+                                                  lin=lin8, per_step=32, allow_noconv=True)
+            trans += d
+            log(f"bfs8 transient step {n}: Newton {len(d)}, {time.perf_counter() - tr:.1f} s")
+        report["bfs8"] = {"n_elems": m8.n_elems, "n_nodes": m8.n_nodes, "continuation": cont,
+                          "transient_systems": len(trans), "training_systems": len(data) + len(trans) - 1,
+                          "seconds": time.perf_counter() - t0}
+        t1 = time.perf_counter()
+        train_set = data + trans[:-1]
+        val = [(A, S[0].contiguous()) for A, S in trans[-1:]]
+        weights, train = learned.train_validated(ctx8, train_set, val, steps=300, lr=3e-4, check_every=25,
+                                                 val_restart=restart, val_max_iters=60000)
+        train["seconds"] = time.perf_counter() - t1
+        report["training"] = train
+        log(f"training: {train}")
+        del data, trans, train_set, val
+        ctx8.close()
+        torch.cuda.empty_cache()
 
     cfg, m, u0, beta0, bc = build_workload("bfs16")
-    ctx = B.Context(torch.from_numpy(m.xyz).to(dev), torch.from_numpy(m.tets).to(dev),
-                    torch.from_numpy(bc.dofs).to(dev), precision=B.VMS_MIXED, max_restart=restart)
     dofs = torch.from_numpy(bc.dofs.astype(np.int64)).to(dev)
     vals = torch.from_numpy(bc.values).to(dev)
     report["bfs16"] = {"n_elems": m.n_elems, "n_nodes": m.n_nodes, "re": cfg.re, "dt": cfg.dt, "steps": steps,
                        "restart": restart}
-    for name, w in (("block_jacobi", None), ("learned", weights)):
-        if name == "learned" and w is None:
+    for name in forms:
+        prec = B.VMS_FP64 if name.startswith("fp64") else B.VMS_MIXED
+        w = weights if name == "mixed_learned" else None
+        if name == "mixed_learned" and w is None:
             report["bfs16"][name] = "validation selected plain block-Jacobi"
             continue
+        ctx = B.Context(torch.from_numpy(m.xyz).to(dev), torch.from_numpy(m.tets).to(dev),
+                        torch.from_numpy(bc.dofs).to(dev), precision=prec, max_restart=max(50, restart))
         u = torch.from_numpy(u0).to(dev)
         beta = torch.from_numpy(beta0).to(dev)
         u_prev = torch.empty_like(u)
@@ -561,7 +565,8 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=128):
                                     forcing="ew")
             per_step.append({"seconds": r.seconds, "newton": len(r.rnorms) - 1,
                              "gmres": int(sum(d["iters"] for d in r.lin)),
-                             "fell_back": int(sum(d["fell_back_to_bj"] for d in r.lin))})
+                             "fell_back": int(sum(d["fell_back_to_bj"] for d in r.lin)),
+                             "rel_residual": r.rnorms[-1] / r.rnorms[0]})
             log(f"bfs16 {name} step {n}: {per_step[-1]}")
         secs = [p["seconds"] for p in per_step]
         report["bfs16"][name] = {
@@ -570,8 +575,10 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=128):
             "seconds": float(sum(secs)), "seconds_per_step_mean": float(np.mean(secs)),
             "seconds_per_step_max": float(np.max(secs)),
             "fell_back_to_bj": int(sum(p["fell_back"] for p in per_step)),
-            "gmres_per_step": [p["gmres"] for p in per_step]}
-        log(f"bfs16 {name}: " + json.dumps({k: v for k, v in report["bfs16"][name].items() if k != "gmres_per_step"}))
+            "per_step": per_step}
+        log(f"bfs16 {name}: " + json.dumps({k: v for k, v in report["bfs16"][name].items() if k != "per_step"}))
+        ctx.close()
+        torch.cuda.empty_cache()
     print(json.dumps(report), flush=True)
 
 
@@ -599,13 +606,16 @@ def measured_traffic(workload, phase):
 
 
 def counter_run(B, cfg, mesh, u0, beta0, bc, dev):
-    """The workload's mixed-precision tangent, GMRES(50) + block-Jacobi capped at COUNTER_ITERS
-    Arnoldi steps (as many launches of the Arnoldi SpMV), then one device-to-device copy of
-    COPY_MIB MiB.  Meant to run under rocprofv3 --pmc."""
+    """One condensed assembly of the workload (mixed precision; transient workloads take their
+    first backward-Euler step from the initial state), GMRES(50) + block-Jacobi on it capped at
+    COUNTER_ITERS Arnoldi steps (as many launches of the Arnoldi SpMV), then one device-to-device
+    copy of COPY_MIB MiB.  Meant to run under rocprofv3 --pmc."""
     import torch
     ctx = B.Context(torch.from_numpy(mesh.xyz).to(dev), torch.from_numpy(mesh.tets).to(dev),
                     torch.from_numpy(bc.dofs).to(dev), precision=B.VMS_MIXED)
-    A, rhs, _ = B.vms_condense_assemble(ctx, torch.from_numpy(u0).to(dev), torch.from_numpy(beta0).to(dev), cfg.re)
+    u = torch.from_numpy(u0).to(dev)
+    dt = cfg.dt if cfg.dt > 0 else 0.0
+    A, rhs, _ = B.vms_condense_assemble(ctx, u, torch.from_numpy(beta0).to(dev), cfg.re, dt, u if dt > 0 else None)
     x = ctx.new_vec()
     _, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=50, rtol=1e-14, max_iters=COUNTER_ITERS),
                                 allow_noconv=True)

@@ -124,7 +124,7 @@ static void free_all(vms_ctx* c) {
         c->full = nullptr;
     }
     void* ptrs[] = {c->full_cc, c->full_epos, c->zfull, c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
-                    c->tpos, c->tile_node0, c->tile_iptr, c->item_ea, c->item_pos, c->bmask, c->tile_part, c->A, c->rhs, c->du, c->rnorm, c->flags,
+                    c->tpos, c->tile_node0, c->tile_iptr, c->tile_nptr, c->tile_nodes, c->items, c->bmask, c->tile_part, c->A, c->rhs, c->du, c->rnorm, c->flags,
                     c->V, c->w, c->z, c->d, c->r, c->Minv, c->AP, c->Az, c->x64, c->r64, c->gs, c->red,
                     c->feats, c->hid, c->pblk, c->gblk, c->gdel, c->tvec, c->wgrad, c->fscal};
     for (void* p : ptrs)
@@ -407,16 +407,20 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
         for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) tpos[k] = find(colidx[k], (int32_t)i);
     }
 
-    // Assembly tiles: contiguous node ranges whose block rows fit the LDS budget.
+    // Assembly tiles: contiguous node ranges whose block rows fit the LDS budget and whose
+    // elements touch at most kTileMaxNodes distinct nodes (their coordinates and state are staged
+    // in LDS).  Local node numbering per tile: the owned nodes first, in order, then the other
+    // vertices of the tile's elements in increasing global order.
     const size_t acc_size = c->prec == VMS_FP64 ? sizeof(double) : kMixedAccSize;
     const int64_t max_blocks = acc_size == sizeof(double) ? kTileBlocksFP64 : kTileBlocksFP32;
-    std::vector<int32_t> tnode0{0}, tiptr{0}, iea;
-    std::vector<uint2> ipos;
-    iea.reserve(4 * ne);
-    ipos.reserve(4 * ne);
-    size_t lds_max = 0;
+    std::vector<int32_t> tnode0{0}, tiptr{0}, tnptr{0}, tnodes;
+    std::vector<uint4> items;
+    items.reserve(4 * ne);
+    size_t lds_max = 0, lds_max_tr = 0;
     {
+        std::vector<int32_t> stamp(nn, -1), loc(nn, 0), cand, halo;
         int64_t r0 = 0;
+        int32_t tile = 0;
         std::vector<std::pair<int32_t, int32_t>> list;   // (element, local vertex)
         while (r0 < nn) {
             if (rowptr[r0 + 1] - rowptr[r0] > max_blocks) {
@@ -425,8 +429,44 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
                 return set_error(nullptr, VMS_EINVAL, "vms_create: node " + std::to_string(r0) +
                                                           " has more block neighbours than an assembly tile holds");
             }
-            int64_t r1 = r0 + 1;
-            while (r1 < nn && r1 - r0 < kTileNodes && rowptr[r1 + 1] - rowptr[r0] <= max_blocks) ++r1;
+            int64_t r1 = r0;
+            int32_t ndist = 0;
+            while (r1 < nn && r1 - r0 < kTileNodes && rowptr[r1 + 1] - rowptr[r0] <= max_blocks) {
+                cand.clear();
+                if (stamp[r1] != tile) cand.push_back((int32_t)r1);
+                for (int32_t k = n2e_ptr[r1]; k < n2e_ptr[r1 + 1]; ++k)
+                    for (int a = 0; a < 4; ++a) {
+                        const int32_t v = tets[4 * (int64_t)n2e[k] + a];
+                        if (stamp[v] != tile) cand.push_back(v);
+                    }
+                std::sort(cand.begin(), cand.end());
+                cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+                if (ndist + (int64_t)cand.size() > kTileMaxNodes) break;
+                for (int32_t v : cand) stamp[v] = tile;
+                ndist += (int32_t)cand.size();
+                ++r1;
+            }
+            if (r1 == r0) {
+                free_all(c);
+                delete c;
+                return set_error(nullptr, VMS_EINVAL, "vms_create: the elements around node " + std::to_string(r0) +
+                                                          " touch more nodes than an assembly tile stages");
+            }
+            halo.clear();
+            for (int64_t i = r0; i < r1; ++i) {
+                loc[i] = (int32_t)(i - r0);
+                for (int32_t k = n2e_ptr[i]; k < n2e_ptr[i + 1]; ++k)
+                    for (int a = 0; a < 4; ++a) {
+                        const int32_t v = tets[4 * (int64_t)n2e[k] + a];
+                        if (v < r0 || v >= r1) halo.push_back(v);
+                    }
+            }
+            std::sort(halo.begin(), halo.end());
+            halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+            for (size_t j = 0; j < halo.size(); ++j) loc[halo[j]] = (int32_t)(r1 - r0 + (int64_t)j);
+            for (int64_t i = r0; i < r1; ++i) tnodes.push_back((int32_t)i);
+            tnodes.insert(tnodes.end(), halo.begin(), halo.end());
+            const int64_t ntn = (r1 - r0) + (int64_t)halo.size();
             // Items round-robin over the owned vertices (the r-th element of every owned node, then
             // the (r+1)-th, ...): a tile has at most 64 nodes, so the 64 lanes of a wave mostly own
             // different vertices and their LDS row additions do not collide on an address.
@@ -443,21 +483,30 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
             const int32_t b0 = rowptr[r0];
             for (auto& it : list) {
                 const int32_t e = it.first, a = it.second;
-                const int32_t row = tets[4 * (int64_t)e + a];
-                // slots in the item's vertex order a, a^1, a^2, a^3 (owned vertex first)
-                uint32_t p[4];
-                for (int b = 0; b < 4; ++b) p[b] = (uint32_t)(find(row, tets[4 * (int64_t)e + (b ^ a)]) - b0);
-                iea.push_back(4 * e + a);
-                ipos.push_back(make_uint2(p[0] | (p[1] << 16), p[2] | (p[3] << 16)));
+                const int32_t* t = &tets[4 * (int64_t)e];
+                // vertex order a, a^1, a^2, a^3 (owned vertex first): local node numbers and the
+                // tile-local block slots of the owned row; bit 15 marks the element's first vertex
+                uint32_t p[4], l = 0;
+                for (int b = 0; b < 4; ++b) {
+                    p[b] = (uint32_t)(find(t[a], t[b ^ a]) - b0);
+                    l |= (uint32_t)loc[t[b ^ a]] << (8 * b);
+                }
+                items.push_back(make_uint4((uint32_t)e, l, p[0] | (a == 0 ? 0x8000u : 0u) | (p[1] << 16),
+                                           p[2] | (p[3] << 16)));
             }
             tnode0.push_back((int32_t)r1);
-            tiptr.push_back((int32_t)iea.size());
-            lds_max = std::max(lds_max, tile_lds_bytes(rowptr[r1] - rowptr[r0], r1 - r0, acc_size));
+            tiptr.push_back((int32_t)items.size());
+            tnptr.push_back((int32_t)tnodes.size());
+            const size_t base = tile_lds_bytes(rowptr[r1] - rowptr[r0], r1 - r0, acc_size);
+            lds_max = std::max(lds_max, base + (size_t)ntn * 64);
+            lds_max_tr = std::max(lds_max_tr, base + (size_t)ntn * 96);
             r0 = r1;
+            ++tile;
         }
     }
     c->n_tiles = (int32_t)(tnode0.size() - 1);
     c->tile_lds = lds_max;
+    c->tile_lds_tr = lds_max_tr;
 
     std::vector<double> xyz4(4 * nn);
     for (int64_t i = 0; i < nn; ++i) {
@@ -479,8 +528,9 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->tpos, c->nb * sizeof(int32_t), "alloc tpos"));
     TRY(dev_alloc(c, &c->tile_node0, tnode0.size() * sizeof(int32_t), "alloc tiles"));
     TRY(dev_alloc(c, &c->tile_iptr, tiptr.size() * sizeof(int32_t), "alloc tiles"));
-    TRY(dev_alloc(c, &c->item_ea, iea.size() * sizeof(int32_t), "alloc tile items"));
-    TRY(dev_alloc(c, &c->item_pos, ipos.size() * sizeof(uint2), "alloc tile items"));
+    TRY(dev_alloc(c, &c->tile_nptr, tnptr.size() * sizeof(int32_t), "alloc tiles"));
+    TRY(dev_alloc(c, &c->tile_nodes, tnodes.size() * sizeof(int32_t), "alloc tile nodes"));
+    TRY(dev_alloc(c, &c->items, items.size() * sizeof(uint4), "alloc tile items"));
     TRY(dev_alloc(c, &c->bmask, c->nb * sizeof(uint16_t), "alloc block masks"));
     TRY(dev_alloc(c, &c->tile_part, 2 * (size_t)c->n_tiles * sizeof(double), "alloc tile partials"));
     TRY(dev_alloc(c, &c->A, c->nb * 16 * es, "alloc A"));
@@ -533,8 +583,9 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(check_hip(c, hipMemcpy(c->tpos, tpos.data(), c->nb * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     TRY(check_hip(c, hipMemcpy(c->tile_node0, tnode0.data(), tnode0.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     TRY(check_hip(c, hipMemcpy(c->tile_iptr, tiptr.data(), tiptr.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
-    TRY(check_hip(c, hipMemcpy(c->item_ea, iea.data(), iea.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
-    TRY(check_hip(c, hipMemcpy(c->item_pos, ipos.data(), ipos.size() * sizeof(uint2), hipMemcpyHostToDevice), "upload"));
+    TRY(check_hip(c, hipMemcpy(c->tile_nptr, tnptr.data(), tnptr.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    TRY(check_hip(c, hipMemcpy(c->tile_nodes, tnodes.data(), tnodes.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    TRY(check_hip(c, hipMemcpy(c->items, items.data(), items.size() * sizeof(uint4), hipMemcpyHostToDevice), "upload"));
     {
         std::vector<uint16_t> bm(c->nb);
         for (int64_t i = 0; i < nn; ++i)

@@ -347,8 +347,9 @@ constexpr int kTileThreads = VMS_TILE_THREADS;
 struct TileArgs {
     const int32_t* __restrict__ node0;
     const int32_t* __restrict__ iptr;
-    const int32_t* __restrict__ ea;
-    const uint2* __restrict__ pos;
+    const int32_t* __restrict__ nptr;
+    const int32_t* __restrict__ nodes;
+    const uint4* __restrict__ items;
     const int32_t* __restrict__ rowptr;
     const uint16_t* __restrict__ bmask;   // per block: column node's Dirichlet bits (0..3),
                                           // row node's (4..7), diagonal block (bit 8)
@@ -416,8 +417,20 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
     const size_t off = CONDENSE ? align16((size_t)nbk * kLdsBlockStride * sizeof(TACC)) : 0;
     double* rr = reinterpret_cast<double*>(smem + off);
     double* rg = rr + (size_t)nn * 4;
+    // the tile's nodes: coordinates, state and (transient) previous state, one double4 each
+    const int nbase = ta.nptr[t], ntn = ta.nptr[t + 1] - nbase;
+    double4* sx = reinterpret_cast<double4*>(rg + (size_t)nn * 4);
+    double4* su = sx + ntn;
+    double4* sup = su + ntn;
     __shared__ double wsum[kTileThreads / 64][2];
 
+    const bool transient = args.u_prev != nullptr && args.inv_dt != 0.0;
+    for (int i = threadIdx.x; i < ntn; i += blockDim.x) {
+        const int g = ta.nodes[nbase + i];
+        sx[i] = args.xyz4[g];
+        su[i] = reinterpret_cast<const double4*>(args.u)[g];
+        if (transient) sup[i] = reinterpret_cast<const double4*>(args.u_prev)[g];
+    }
     if (CONDENSE)
         for (int i = threadIdx.x; i < nbk * kLdsBlockStride; i += blockDim.x) blk[i] = TACC(0);
     for (int i = threadIdx.x; i < nn * 4; i += blockDim.x) {
@@ -427,35 +440,22 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
     __syncthreads();
 
     const double nu = args.nu;
-    const bool transient = args.u_prev != nullptr && args.inv_dt != 0.0;
     const double inv_dt = transient ? args.inv_dt : 0.0;
     double rf2 = 0.0;
     const int k_end = ta.iptr[t + 1];
     for (int k = ta.iptr[t] + threadIdx.x; k < k_end; k += blockDim.x) {
-        const int ea = ta.ea[k];
-        const int e = ea >> 2, a = ea & 3;
-        int4 tv = args.tets[e];
-        // vertex order (a, a^1, a^2, a^3): the owned vertex first, orientation kept
-        if (a & 1) {
-            const int x = tv.x, z = tv.z;
-            tv.x = tv.y;
-            tv.y = x;
-            tv.z = tv.w;
-            tv.w = z;
-        }
-        if (a & 2) {
-            const int x = tv.x, y = tv.y;
-            tv.x = tv.z;
-            tv.y = tv.w;
-            tv.z = x;
-            tv.w = y;
-        }
-        const int nid[4] = {tv.x, tv.y, tv.z, tv.w};
+        // item: element, local node numbers in the order (a, a^1, a^2, a^3) -- the owned vertex
+        // first, orientation kept -- and the owned row's block slots
+        const uint4 rec = ta.items[k];
+        const int e = (int)rec.x;
+        const int nl[4] = {(int)(rec.y & 255u), (int)((rec.y >> 8) & 255u), (int)((rec.y >> 16) & 255u),
+                           (int)(rec.y >> 24)};
+        const bool first = (rec.z & 0x8000u) != 0;     // the element's vertex 0 (R_f counted once)
         // geometry
         double X[4][3];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const double4 x = args.xyz4[nid[q]];
+            const double4 x = sx[nl[q]];
             X[q][0] = x.x;
             X[q][1] = x.y;
             X[q][2] = x.z;
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
         double dvs[3] = {}, dv0[3] = {}, fs[3] = {}, f0[3] = {};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const double4 uu = reinterpret_cast<const double4*>(args.u)[nid[q]];
+            const double4 uu = su[nl[q]];
             const double vq[3] = {uu.x, uu.y, uu.z};
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
             }
             ps += uu.w;
             if (transient) {
-                const double4 up = reinterpret_cast<const double4*>(args.u_prev)[nid[q]];
+                const double4 up = sup[nl[q]];
                 const double d[3] = {vq[0] - up.x, vq[1] - up.y, vq[2] - up.z};
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
@@ -519,9 +519,10 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
                 }
             }
             if (args.body) {
+                const size_t gq = (size_t)ta.nodes[nbase + nl[q]];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    const double f = args.body[3 * (size_t)nid[q] + i];
+                    const double f = args.body[3 * gq + i];
                     fs[i] += f;
                     if (q == 0) f0[i] = f;
                 }
@@ -543,7 +544,7 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
             Rf[i] = G[i][0] * Wv[0] + G[i][1] * Wv[1] + G[i][2] * Wv[2] +
                     Cm * (G[i][0] * be[0] + G[i][1] * be[1] + G[i][2] * be[2] - 0.5 * th * be[i]) +
                     2.0 * nu * Kb * be[i] + Bm * gp[i] - B1 * fs[i] + inv_dt * B1 * dvs[i];
-        if (a == 0) rf2 += Rf[0] * Rf[0] + Rf[1] * Rf[1] + Rf[2] * Rf[2];
+        if (first) rf2 += Rf[0] * Rf[0] + Rf[1] * Rf[1] + Rf[2] * Rf[2];
         // coarse residual rows of vertex 0
         const double g0W = g[0][0] * Wv[0] + g[0][1] * Wv[1] + g[0][2] * Wv[2];
         const double bg0 = be[0] * g[0][0] + be[1] * g[0][1] + be[2] * g[0][2];
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
                     2.0 * nu * vol * (G[i][0] * g[0][0] + G[i][1] * g[0][1] + G[i][2] * g[0][2]) -
                     0.25 * vol * ps * g[0][i] - m0 * (fs[i] + f0[i]) + inv_dt * m0 * (dvs[i] + dv0[i]);
         Rc[3] = -th * vol * 0.25 + Bm * bg0;
-        const int la = nid[0] - n0;
+        const int la = nl[0];                           // owned nodes come first in the local numbering
 #pragma unroll
         for (int r = 0; r < 4; ++r) atomic_add(&rg[4 * la + r], Rc[r]);
         if (!CONDENSE) continue;
@@ -652,8 +653,7 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
         F.idt = T(inv_dt);
         F.B1idt = T(B1 * inv_dt);
         F.Bm = T(Bm);
-        const uint2 pp = ta.pos[k];
-        const uint32_t slot[4] = {pp.x & 0xffffu, pp.x >> 16, pp.y & 0xffffu, pp.y >> 16};
+        const uint32_t slot[4] = {rec.z & 0x7fffu, rec.z >> 16, rec.w & 0xffffu, rec.w >> 16};
         add_blocks<T, TACC>(F, blk, slot);
     }
     __syncthreads();
@@ -836,12 +836,18 @@ ElemArgs make_args(vms_ctx* c, const double* u, const double* u_prev, const doub
     return a;
 }
 
+// dynamic LDS of a tile launch: the previous velocity is staged only in transient launches
+size_t tile_lds_of(const vms_ctx* c, const ElemArgs& a) {
+    return (a.u_prev != nullptr && a.inv_dt != 0.0) ? c->tile_lds_tr : c->tile_lds;
+}
+
 TileArgs tile_args(vms_ctx* c) {
     TileArgs t;
     t.node0 = c->tile_node0;
     t.iptr = c->tile_iptr;
-    t.ea = c->item_ea;
-    t.pos = c->item_pos;
+    t.nptr = c->tile_nptr;
+    t.nodes = c->tile_nodes;
+    t.items = c->items;
     t.rowptr = c->rowptr;
     t.bmask = c->bmask;
     return t;
@@ -850,7 +856,7 @@ TileArgs tile_args(vms_ctx* c) {
 }  // namespace
 
 hipError_t tile_kernels_configure(vms_ctx* c) {
-    const int lds = (int)c->tile_lds;
+    const int lds = (int)std::max(c->tile_lds, c->tile_lds_tr);
     hipError_t e = hipFuncSetAttribute((const void*)tile_kernel<double, double, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e == hipSuccess)
@@ -952,14 +958,14 @@ int launch_full_assemble(vms_ctx* c, const double* u, const double* u_prev, cons
     const int n4 = 4 * c->n_nodes;
     const int gcopy = (int)((std::max<int64_t>(nb16, n4) + kBlock - 1) / kBlock);
     if (c->prec == VMS_FP64) {
-        tile_kernel<double, double, true, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(
+        tile_kernel<double, double, true, false><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(
             a, tile_args(c), (double*)c->A, c->rhs, nullptr, c->tile_part);
         full_element_kernel<double><<<grid_for(c->n_elems), kBlock, 0, s>>>(a, c->n_nodes, c->full_epos,
                                                                             (double*)vals, rhs);
         full_copy_kernel<double><<<gcopy, kBlock, 0, s>>>(c->nb, n4, c->full_cc, (const double*)c->A,
                                                           (double*)vals, c->rhs, rhs);
     } else {
-        tile_kernel<float, MixedAcc, true, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(
+        tile_kernel<float, MixedAcc, true, false><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(
             a, tile_args(c), (float*)c->A, c->rhs, nullptr, c->tile_part);
         full_element_kernel<float><<<grid_for(c->n_elems), kBlock, 0, s>>>(a, c->n_nodes, c->full_epos,
                                                                           (float*)vals, rhs);
@@ -975,15 +981,19 @@ int launch_full_update(vms_ctx* c, const double* dx, double* u, double* beta, hi
     return check_hip(c, hipGetLastError(), "full update launch");
 }
 
-int launch_condense(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
-                    double inv_dt, const double* body, void* A, double* rhs, double* rglob, hipStream_t s) {
+// The condensed assembly with its scratch (element flags, per-tile norm partials) at the given
+// device addresses: the context's own buffers, or the static scratch of the no-allocation entry.
+static int launch_condense_in(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
+                              double inv_dt, const double* body, void* A, double* rhs, double* rglob,
+                              int32_t* flags, double* tile_part, hipStream_t s) {
     const size_t es = elt_size(c);
     const double nn = c->n_nodes, ne = c->n_elems;
     {
         PhaseScope ph(c, VMS_PH_FILL, 0.0, s);
-        flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
+        flags_reset_kernel<<<1, 64, 0, s>>>(flags);
     }
     ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
+    a.flags = flags;
     // algorithmic bytes: connectivity + beta per element; coordinates, state (and previous
     // velocity, body force) per node; block-CSR values and rhs written once (and the residual
     // rows, when asked for)
@@ -991,12 +1001,17 @@ int launch_condense(vms_ctx* c, const double* u, const double* u_prev, const dou
                        (double)c->nb * 16 * es + 32.0 * nn * (rglob ? 2.0 : 1.0);
     PhaseScope ph(c, VMS_PH_CONDENSE, alg, s);
     if (c->prec == VMS_FP64)
-        tile_kernel<double, double, true><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (double*)A,
-                                                                                       rhs, rglob, c->tile_part);
+        tile_kernel<double, double, true><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(a, tile_args(c), (double*)A,
+                                                                                       rhs, rglob, tile_part);
     else
-        tile_kernel<float, MixedAcc, true><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(a, tile_args(c), (float*)A,
-                                                                                        rhs, rglob, c->tile_part);
+        tile_kernel<float, MixedAcc, true><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(a, tile_args(c), (float*)A,
+                                                                                        rhs, rglob, tile_part);
     return check_hip(c, hipGetLastError(), "condense launch");
+}
+
+int launch_condense(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
+                    double inv_dt, const double* body, void* A, double* rhs, double* rglob, hipStream_t s) {
+    return launch_condense_in(c, u, u_prev, beta, nu, inv_dt, body, A, rhs, rglob, c->flags, c->tile_part, s);
 }
 
 int launch_residual(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
@@ -1008,15 +1023,19 @@ int launch_residual(vms_ctx* c, const double* u, const double* u_prev, const dou
         PhaseScope ph(c, VMS_PH_RESIDUAL,
                       ne * 40.0 + nn * (56.0 + (a.u_prev ? 24.0 : 0.0) + (body ? 24.0 : 0.0)) +
                           (rglob ? 32.0 * nn : 0.0), s);
-        tile_kernel<double, double, false><<<c->n_tiles, kTileThreads, c->tile_lds, s>>>(
+        tile_kernel<double, double, false><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(
             a, tile_args(c), (double*)nullptr, nullptr, rglob, c->tile_part);
     }
     return check_hip(c, hipGetLastError(), "residual launch");
 }
 
-int launch_norm_finalize(vms_ctx* c, double* out, hipStream_t s) {
-    norm_finalize_kernel<<<1, kFinThreads, 0, s>>>(c->n_tiles, c->tile_part, out);
+static int launch_norm_finalize_in(vms_ctx* c, const double* tile_part, double* out, hipStream_t s) {
+    norm_finalize_kernel<<<1, kFinThreads, 0, s>>>(c->n_tiles, tile_part, out);
     return check_hip(c, hipGetLastError(), "norm launch");
+}
+
+int launch_norm_finalize(vms_ctx* c, double* out, hipStream_t s) {
+    return launch_norm_finalize_in(c, c->tile_part, out, s);
 }
 
 int check_element_flags(vms_ctx* c, hipStream_t s) {

@@ -1393,7 +1393,9 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     cycle_v0_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, r0, V, c->gs);
     const int steps = std::min(m, budget);
     const double vb = (double)n * sizeof(T);      // bytes of one Krylov vector
-    const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 3.0 * vb;
+    // algorithmic bytes of the Arnoldi SpMV: blocks and column indices, row pointers, the input
+    // and output vectors once (the coarse-pressure vector A z it also reads is not credited)
+    const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 2.0 * vb;
     const int nch = std::max(1, std::min(kFusedChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
     double* part = c->red->partial;
     const double eps_dot = sizeof(T) == 8 ? 1e-14 : 1e-6;

@@ -22,17 +22,18 @@ extern "C" int vms_newton_step(vms_ctx* c, double* u, double* beta, const double
     int rc = launch_condense(c, u, up, beta, nu, inv_dt, body, c->A, c->rhs, nullptr, s);
     if (rc) return rc;
     if ((rc = launch_norm_finalize(c, c->rnorm, s))) return rc;
-    if ((rc = check_element_flags(c, s))) {
-        if (info) *info = inf;
-        return rc;
-    }
     if ((rc = check_hip(c, hipMemcpyAsync(&inf.rnorm_before, c->rnorm, sizeof(double), hipMemcpyDeviceToHost, s),
                         "read rnorm")))
         return rc;
     if ((rc = check_hip(c, hipStreamSynchronize(s), "sync"))) return rc;
+    // a non-finite state is reported as such (its K_ff also fails the singularity test)
     if (!std::isfinite(inf.rnorm_before)) {
         if (info) *info = inf;
         return set_error(c, VMS_ENONFINITE, "vms_newton_step: non-finite residual");
+    }
+    if ((rc = check_element_flags(c, s))) {
+        if (info) *info = inf;
+        return rc;
     }
 
     if ((rc = launch_fill(c->du, n * sizeof(double), s))) return rc;
@@ -79,10 +80,6 @@ extern "C" int vms_full_newton_step(vms_ctx* c, double* u, double* beta, const d
     int rc = launch_full_assemble(c, u, up, beta, nu, inv_dt, body, f->A, f->rhs, s);
     if (rc) return rc;
     if ((rc = launch_norm_finalize(c, c->rnorm, s))) return rc;
-    if ((rc = check_element_flags(c, s))) {
-        if (info) *info = inf;
-        return rc;
-    }
     if ((rc = check_hip(c, hipMemcpyAsync(&inf.rnorm_before, c->rnorm, sizeof(double), hipMemcpyDeviceToHost, s),
                         "read rnorm")))
         return rc;
@@ -90,6 +87,10 @@ extern "C" int vms_full_newton_step(vms_ctx* c, double* u, double* beta, const d
     if (!std::isfinite(inf.rnorm_before)) {
         if (info) *info = inf;
         return set_error(c, VMS_ENONFINITE, "vms_full_newton_step: non-finite residual");
+    }
+    if ((rc = check_element_flags(c, s))) {
+        if (info) *info = inf;
+        return rc;
     }
     if ((rc = launch_fill(f->du, n * sizeof(double), s))) return rc;
     vms_solve_opts lin = opts->lin;

@@ -21,8 +21,9 @@ constexpr int kMaxRestart = 128;
 #define VMS_DOT_CHUNKS 64          // upper bound on the workgroups (partials) per GMRES dot slot
 #endif
 constexpr int kTileNodes = 64;           // max nodes owned by one assembly tile
+constexpr int kTileMaxNodes = 255;       // max nodes staged by one tile (8-bit local numbers)
 #ifndef VMS_TILE_BLOCKS_FP64
-#define VMS_TILE_BLOCKS_FP64 300
+#define VMS_TILE_BLOCKS_FP64 280
 #endif
 #ifndef VMS_TILE_BLOCKS_FP32
 #define VMS_TILE_BLOCKS_FP32 870
@@ -110,18 +111,22 @@ struct vms_ctx {
     int32_t* colidx = nullptr;       // [nb]
     int32_t* diagpos = nullptr;      // [n_nodes]
     int32_t* tpos = nullptr;         // [nb] position of the transposed block
-    // assembly tiles: tile t owns block rows [tile_node0[t], tile_node0[t+1]) and works
-    // through work items (element e, owned vertex a): item_ea = 4 e + a, item_pos = the four
-    // tile-local block slots of row a (16 bits each) in the item's vertex order a, a^1, a^2, a^3
+    // assembly tiles: tile t owns block rows [tile_node0[t], tile_node0[t+1]) and stages the
+    // nodes tile_nodes[tile_nptr[t] ..) (owned ones first); it works through items
+    // [tile_iptr[t], tile_iptr[t+1]), one per (element e, owned vertex a), in the vertex order
+    // a, a^1, a^2, a^3: items = (e, four 8-bit local node numbers, four 16-bit tile-local block
+    // slots of the owned row; bit 15 of the first slot marks a = 0)
     int32_t n_tiles = 0;
     int32_t* tile_node0 = nullptr;   // [n_tiles + 1]
     int32_t* tile_iptr = nullptr;    // [n_tiles + 1]
-    int32_t* item_ea = nullptr;      // [4 n_elems]
-    uint2* item_pos = nullptr;       // [4 n_elems]
+    int32_t* tile_nptr = nullptr;    // [n_tiles + 1]
+    int32_t* tile_nodes = nullptr;   // [tile_nptr[n_tiles]]
+    uint4* items = nullptr;          // [4 n_elems]
     uint16_t* bmask = nullptr;       // [nb] Dirichlet bits of the column node (0..3) and the row
                                      // node (4..7), bit 8 on diagonal blocks
     double* tile_part = nullptr;     // [n_tiles][2] partial sums of the residual norm
-    size_t tile_lds = 0;             // dynamic LDS bytes of the largest tile
+    size_t tile_lds = 0;             // dynamic LDS bytes of the largest tile (steady)
+    size_t tile_lds_tr = 0;          // same with the previous velocity staged (transient)
 
     // Newton workspaces (device)
     void* A = nullptr;               // [nb][16] of the ctx precision
