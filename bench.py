@@ -118,12 +118,14 @@ def assembly_bench(B, ctx, mesh, u, beta, re, dt=0.0, u_prev=None):
             "alg_bytes_per_launch": byt / cnt, "alg_GBps": byt / cnt / (kern_us * 1e-6) / 1e9}
 
 
-# Algorithmic flops of one element's condensed tangent and residual (closed-form element),
-# counted from the formulas of the tile kernel with each element's shared work counted once:
-# geometry 87, fields 77, R_f 45, K_ff and its inverse 72 (FP64); per row vertex R_c 66,
-# K_cf 30, Y = K_cf K_ff^-1 36, R* 24 (FP64); per (row, column) block 48 (precision T).
-ELEM_FLOPS_FP64 = 87 + 77 + 45 + 72 + 4 * (66 + 30 + 36 + 24)
-ELEM_FLOPS_T = 16 * 48
+# Algorithmic flops of one element's condensed tangent and residual (closed-form element,
+# backward Euler, no body force), counted term by term from the tile kernel's formulas with
+# every quantity the element's four rows share counted once (add, sub, mul, div = 1 flop):
+#   FP64, per element: geometry 87, fields 128, R_f 84, K_ff and its inverse 78;
+#         per row vertex: R_c 121, K_cf 65, K_ff^-1 R_f and R* 39, Y = K_cf K_ff^-1 60
+#   precision T, per row vertex: block factors 165; per (row, column) block 111
+ELEM_FLOPS_FP64 = 87 + 128 + 84 + 78 + 4 * (121 + 65 + 39 + 60)
+ELEM_FLOPS_T = 4 * (165 + 4 * 111)
 
 
 def assembly_roofline(res, n_elems, mixed):
@@ -142,13 +144,14 @@ def assembly_roofline(res, n_elems, mixed):
 
 
 def cache_probe_gbps(nbytes):
-    """Device copy of nbytes (read nbytes + write nbytes) repeated, so that it stays in the caches:
-    the bandwidth a working set of this size sees (median of 20, HIP events)."""
+    """Read bandwidth a working set of nbytes sees when it is re-read back to back (so that it
+    stays in the L2 and Infinity Cache): a float32 sum over nbytes, median of 20 after 5
+    warm-ups, HIP events."""
     import torch
-    src = torch.ones(nbytes // 8, dtype=torch.float32, device="cuda:0")
-    dst = torch.empty_like(src)
-    t_us = event_median_us(lambda: dst.copy_(src), reps=20, warm=5)
-    return 2 * src.numel() * 4 / (t_us * 1e-6) / 1e9
+    buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    out = torch.empty((), dtype=torch.float32, device="cuda:0")
+    t_us = event_median_us(lambda: torch.sum(buf, out=out), reps=20, warm=5)
+    return buf.numel() * 4 / (t_us * 1e-6) / 1e9
 
 
 def spmv_roofline(prof, phase):
@@ -292,7 +295,7 @@ def main():
     roofline["traffic_source"] = traffic_src
     # the 37 MB matrix of this size stays in the 256 MB Infinity Cache between launches: its
     # bandwidth is also given against a copy of the same working set
-    probe = cache_probe_gbps(int(roofline["alg_bytes_per_launch"]) // 2)
+    probe = cache_probe_gbps(int(roofline["alg_bytes_per_launch"]))
     roofline["cache_probe_GBps"] = round(probe, 1)
     roofline["frac_vs_cache_probe"] = round(roofline["achieved"] / probe, 4)
     log(f"roofline: {roofline}")

@@ -124,7 +124,7 @@ static void free_all(vms_ctx* c) {
         c->full = nullptr;
     }
     void* ptrs[] = {c->full_cc, c->full_epos, c->zfull, c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
-                    c->tpos, c->tile_node0, c->tile_iptr, c->tile_nptr, c->tile_nodes, c->items, c->bmask, c->tile_part, c->A, c->rhs, c->du, c->rnorm, c->flags,
+                    c->tpos, c->tile_meta, c->tile_nodes, c->items, c->bmask, c->tile_part, c->A, c->rhs, c->du, c->rnorm, c->flags,
                     c->V, c->w, c->z, c->d, c->r, c->Minv, c->AP, c->Az, c->x64, c->r64, c->gs, c->red,
                     c->feats, c->hid, c->pblk, c->gblk, c->gdel, c->tvec, c->wgrad, c->fscal};
     for (void* p : ptrs)
@@ -526,9 +526,7 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->colidx, c->nb * sizeof(int32_t), "alloc colidx"));
     TRY(dev_alloc(c, &c->diagpos, nn * sizeof(int32_t), "alloc diagpos"));
     TRY(dev_alloc(c, &c->tpos, c->nb * sizeof(int32_t), "alloc tpos"));
-    TRY(dev_alloc(c, &c->tile_node0, tnode0.size() * sizeof(int32_t), "alloc tiles"));
-    TRY(dev_alloc(c, &c->tile_iptr, tiptr.size() * sizeof(int32_t), "alloc tiles"));
-    TRY(dev_alloc(c, &c->tile_nptr, tnptr.size() * sizeof(int32_t), "alloc tiles"));
+    TRY(dev_alloc(c, &c->tile_meta, 2 * (size_t)c->n_tiles * sizeof(int4), "alloc tiles"));
     TRY(dev_alloc(c, &c->tile_nodes, tnodes.size() * sizeof(int32_t), "alloc tile nodes"));
     TRY(dev_alloc(c, &c->items, items.size() * sizeof(uint4), "alloc tile items"));
     TRY(dev_alloc(c, &c->bmask, c->nb * sizeof(uint16_t), "alloc block masks"));
@@ -581,9 +579,15 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(check_hip(c, hipMemcpy(c->colidx, colidx.data(), c->nb * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     TRY(check_hip(c, hipMemcpy(c->diagpos, diagpos.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     TRY(check_hip(c, hipMemcpy(c->tpos, tpos.data(), c->nb * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
-    TRY(check_hip(c, hipMemcpy(c->tile_node0, tnode0.data(), tnode0.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
-    TRY(check_hip(c, hipMemcpy(c->tile_iptr, tiptr.data(), tiptr.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
-    TRY(check_hip(c, hipMemcpy(c->tile_nptr, tnptr.data(), tnptr.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
+    {
+        std::vector<int4> meta(2 * (size_t)c->n_tiles);
+        for (int32_t t = 0; t < c->n_tiles; ++t) {
+            meta[2 * t] = make_int4(tnode0[t], tnode0[t + 1], rowptr[tnode0[t]], rowptr[tnode0[t + 1]] - rowptr[tnode0[t]]);
+            meta[2 * t + 1] = make_int4(tiptr[t], tiptr[t + 1], tnptr[t], tnptr[t + 1] - tnptr[t]);
+        }
+        TRY(check_hip(c, hipMemcpy(c->tile_meta, meta.data(), meta.size() * sizeof(int4), hipMemcpyHostToDevice),
+                      "upload"));
+    }
     TRY(check_hip(c, hipMemcpy(c->tile_nodes, tnodes.data(), tnodes.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload"));
     TRY(check_hip(c, hipMemcpy(c->items, items.data(), items.size() * sizeof(uint4), hipMemcpyHostToDevice), "upload"));
     {

@@ -307,11 +307,6 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
     unsafeAtomicAdd(p, v);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
 
 // -------------------------------------------------------------------------------------------
 // Tiled assembly.  Workgroup t owns the block rows of nodes [n0, n1) (a contiguous range, so
@@ -345,12 +340,9 @@ constexpr int kTileThreads = VMS_TILE_THREADS;
 #endif
 
 struct TileArgs {
-    const int32_t* __restrict__ node0;
-    const int32_t* __restrict__ iptr;
-    const int32_t* __restrict__ nptr;
+    const int4* __restrict__ meta;        // per tile: (n0, n1, b0, nbk), (item0, item1, node base, nodes)
     const int32_t* __restrict__ nodes;
     const uint4* __restrict__ items;
-    const int32_t* __restrict__ rowptr;
     const uint16_t* __restrict__ bmask;   // per block: column node's Dirichlet bits (0..3),
                                           // row node's (4..7), diagonal block (bit 8)
 };
@@ -411,14 +403,14 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
     double* __restrict__ tile_part) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = blockIdx.x;
-    const int n0 = ta.node0[t], n1 = ta.node0[t + 1], nn = n1 - n0;
-    const int b0 = ta.rowptr[n0], nbk = ta.rowptr[n1] - b0;
+    const int4 m0 = ta.meta[2 * t], m1 = ta.meta[2 * t + 1];
+    const int n0 = m0.x, nn = m0.y - m0.x, b0 = m0.z, nbk = m0.w;
     TACC* blk = reinterpret_cast<TACC*>(smem);
     const size_t off = CONDENSE ? align16((size_t)nbk * kLdsBlockStride * sizeof(TACC)) : 0;
     double* rr = reinterpret_cast<double*>(smem + off);
     double* rg = rr + (size_t)nn * 4;
     // the tile's nodes: coordinates, state and (transient) previous state, one double4 each
-    const int nbase = ta.nptr[t], ntn = ta.nptr[t + 1] - nbase;
+    const int nbase = m1.z, ntn = m1.w;
     double4* sx = reinterpret_cast<double4*>(rg + (size_t)nn * 4);
     double4* su = sx + ntn;
     double4* sup = su + ntn;
@@ -431,22 +423,26 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
         su[i] = reinterpret_cast<const double4*>(args.u)[g];
         if (transient) sup[i] = reinterpret_cast<const double4*>(args.u_prev)[g];
     }
-    if (CONDENSE)
-        for (int i = threadIdx.x; i < nbk * kLdsBlockStride; i += blockDim.x) blk[i] = TACC(0);
-    for (int i = threadIdx.x; i < nn * 4; i += blockDim.x) {
-        rr[i] = 0.0;
-        rg[i] = 0.0;
+    // zero the staged rows (blocks, then rhs and residual rows), 16 bytes per store; the block
+    // region is padded to 16 bytes
+    {
+        const int nz = (CONDENSE ? (int)(off / 16) : 0) + nn * 4;
+        double2* z = reinterpret_cast<double2*>(CONDENSE ? smem : smem + off);
+        for (int i = threadIdx.x; i < nz; i += blockDim.x) z[i] = make_double2(0.0, 0.0);
     }
     __syncthreads();
 
     const double nu = args.nu;
     const double inv_dt = transient ? args.inv_dt : 0.0;
     double rf2 = 0.0;
-    const int k_end = ta.iptr[t + 1];
-    for (int k = ta.iptr[t] + threadIdx.x; k < k_end; k += blockDim.x) {
+    const int k_end = m1.y;
+    // item records are fetched one iteration ahead
+    uint4 rec_next = m1.x + (int)threadIdx.x < k_end ? ta.items[m1.x + threadIdx.x] : make_uint4(0, 0, 0, 0);
+    for (int k = m1.x + threadIdx.x; k < k_end; k += blockDim.x) {
         // item: element, local node numbers in the order (a, a^1, a^2, a^3) -- the owned vertex
         // first, orientation kept -- and the owned row's block slots
-        const uint4 rec = ta.items[k];
+        const uint4 rec = rec_next;
+        if (k + (int)blockDim.x < k_end) rec_next = ta.items[k + blockDim.x];
         const int e = (int)rec.x;
         const int nl[4] = {(int)(rec.y & 255u), (int)((rec.y >> 8) & 255u), (int)((rec.y >> 16) & 255u),
                            (int)(rec.y >> 24)};
@@ -843,12 +839,9 @@ size_t tile_lds_of(const vms_ctx* c, const ElemArgs& a) {
 
 TileArgs tile_args(vms_ctx* c) {
     TileArgs t;
-    t.node0 = c->tile_node0;
-    t.iptr = c->tile_iptr;
-    t.nptr = c->tile_nptr;
+    t.meta = c->tile_meta;
     t.nodes = c->tile_nodes;
     t.items = c->items;
-    t.rowptr = c->rowptr;
     t.bmask = c->bmask;
     return t;
 }

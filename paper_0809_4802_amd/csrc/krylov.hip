@@ -39,33 +39,6 @@ inline int xcd_round(int g) { return (g + kXcds - 1) / kXcds * kXcds; }
 // Lane exchanges of a double by DPP (two 32-bit moves; no LDS round trip).  CTRL: a
 // quad_perm pattern, or 0x140 (row_mirror: lane i <-> 15 - i in a row of 16) and 0x141
 // (row_half_mirror: lane i <-> 7 - i in a group of 8).  Every lane of the wave must be active.
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double read_lane(double v, int l) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-
-// Sum over the eight lanes of an aligned group (every lane gets it).
-__device__ __forceinline__ double group8_sum(double v) {
-    v += dpp_mov<0xB1>(v);           // quad_perm [1,0,3,2]: lane ^ 1
-    v += dpp_mov<0x4E>(v);           // quad_perm [2,3,0,1]: lane ^ 2
-    return v + dpp_mov<0x141>(v);    // the other quad of the eight
-}
-
-// Sum over the 64 lanes of the wave (every lane gets it): rows of 16 by DPP, then the four
-// row sums read back as scalars.  Every lane of the wave must be active.
-__device__ __forceinline__ double wave_sum(double v) {
-    v = group8_sum(v);
-    v += dpp_mov<0x140>(v);          // the other eight of the row
-    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
-}
-
 __device__ __forceinline__ double ld_agent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -49,6 +49,34 @@ __host__ __device__ inline size_t tile_lds_bytes(int64_t nblocks, int64_t nnodes
     return align16(nblocks * kLdsBlockStride * elt) + 2 * nnodes * 4 * 8;
 }
 
+// Lane exchanges by DPP moves (no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the eight lanes of an aligned group (every lane gets it).
+__device__ __forceinline__ double group8_sum(double v) {
+    v += dpp_mov<0xB1>(v);           // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_mov<0x4E>(v);           // quad_perm [2,3,0,1]: lane ^ 2
+    return v + dpp_mov<0x141>(v);    // the other quad of the eight
+}
+
+// Sum over the 64 lanes of the wave (every lane gets it): rows of 16 by DPP, then the four
+// row sums read back as scalars.  Every lane of the wave must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+    v = group8_sum(v);
+    v += dpp_mov<0x140>(v);          // the other eight of the row
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // Device-resident state of one GMRES cycle (Hessenberg matrix, Givens
 // rotations, residual estimate).  Updated by single-lane finalisers so that
 // the Arnoldi loop never waits for the host.
@@ -111,16 +139,15 @@ struct vms_ctx {
     int32_t* colidx = nullptr;       // [nb]
     int32_t* diagpos = nullptr;      // [n_nodes]
     int32_t* tpos = nullptr;         // [nb] position of the transposed block
-    // assembly tiles: tile t owns block rows [tile_node0[t], tile_node0[t+1]) and stages the
-    // nodes tile_nodes[tile_nptr[t] ..) (owned ones first); it works through items
-    // [tile_iptr[t], tile_iptr[t+1]), one per (element e, owned vertex a), in the vertex order
-    // a, a^1, a^2, a^3: items = (e, four 8-bit local node numbers, four 16-bit tile-local block
-    // slots of the owned row; bit 15 of the first slot marks a = 0)
+    // assembly tiles: tile t owns the block rows of a contiguous node range and stages the nodes
+    // its elements touch (owned ones first) in LDS; it works through its items, one per
+    // (element e, owned vertex a), in the vertex order a, a^1, a^2, a^3: items = (e, four 8-bit
+    // local node numbers, four 16-bit tile-local block slots of the owned row; bit 15 of the
+    // first slot marks a = 0)
     int32_t n_tiles = 0;
-    int32_t* tile_node0 = nullptr;   // [n_tiles + 1]
-    int32_t* tile_iptr = nullptr;    // [n_tiles + 1]
-    int32_t* tile_nptr = nullptr;    // [n_tiles + 1]
-    int32_t* tile_nodes = nullptr;   // [tile_nptr[n_tiles]]
+    int4* tile_meta = nullptr;       // [n_tiles][2]: (first node, end node, first block, blocks),
+                                     // (first item, end item, first staged node, staged nodes)
+    int32_t* tile_nodes = nullptr;   // [staged nodes of all tiles]
     uint4* items = nullptr;          // [4 n_elems]
     uint16_t* bmask = nullptr;       // [nb] Dirichlet bits of the column node (0..3) and the row
                                      // node (4..7), bit 8 on diagonal blocks
