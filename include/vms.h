@@ -122,6 +122,22 @@ int vms_condense_assemble(vms_ctx* ctx, const double* u, const double* u_prev, c
                           double Re, double dt, const double* body, void* bsr_vals, double* rhs,
                           double* rnorm, hipStream_t stream);
 
+/* The same call for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * identical inputs and outputs, but the scratch the call needs (element
+ * error flags and the per-tile partial sums of rnorm) lives in a static
+ * device array of the library, 1 MiB + 256 B per GPU, held until the process
+ * ends, instead of the context's buffers.  Nothing is allocated or freed and
+ * no library routine that allocates is called.  Limit: contexts of at most
+ * 65,536 assembly tiles (about 18 million block rows' worth of elements);
+ * larger ones get VMS_EINVAL.  Every call on one GPU shares that GPU's
+ * array (its contents are rewritten by each call): calls that overlap on one
+ * GPU, from any stream, thread or context, race and must be serialised by
+ * the caller.  Not synchronising. */
+int vms_condense_assemble_noalloc(vms_ctx* ctx, const double* u, const double* u_prev,
+                                  const double* beta, double Re, double dt, const double* body,
+                                  void* bsr_vals, double* rhs, double* rnorm, hipStream_t stream);
+
 /* FP64 Newton residual norm only (same definition as above); rglob
  * (double [n_nodes][4], may be NULL) receives the assembled [R_c; R_p].
  * Not synchronising. */

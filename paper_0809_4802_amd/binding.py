@@ -32,7 +32,7 @@ PC_NIN, PC_NHID, PC_NOUT = 25, 64, 16
 PC_NWEIGHTS = PC_NHID * PC_NIN + PC_NHID + PC_NOUT * PC_NHID + PC_NOUT
 
 EXPORTED = ["vms_create", "vms_destroy", "vms_last_error", "vms_bsr_info", "vms_element_tangents",
-            "vms_condense_assemble", "vms_residual", "vms_recover_update", "vms_bsr_spmv",
+            "vms_condense_assemble", "vms_condense_assemble_noalloc", "vms_residual", "vms_recover_update", "vms_bsr_spmv",
             "vms_gmres_solve", "vms_newton_step", "vms_full_info", "vms_full_assemble",
             "vms_full_newton_step", "vms_pc_features", "vms_pc_blocks",
             "vms_pc_train_step", "vms_profile", "vms_profile_read", "vms_set_linearization"]
@@ -92,6 +92,7 @@ _sig = {
                      ctypes.POINTER(_vp), ctypes.POINTER(_i32)],
     "vms_element_tangents": [_vp, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _vp],
     "vms_condense_assemble": [_vp, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _vp, _vp],
+    "vms_condense_assemble_noalloc": [_vp, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _vp, _vp],
     "vms_residual": [_vp, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _vp],
     "vms_recover_update": [_vp, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp],
     "vms_bsr_spmv": [_vp, _vp, _vp, _vp, _vp],
@@ -269,6 +270,16 @@ def vms_condense_assemble(ctx: Context, u, beta, Re, dt=0.0, u_prev=None, body=N
     rnorm = torch.zeros(1, dtype=torch.float64, device=ctx.device) if rnorm is None else rnorm
     _check(_lib.vms_condense_assemble(ctx.handle, _ptr(u), _ptr(u_prev), _ptr(beta), float(Re), float(dt),
                                       _ptr(body), _ptr(bsr_vals), _ptr(rhs), _ptr(rnorm), _stream(stream)),
+           ctx.handle)
+    return bsr_vals, rhs, rnorm
+
+
+def vms_condense_assemble_noalloc(ctx: Context, u, beta, Re, bsr_vals, rhs, rnorm, dt=0.0, u_prev=None, body=None,
+                                  stream=None):
+    """The no-allocation variant: every output buffer comes from the caller (nothing is allocated
+    here either)."""
+    _check(_lib.vms_condense_assemble_noalloc(ctx.handle, _ptr(u), _ptr(u_prev), _ptr(beta), float(Re), float(dt),
+                                              _ptr(body), _ptr(bsr_vals), _ptr(rhs), _ptr(rnorm), _stream(stream)),
            ctx.handle)
     return bsr_vals, rhs, rnorm
 

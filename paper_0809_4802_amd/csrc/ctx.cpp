@@ -605,6 +605,7 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     if (opts && opts->full_system)
         TRY(create_full_system(c, tets, n2e_ptr, n2e, rowptr, colidx, diagpos, dmask));
     TRY(check_hip(c, hipMemset(c->flags, 0, 8 * sizeof(int32_t)), "clear"));
+    TRY(noalloc_scratch_init(c));
     TRY(check_hip(c, hipDeviceSynchronize(), "sync"));
     *out = c;
     return VMS_OK;

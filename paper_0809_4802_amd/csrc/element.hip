@@ -27,6 +27,7 @@
 //   K* = K_cc - K_cf K_ff^-1 K_fc,  R* = R_cp - K_cf K_ff^-1 R_f,
 // recovery: dbeta = K_ff^-1 (-R_f - K_fc du_e).
 #include <climits>
+#include <mutex>
 
 #include "vms_internal.h"
 
@@ -1031,6 +1032,47 @@ int launch_norm_finalize(vms_ctx* c, double* out, hipStream_t s) {
     return launch_norm_finalize_in(c, c->tile_part, out, s);
 }
 
+// ---- scratch of the no-allocation entry point -----------------------------------------
+// One static array per device (each GPU the library runs on holds its own copy until the
+// process ends): the element flags, then the per-tile partial sums of the residual norm.
+constexpr int kNoallocMaxTiles = 1 << 16;
+constexpr size_t kNoallocFlagBytes = 256;
+constexpr size_t kNoallocBytes = kNoallocFlagBytes + 2 * sizeof(double) * kNoallocMaxTiles;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::once_flag g_scratch_once[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (hipGetSymbolAddress, once per device, with
+// that device current).  Host code uses only this address: the array's own name is a host-side
+// stand-in, not a device address.
+static int noalloc_scratch(vms_ctx* c, unsigned char** out) {
+    const int dev = c->device;
+    if (dev < 0 || dev >= kMaxDevices) return set_error(c, VMS_EINVAL, "no-allocation scratch: device index");
+    std::call_once(g_scratch_once[dev], [dev]() {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        g_scratch_err[dev] = e;
+        g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+    });
+    if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+        return check_hip(c, g_scratch_err[dev] != hipSuccess ? g_scratch_err[dev] : hipErrorInvalidSymbol,
+                         "no-allocation scratch address");
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return VMS_OK;
+}
+
+int noalloc_scratch_init(vms_ctx* c) {
+    unsigned char* p = nullptr;
+    return noalloc_scratch(c, &p);
+}
+
 int check_element_flags(vms_ctx* c, hipStream_t s) {
     int32_t h[3];
     int rc = check_hip(c, hipMemcpyAsync(h, c->flags, sizeof h, hipMemcpyDeviceToHost, s), "flags");
@@ -1080,6 +1122,27 @@ extern "C" int vms_condense_assemble(vms_ctx* c, const double* u, const double* 
                          bsr_vals, rhs, nullptr, s);
     if (rc) return rc;
     if (rnorm) return launch_norm_finalize(c, rnorm, s);
+    return VMS_OK;
+}
+
+extern "C" int vms_condense_assemble_noalloc(vms_ctx* c, const double* u, const double* u_prev, const double* beta,
+                                             double Re, double dt, const double* body, void* bsr_vals, double* rhs,
+                                             double* rnorm, hipStream_t s) {
+    int rc = check_state_args(c, u, beta, Re, dt, u_prev, "vms_condense_assemble_noalloc");
+    if (rc) return rc;
+    if (!bsr_vals || !rhs) return set_error(c, VMS_EINVAL, "vms_condense_assemble_noalloc: NULL output");
+    if (c->n_tiles > kNoallocMaxTiles)
+        return set_error(c, VMS_EINVAL, "vms_condense_assemble_noalloc: " + std::to_string(c->n_tiles) +
+                                            " assembly tiles exceed the static scratch (" +
+                                            std::to_string(kNoallocMaxTiles) + ")");
+    unsigned char* base = nullptr;
+    if ((rc = noalloc_scratch(c, &base))) return rc;
+    int32_t* flags = reinterpret_cast<int32_t*>(base);
+    double* part = reinterpret_cast<double*>(base + kNoallocFlagBytes);
+    rc = launch_condense_in(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body,
+                            bsr_vals, rhs, nullptr, flags, part, s);
+    if (rc) return rc;
+    if (rnorm) return launch_norm_finalize_in(c, part, rnorm, s);
     return VMS_OK;
 }
 

@@ -269,6 +269,9 @@ int launch_residual(vms_ctx* ctx, const double* u, const double* u_prev, const d
                     double nu, double inv_dt, const double* body, double* rglob, hipStream_t s);
 int launch_norm_finalize(vms_ctx* ctx, double* out, hipStream_t s);
 int check_element_flags(vms_ctx* ctx, hipStream_t s);
+// Resolves this device's address of the no-allocation entry point's static scratch (once per
+// device; called by vms_create with the context's device current).
+int noalloc_scratch_init(vms_ctx* ctx);
 // Uncondensed system (ctx->full must exist): assembly into vals / rhs of the full pattern, and
 // the Newton update from its solution dx.
 int launch_full_assemble(vms_ctx* ctx, const double* u, const double* u_prev, const double* beta, double nu,
