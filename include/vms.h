@@ -80,6 +80,15 @@ typedef struct {
     int32_t max_restart;       /* Krylov basis allocated (<= 0: 50)          */
     int32_t full_system;       /* 1: also build the uncondensed system used by
                                   vms_full_assemble / vms_full_newton_step   */
+    int32_t deterministic;     /* 1: assembly tiles of one wavefront, whose
+                                  staged sums are then formed in one fixed
+                                  order: every assembly (and every solve on
+                                  it) is bitwise reproducible from run to run
+                                  on the same device and build, at about 1.3x
+                                  the assembly time.  0: tiles of 256
+                                  threads, whose LDS additions interleave in
+                                  an order that varies from run to run
+                                  (results agree to rounding)               */
 } vms_create_opts;
 
 /* Builds the 4x4 block-CSR pattern of the condensed system (one block per

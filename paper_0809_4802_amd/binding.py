@@ -52,7 +52,8 @@ class MeshDesc(ctypes.Structure):
 
 
 class CreateOpts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("max_restart", ctypes.c_int32), ("full_system", ctypes.c_int32)]
+    _fields_ = [("precision", ctypes.c_int), ("max_restart", ctypes.c_int32), ("full_system", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -151,7 +152,7 @@ class Context:
     """Owns a vms_ctx*.  Tensors passed to it must be CUDA (HIP) tensors."""
 
     def __init__(self, xyz, tets, dirichlet_dofs, precision=VMS_FP64, max_restart=50, full_system=False,
-                 stream=None):
+                 stream=None, deterministic=False):
         xyz = _dev(xyz, torch.float64).contiguous()
         tets = _dev(tets, torch.int32).contiguous()
         dd = _dev(dirichlet_dofs, torch.int32).contiguous()
@@ -161,7 +162,7 @@ class Context:
         self.dtype = torch.float64 if precision == VMS_FP64 else torch.float32
         desc = MeshDesc(self.n_nodes, self.n_elems, xyz.data_ptr(), tets.data_ptr(), int(dd.numel()),
                         dd.data_ptr() if dd.numel() else None)
-        opts = CreateOpts(precision, max_restart, 1 if full_system else 0)
+        opts = CreateOpts(precision, max_restart, 1 if full_system else 0, 1 if deterministic else 0)
         h = ctypes.c_void_p()
         _check(_lib.vms_create(ctypes.byref(desc), ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
         self.handle = h

@@ -412,7 +412,15 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     // in LDS).  Local node numbering per tile: the owned nodes first, in order, then the other
     // vertices of the tile's elements in increasing global order.
     const size_t acc_size = c->prec == VMS_FP64 ? sizeof(double) : kMixedAccSize;
-    const int64_t max_blocks = acc_size == sizeof(double) ? kTileBlocksFP64 : kTileBlocksFP32;
+    const bool det = opts && opts->deterministic;
+    c->tile_threads = det ? 64 : 256;
+    int64_t max_blocks = det ? kTileBlocksDet : acc_size == sizeof(double) ? kTileBlocksFP64 : kTileBlocksFP32;
+    if (det) {
+        // a one-wavefront tile still holds the longest row of the pattern
+        int64_t longest = 0;
+        for (int64_t i = 0; i < nn; ++i) longest = std::max<int64_t>(longest, rowptr[i + 1] - rowptr[i]);
+        max_blocks = std::max(max_blocks, longest);
+    }
     std::vector<int32_t> tnode0{0}, tiptr{0}, tnptr{0}, tnodes;
     std::vector<uint4> items;
     items.reserve(4 * ne);

@@ -336,6 +336,10 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
 #define VMS_TILE_THREADS 256
 #endif
 constexpr int kTileThreads = VMS_TILE_THREADS;
+// Deterministic contexts: tiles of one wavefront.  Its LDS additions then happen in program
+// order (and, inside one instruction, in the hardware's fixed lane order), so every staged sum
+// is formed in the same order on every run.
+constexpr int kTileThreadsDet = 64;
 #ifndef VMS_TILE_WAVES_PER_SIMD
 #define VMS_TILE_WAVES_PER_SIMD 3
 #endif
@@ -398,8 +402,8 @@ __device__ __forceinline__ void add_blocks(const BlockFactors<T>& F, TACC* __res
     }
 }
 
-template <typename T, typename TACC, bool CONDENSE, bool SCHUR = true>
-__global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
+template <typename T, typename TACC, bool CONDENSE, bool SCHUR = true, int NT = kTileThreads>
+__global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
     ElemArgs args, TileArgs ta, T* __restrict__ Aval, double* __restrict__ rhs, double* __restrict__ rglob,
     double* __restrict__ tile_part) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -415,7 +419,7 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
     double4* sx = reinterpret_cast<double4*>(rg + (size_t)nn * 4);
     double4* su = sx + ntn;
     double4* sup = su + ntn;
-    __shared__ double wsum[kTileThreads / 64][2];
+    __shared__ double wsum[NT / 64][2];
 
     const bool transient = args.u_prev != nullptr && args.inv_dt != 0.0;
     for (int i = threadIdx.x; i < ntn; i += blockDim.x) {
@@ -424,6 +428,16 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
         su[i] = reinterpret_cast<const double4*>(args.u)[g];
         if (transient) sup[i] = reinterpret_cast<const double4*>(args.u_prev)[g];
     }
+    // the write-out's masks, fetched now so that their latency hides behind the items: the
+    // first two blocks of this thread (block masks) and its rhs entry's node (Dirichlet bits)
+    constexpr int kPre = 2;
+    uint32_t bm_pre[kPre];
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+        const int kb = threadIdx.x + q * (int)blockDim.x;
+        bm_pre[q] = (CONDENSE && kb < nbk) ? ta.bmask[b0 + kb] : 0u;
+    }
+    const uint32_t dm_pre = (int)threadIdx.x < nn * 4 ? args.dmask[n0 + (threadIdx.x >> 2)] : 0u;
     // zero the staged rows (blocks, then rhs and residual rows), 16 bytes per store; the block
     // region is padded to 16 bytes
     {
@@ -655,19 +669,34 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
     }
     __syncthreads();
     if (CONDENSE) {
-        // write the rows once, eliminating the Dirichlet dofs: zero rows and columns, unit diagonal
-        T* gdst = Aval + (size_t)b0 * 16;
-        for (int i = threadIdx.x; i < nbk * 16; i += blockDim.x) {
-            const int kb = i >> 4, r = (i >> 2) & 3, c = i & 3;
-            const uint32_t bm = ta.bmask[b0 + kb];
-            T v = T(blk[kb * kLdsBlockStride + (i & 15)]);
-            if (((bm >> (4 + r)) | (bm >> c)) & 1u) v = ((bm & 0x100u) && r == c) ? T(1) : T(0);
-            gdst[i] = v;
+        // write the rows once, a block per thread, eliminating the Dirichlet dofs: zero rows and
+        // columns, unit diagonal
+        using V4 = typename Vec4<T>::type;
+        for (int q = 0, kb = threadIdx.x; kb < nbk; ++q, kb += blockDim.x) {
+            const uint32_t bm = q < kPre ? bm_pre[q] : ta.bmask[b0 + kb];
+            const TACC* src = blk + (size_t)kb * kLdsBlockStride;
+            V4* dst = reinterpret_cast<V4*>(Aval + ((size_t)b0 + kb) * 16);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T v[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    v[c] = T(src[4 * r + c]);
+                    if (((bm >> (4 + r)) | (bm >> c)) & 1u) v[c] = ((bm & 0x100u) && r == c) ? T(1) : T(0);
+                }
+                V4 w;
+                w.x = v[0];
+                w.y = v[1];
+                w.z = v[2];
+                w.w = v[3];
+                dst[r] = w;
+            }
         }
     }
     double rg2 = 0.0;
     for (int i = threadIdx.x; i < nn * 4; i += blockDim.x) {
-        const bool fixed = (args.dmask[n0 + (i >> 2)] >> (i & 3)) & 1u;
+        const uint32_t dm = i == (int)threadIdx.x ? dm_pre : args.dmask[n0 + (i >> 2)];
+        const bool fixed = (dm >> (i & 3)) & 1u;
         const double rv = fixed ? 0.0 : rg[i];
         rg2 += rv * rv;
         if (rglob) rglob[4 * (size_t)n0 + i] = rv;
@@ -683,7 +712,7 @@ __global__ __launch_bounds__(kTileThreads, VMS_TILE_WAVES_PER_SIMD) void tile_ke
     if (threadIdx.x < 2) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < kTileThreads / 64; ++w) s += wsum[w][threadIdx.x];
+        for (int w = 0; w < NT / 64; ++w) s += wsum[w][threadIdx.x];
         tile_part[2 * (size_t)t + threadIdx.x] = s;
     }
 }
@@ -833,6 +862,19 @@ ElemArgs make_args(vms_ctx* c, const double* u, const double* u_prev, const doub
     return a;
 }
 
+// Launches tile_kernel<T, TACC, CONDENSE, SCHUR> at the context's tile width (256 threads, or one
+// wavefront in deterministic contexts).
+template <typename T, typename TACC, bool CONDENSE, bool SCHUR = true>
+void launch_tiles(const vms_ctx* c, const ElemArgs& a, const TileArgs& ta, size_t lds, T* Aval, double* rhs,
+                  double* rglob, double* part, hipStream_t s) {
+    if (c->tile_threads == kTileThreadsDet)
+        tile_kernel<T, TACC, CONDENSE, SCHUR, kTileThreadsDet><<<c->n_tiles, kTileThreadsDet, lds, s>>>(
+            a, ta, Aval, rhs, rglob, part);
+    else
+        tile_kernel<T, TACC, CONDENSE, SCHUR, kTileThreads><<<c->n_tiles, kTileThreads, lds, s>>>(a, ta, Aval, rhs,
+                                                                                                 rglob, part);
+}
+
 // dynamic LDS of a tile launch: the previous velocity is staged only in transient launches
 size_t tile_lds_of(const vms_ctx* c, const ElemArgs& a) {
     return (a.u_prev != nullptr && a.inv_dt != 0.0) ? c->tile_lds_tr : c->tile_lds;
@@ -851,14 +893,20 @@ TileArgs tile_args(vms_ctx* c) {
 
 hipError_t tile_kernels_configure(vms_ctx* c) {
     const int lds = (int)std::max(c->tile_lds, c->tile_lds_tr);
-    hipError_t e = hipFuncSetAttribute((const void*)tile_kernel<double, double, true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)tile_kernel<float, MixedAcc, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)tile_kernel<double, double, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    const void* fns[] = {
+        (const void*)tile_kernel<double, double, true, true, kTileThreads>,
+        (const void*)tile_kernel<float, MixedAcc, true, true, kTileThreads>,
+        (const void*)tile_kernel<double, double, false, true, kTileThreads>,
+        (const void*)tile_kernel<double, double, true, false, kTileThreads>,
+        (const void*)tile_kernel<float, MixedAcc, true, false, kTileThreads>,
+        (const void*)tile_kernel<double, double, true, true, kTileThreadsDet>,
+        (const void*)tile_kernel<float, MixedAcc, true, true, kTileThreadsDet>,
+        (const void*)tile_kernel<double, double, false, true, kTileThreadsDet>,
+        (const void*)tile_kernel<double, double, true, false, kTileThreadsDet>,
+        (const void*)tile_kernel<float, MixedAcc, true, false, kTileThreadsDet>};
+    hipError_t e = hipSuccess;
+    for (const void* f : fns)
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     return e;
 }
 
@@ -952,15 +1000,15 @@ int launch_full_assemble(vms_ctx* c, const double* u, const double* u_prev, cons
     const int n4 = 4 * c->n_nodes;
     const int gcopy = (int)((std::max<int64_t>(nb16, n4) + kBlock - 1) / kBlock);
     if (c->prec == VMS_FP64) {
-        tile_kernel<double, double, true, false><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(
-            a, tile_args(c), (double*)c->A, c->rhs, nullptr, c->tile_part);
+        launch_tiles<double, double, true, false>(c, a, tile_args(c), tile_lds_of(c, a), (double*)c->A, c->rhs,
+                                                  nullptr, c->tile_part, s);
         full_element_kernel<double><<<grid_for(c->n_elems), kBlock, 0, s>>>(a, c->n_nodes, c->full_epos,
                                                                             (double*)vals, rhs);
         full_copy_kernel<double><<<gcopy, kBlock, 0, s>>>(c->nb, n4, c->full_cc, (const double*)c->A,
                                                           (double*)vals, c->rhs, rhs);
     } else {
-        tile_kernel<float, MixedAcc, true, false><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(
-            a, tile_args(c), (float*)c->A, c->rhs, nullptr, c->tile_part);
+        launch_tiles<float, MixedAcc, true, false>(c, a, tile_args(c), tile_lds_of(c, a), (float*)c->A, c->rhs,
+                                                   nullptr, c->tile_part, s);
         full_element_kernel<float><<<grid_for(c->n_elems), kBlock, 0, s>>>(a, c->n_nodes, c->full_epos,
                                                                           (float*)vals, rhs);
         full_copy_kernel<float><<<gcopy, kBlock, 0, s>>>(c->nb, n4, c->full_cc, (const float*)c->A, (float*)vals,
@@ -995,11 +1043,9 @@ static int launch_condense_in(vms_ctx* c, const double* u, const double* u_prev,
                        (double)c->nb * 16 * es + 32.0 * nn * (rglob ? 2.0 : 1.0);
     PhaseScope ph(c, VMS_PH_CONDENSE, alg, s);
     if (c->prec == VMS_FP64)
-        tile_kernel<double, double, true><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(a, tile_args(c), (double*)A,
-                                                                                       rhs, rglob, tile_part);
+        launch_tiles<double, double, true>(c, a, tile_args(c), tile_lds_of(c, a), (double*)A, rhs, rglob, tile_part, s);
     else
-        tile_kernel<float, MixedAcc, true><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(a, tile_args(c), (float*)A,
-                                                                                        rhs, rglob, tile_part);
+        launch_tiles<float, MixedAcc, true>(c, a, tile_args(c), tile_lds_of(c, a), (float*)A, rhs, rglob, tile_part, s);
     return check_hip(c, hipGetLastError(), "condense launch");
 }
 
@@ -1017,8 +1063,8 @@ int launch_residual(vms_ctx* c, const double* u, const double* u_prev, const dou
         PhaseScope ph(c, VMS_PH_RESIDUAL,
                       ne * 40.0 + nn * (56.0 + (a.u_prev ? 24.0 : 0.0) + (body ? 24.0 : 0.0)) +
                           (rglob ? 32.0 * nn : 0.0), s);
-        tile_kernel<double, double, false><<<c->n_tiles, kTileThreads, tile_lds_of(c, a), s>>>(
-            a, tile_args(c), (double*)nullptr, nullptr, rglob, c->tile_part);
+        launch_tiles<double, double, false>(c, a, tile_args(c), tile_lds_of(c, a), (double*)nullptr, nullptr, rglob,
+                                            c->tile_part, s);
     }
     return check_hip(c, hipGetLastError(), "residual launch");
 }

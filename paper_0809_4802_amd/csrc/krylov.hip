@@ -36,23 +36,10 @@ constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_slot(int b, int g) { return (b % kXcds) * (g / kXcds) + b / kXcds; }
 inline int xcd_round(int g) { return (g + kXcds - 1) / kXcds * kXcds; }
 
-// Lane exchanges of a double by DPP (two 32-bit moves; no LDS round trip).  CTRL: a
-// quad_perm pattern, or 0x140 (row_mirror: lane i <-> 15 - i in a row of 16) and 0x141
-// (row_half_mirror: lane i <-> 7 - i in a group of 8).  Every lane of the wave must be active.
 __device__ __forceinline__ double ld_agent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T>
-struct Vec4;
-template <>
-struct Vec4<double> {
-    using type = double4;
-};
-template <>
-struct Vec4<float> {
-    using type = float4;
-};
 
 __global__ void fill_kernel(uint4* p, size_t n16) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)

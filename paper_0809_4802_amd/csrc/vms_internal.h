@@ -25,6 +25,9 @@ constexpr int kTileMaxNodes = 255;       // max nodes staged by one tile (8-bit 
 #ifndef VMS_TILE_BLOCKS_FP64
 #define VMS_TILE_BLOCKS_FP64 280
 #endif
+#ifndef VMS_TILE_BLOCKS_DET
+#define VMS_TILE_BLOCKS_DET 64
+#endif
 #ifndef VMS_TILE_BLOCKS_FP32
 #define VMS_TILE_BLOCKS_FP32 870
 #endif
@@ -38,7 +41,8 @@ constexpr int kTileMaxNodes = 255;       // max nodes staged by one tile (8-bit 
 using MixedAcc = std::conditional_t<VMS_MIXED_LDS_FP64 != 0, double, float>;
 constexpr size_t kMixedAccSize = sizeof(MixedAcc);
 constexpr int kTileBlocksFP64 = VMS_TILE_BLOCKS_FP64;   // max 4x4 blocks staged in LDS per tile (FP64 values)
-constexpr int kTileBlocksFP32 = VMS_TILE_BLOCKS_FP32;   // same for FP32 values (LDS per tile stays under 64 KB)
+constexpr int kTileBlocksFP32 = VMS_TILE_BLOCKS_FP32;
+constexpr int kTileBlocksDet = VMS_TILE_BLOCKS_DET;     // blocks per one-wavefront tile (deterministic contexts)   // same for FP32 values (LDS per tile stays under 64 KB)
 
 // Dynamic LDS of a tile: block values (each 4x4 block padded to 17 entries so that the
 // lanes of a wave, which update the same entry of different blocks, spread over the LDS
@@ -49,7 +53,21 @@ __host__ __device__ inline size_t tile_lds_bytes(int64_t nblocks, int64_t nnodes
     return align16(nblocks * kLdsBlockStride * elt) + 2 * nnodes * 4 * 8;
 }
 
-// Lane exchanges by DPP moves (no LDS traffic).
+// Four-wide vector of a precision (one node's dofs, one block row).
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<double> {
+    using type = double4;
+};
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+
+// Lane exchanges of a double by DPP (two 32-bit moves; no LDS round trip).  CTRL: a
+// quad_perm pattern, or 0x140 (row_mirror: lane i <-> 15 - i in a row of 16) and 0x141
+// (row_half_mirror: lane i <-> 7 - i in a group of 8).  Every lane of the wave must be active.
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
@@ -152,6 +170,7 @@ struct vms_ctx {
     uint16_t* bmask = nullptr;       // [nb] Dirichlet bits of the column node (0..3) and the row
                                      // node (4..7), bit 8 on diagonal blocks
     double* tile_part = nullptr;     // [n_tiles][2] partial sums of the residual norm
+    int32_t tile_threads = 256;      // threads per assembly tile (64: deterministic context)
     size_t tile_lds = 0;             // dynamic LDS bytes of the largest tile (steady)
     size_t tile_lds_tr = 0;          // same with the previous velocity staged (transient)
 
