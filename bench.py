@@ -150,7 +150,7 @@ def cache_probe_gbps(nbytes):
     import torch
     buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     out = torch.empty((), dtype=torch.float32, device="cuda:0")
-    t_us = event_median_us(lambda: torch.sum(buf, out=out), reps=20, warm=5)
+    t_us = event_median_us(lambda: torch.sum(buf, dim=0, out=out), reps=20, warm=5)
     return buf.numel() * 4 / (t_us * 1e-6) / 1e9
 
 

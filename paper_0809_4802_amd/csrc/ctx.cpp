@@ -11,6 +11,8 @@
 #include <cstring>
 #include <vector>
 
+#include <map>
+
 #include "vms_internal.h"
 
 namespace {
@@ -407,6 +409,11 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
         for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) tpos[k] = find(colidx[k], (int32_t)i);
     }
 
+    struct Quad {
+        int32_t e[4];
+        int n;          // elements taken (the rest are zero-weight copies of e[0])
+        int32_t j;      // neighbour shared by all four elements, or -1
+    };
     // Assembly tiles: contiguous node ranges whose block rows fit the LDS budget and whose
     // elements touch at most kTileMaxNodes distinct nodes (their coordinates and state are staged
     // in LDS).  Local node numbering per tile: the owned nodes first, in order, then the other
@@ -414,6 +421,9 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     const size_t acc_size = c->prec == VMS_FP64 ? sizeof(double) : kMixedAccSize;
     const bool det = opts && opts->deterministic;
     c->tile_threads = det ? 64 : 256;
+    // DPP quads in the one-wavefront FP32-block tiles (the FP64 kernel has no registers left
+    // for the quad sums)
+    const bool quads = det && c->prec == VMS_MIXED;
     int64_t max_blocks = det ? kTileBlocksDet : acc_size == sizeof(double) ? kTileBlocksFP64 : kTileBlocksFP32;
     if (det) {
         // a one-wavefront tile still holds the longest row of the pattern
@@ -429,7 +439,6 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
         std::vector<int32_t> stamp(nn, -1), loc(nn, 0), cand, halo;
         int64_t r0 = 0;
         int32_t tile = 0;
-        std::vector<std::pair<int32_t, int32_t>> list;   // (element, local vertex)
         while (r0 < nn) {
             if (rowptr[r0 + 1] - rowptr[r0] > max_blocks) {
                 free_all(c);
@@ -475,33 +484,104 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
             for (int64_t i = r0; i < r1; ++i) tnodes.push_back((int32_t)i);
             tnodes.insert(tnodes.end(), halo.begin(), halo.end());
             const int64_t ntn = (r1 - r0) + (int64_t)halo.size();
-            // Items round-robin over the owned vertices (the r-th element of every owned node, then
-            // the (r+1)-th, ...): a tile has at most 64 nodes, so the 64 lanes of a wave mostly own
-            // different vertices and their LDS row additions do not collide on an address.
-            list.clear();
+            // Deterministic mixed-precision tiles take their items in quads: four consecutive items
+            // (the four lanes of a DPP quad) belong to one owned row, so the kernel sums their
+            // diagonal block and residual rows across the quad and lets one lane do the LDS
+            // additions (in a one-wavefront tile, a wavefront holds many items of each row).  A row's elements are grouped greedily
+            // by a shared edge (i, j) where four of them still share one; such a quad puts j at
+            // local position 1 in all four items and sums that block too.  A row's last quad is
+            // padded with zero-weight copies.  Quads go round-robin over the owned rows (the
+            // r-th quad of every row, then the (r+1)-th), so that the lanes of a wavefront mostly
+            // add into different rows.
+            // Without quads (quads == false) every quad holds one item: the items of the owned rows
+            // go round-robin (the r-th element of every owned row, then the (r+1)-th, ...).
+            std::vector<std::vector<Quad>> row_quads(r1 - r0);
             int32_t rounds = 0;
-            for (int64_t i = r0; i < r1; ++i) rounds = std::max(rounds, n2e_ptr[i + 1] - n2e_ptr[i]);
+            for (int64_t i = r0; i < r1; ++i) {
+                auto& qs = row_quads[i - r0];
+                std::vector<int32_t> rem(n2e.begin() + n2e_ptr[i], n2e.begin() + n2e_ptr[i + 1]);
+                while (!rem.empty()) {
+                    Quad q{};
+                    q.j = -1;
+                    if (!quads) {
+                        q.e[0] = rem.front();
+                        q.n = 1;
+                        rem.erase(rem.begin());
+                        qs.push_back(q);
+                        continue;
+                    }
+                    if (rem.size() >= 4) {
+                        // the neighbour shared by the most remaining elements
+                        std::map<int32_t, int> cnt;
+                        for (int32_t e : rem)
+                            for (int b = 0; b < 4; ++b) {
+                                const int32_t v = tets[4 * (int64_t)e + b];
+                                if (v != i) cnt[v]++;
+                            }
+                        int32_t best = -1;
+                        int bc = 0;
+                        for (auto& kv : cnt)
+                            if (kv.second > bc) best = kv.first, bc = kv.second;
+                        if (bc >= 4) q.j = best;
+                    }
+                    int taken = 0;
+                    for (size_t k = 0; k < rem.size() && taken < 4;) {
+                        const int32_t e = rem[k];
+                        bool has = q.j < 0;
+                        for (int b = 0; b < 4 && !has; ++b) has = tets[4 * (int64_t)e + b] == q.j;
+                        if (has) {
+                            q.e[taken++] = e;
+                            rem.erase(rem.begin() + k);
+                        } else {
+                            ++k;
+                        }
+                    }
+                    q.n = taken;
+                    qs.push_back(q);
+                }
+                rounds = std::max(rounds, (int32_t)qs.size());
+            }
+            const int32_t b0 = rowptr[r0];
             for (int32_t r = 0; r < rounds; ++r)
                 for (int64_t i = r0; i < r1; ++i) {
-                    if (n2e_ptr[i] + r >= n2e_ptr[i + 1]) continue;
-                    const int32_t e = n2e[n2e_ptr[i] + r];
-                    for (int a = 0; a < 4; ++a)
-                        if (tets[4 * (int64_t)e + a] == i) list.emplace_back(e, a);
+                    const auto& qs = row_quads[i - r0];
+                    if (r >= (int32_t)qs.size()) continue;
+                    const Quad& q = qs[r];
+                    for (int m = 0; m < (quads ? 4 : 1); ++m) {
+                        const bool dummy = m >= q.n;
+                        const int32_t e = q.e[dummy ? 0 : m];
+                        const int32_t* t = &tets[4 * (int64_t)e];
+                        int a = 0;
+                        while (t[a] != i) ++a;
+                        // vertex order: the owned vertex a first, then j (when the quad shares it),
+                        // then the others, as an even permutation of (0, 1, 2, 3)
+                        int ord[4] = {a, a ^ 1, a ^ 2, a ^ 3};
+                        if (q.j >= 0) {
+                            int pj = 1;
+                            while (t[ord[pj]] != q.j) ++pj;
+                            if (pj != 1) {
+                                // rotate positions 1..3 (an even permutation) until j is at 1
+                                while (t[ord[1]] != q.j) {
+                                    const int x = ord[1];
+                                    ord[1] = ord[2];
+                                    ord[2] = ord[3];
+                                    ord[3] = x;
+                                }
+                            }
+                        }
+                        uint32_t pslot[4], l = 0;
+                        for (int b = 0; b < 4; ++b) {
+                            pslot[b] = (uint32_t)(find((int32_t)i, t[ord[b]]) - b0);
+                            l |= (uint32_t)loc[t[ord[b]]] << (8 * b);
+                        }
+                        // x: element (bit 31: zero-weight copy); y: local node numbers; z: slots
+                        // 0, 1 (bit 15: the element's vertex 0, counted once in the norm); w:
+                        // slots 2, 3 (bit 31: the quad shares slot 1)
+                        items.push_back(make_uint4((uint32_t)e | (dummy ? 0x80000000u : 0u), l,
+                                                   pslot[0] | ((a == 0 && !dummy) ? 0x8000u : 0u) | (pslot[1] << 16),
+                                                   pslot[2] | (pslot[3] << 16) | (q.j >= 0 ? 0x80000000u : 0u)));
+                    }
                 }
-            const int32_t b0 = rowptr[r0];
-            for (auto& it : list) {
-                const int32_t e = it.first, a = it.second;
-                const int32_t* t = &tets[4 * (int64_t)e];
-                // vertex order a, a^1, a^2, a^3 (owned vertex first): local node numbers and the
-                // tile-local block slots of the owned row; bit 15 marks the element's first vertex
-                uint32_t p[4], l = 0;
-                for (int b = 0; b < 4; ++b) {
-                    p[b] = (uint32_t)(find(t[a], t[b ^ a]) - b0);
-                    l |= (uint32_t)loc[t[b ^ a]] << (8 * b);
-                }
-                items.push_back(make_uint4((uint32_t)e, l, p[0] | (a == 0 ? 0x8000u : 0u) | (p[1] << 16),
-                                           p[2] | (p[3] << 16)));
-            }
             tnode0.push_back((int32_t)r1);
             tiptr.push_back((int32_t)items.size());
             tnptr.push_back((int32_t)tnodes.size());

@@ -374,9 +374,36 @@ struct BlockFactors {
     T m0, idt, B1idt, Bm;
 };
 
-// One item's four condensed blocks added to the staged rows.
-template <typename T, typename TACC>
-__device__ __forceinline__ void add_blocks(const BlockFactors<T>& F, TACC* __restrict__ blk, const uint32_t slot[4]) {
+// Sum over the four lanes of a DPP quad (all four active; every lane gets the sum).
+__device__ __forceinline__ float quad_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_mov<0xB1>(v);
+    return v + dpp_mov<0x4E>(v);
+}
+
+// Adds one value of an item to the staged rows.  With QUADS, quad-shared entries (the four
+// lanes of the quad add into the same entry) are summed across the quad and added by its first
+// lane, and every lane of the quad must call it; otherwise (and for unshared entries) every
+// live lane adds its own value.
+template <bool QUADS, typename T, typename TACC>
+__device__ __forceinline__ void quad_add(TACC* p, T v, bool live, bool shared, bool lead) {
+    if (QUADS) {
+        const T s = quad_sum(live ? v : T(0));
+        if (shared ? lead : live) atomic_add(p, TACC(shared ? s : v));
+    } else if (live) {
+        atomic_add(p, TACC(v));
+    }
+}
+
+// One item's four condensed blocks added to the staged rows.  Block 0 (the row's diagonal
+// block) is shared by the four items of a quad, block 1 when the quad's elements share the
+// edge to their vertex 1 (share1).
+template <bool QUADS, typename T, typename TACC>
+__device__ __forceinline__ void add_blocks(const BlockFactors<T>& F, TACC* __restrict__ blk, const uint32_t slot[4],
+                                           bool live, bool share1, bool lead) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const T* gb = F.g[b];
@@ -393,11 +420,17 @@ __device__ __forceinline__ void add_blocks(const BlockFactors<T>& F, TACC* __res
                 v += F.q[r] * gb[c];
                 v -= F.Y[r][c] * d_b;
                 if (r == c) v += s_b;
-                atomic_add(&dst[r * 4 + c], TACC(v));
+                if (b < 2)
+                    quad_add<QUADS, T, TACC>(&dst[r * 4 + c], v, live, b == 0 || share1, lead);
+                else if (live)
+                    atomic_add(&dst[r * 4 + c], TACC(v));
             }
             const T yg = F.Y[r][0] * gb[0] + F.Y[r][1] * gb[1] + F.Y[r][2] * gb[2];
             const T vp = (r < 3 ? F.pc[r] : T(0)) - F.Bm * yg;
-            atomic_add(&dst[r * 4 + 3], TACC(vp));
+            if (b < 2)
+                quad_add<QUADS, T, TACC>(&dst[r * 4 + 3], vp, live, b == 0 || share1, lead);
+            else if (live)
+                atomic_add(&dst[r * 4 + 3], TACC(vp));
         }
     }
 }
@@ -407,6 +440,8 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
     ElemArgs args, TileArgs ta, T* __restrict__ Aval, double* __restrict__ rhs, double* __restrict__ rglob,
     double* __restrict__ tile_part) {
     extern __shared__ __align__(16) unsigned char smem[];
+    // DPP quads: the one-wavefront tiles of FP32 blocks (their items come in quads of one row)
+    constexpr bool QUADS = NT == kTileThreadsDet && sizeof(T) == 4;
     const int t = blockIdx.x;
     const int4 m0 = ta.meta[2 * t], m1 = ta.meta[2 * t + 1];
     const int n0 = m0.x, nn = m0.y - m0.x, b0 = m0.z, nbk = m0.w;
@@ -458,10 +493,14 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
         // first, orientation kept -- and the owned row's block slots
         const uint4 rec = rec_next;
         if (k + (int)blockDim.x < k_end) rec_next = ta.items[k + blockDim.x];
-        const int e = (int)rec.x;
+        // with QUADS, the four items of a quad (lanes 4m .. 4m+3) share the owned row and a
+        // zero-weight copy pads a row's last quad; otherwise the two flag bits are zero
+        const int e = (int)(rec.x & 0x7fffffffu);
+        const bool dummy = (rec.x >> 31) != 0;
+        const bool share1 = (rec.w >> 31) != 0;
+        const bool lead = (threadIdx.x & 3) == 0;
         const int nl[4] = {(int)(rec.y & 255u), (int)((rec.y >> 8) & 255u), (int)((rec.y >> 16) & 255u),
                            (int)(rec.y >> 24)};
-        const bool first = (rec.z & 0x8000u) != 0;     // the element's vertex 0 (R_f counted once)
         // geometry
         double X[4][3];
 #pragma unroll
@@ -480,11 +519,12 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
         const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
         const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
         const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-        if (!(det > 0.0)) {
-            atomicMin(&args.flags[0], e);
-            continue;
-        }
-        const double id = 1.0 / det;
+        // a degenerate element is flagged and contributes nothing (its lane stays in its quad)
+        const bool degenerate = !(det > 0.0);
+        if (degenerate) atomicMin(&args.flags[0], e);
+        const bool live = !dummy && !degenerate;
+        const bool first = live && (rec.z & 0x8000u) != 0;   // the element's vertex 0 (R_f counted once)
+        const double id = degenerate ? 0.0 : 1.0 / det;
         double g[4][3];
         g[1][0] = c00 * id;
         g[1][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
@@ -569,7 +609,7 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
         Rc[3] = -th * vol * 0.25 + Bm * bg0;
         const int la = nl[0];                           // owned nodes come first in the local numbering
 #pragma unroll
-        for (int r = 0; r < 4; ++r) atomic_add(&rg[4 * la + r], Rc[r]);
+        for (int r = 0; r < 4; ++r) quad_add<QUADS, double, double>(&rg[4 * la + r], Rc[r], live, true, lead);
         if (!CONDENSE) continue;
 
         // Y = K_cf(0) K_ff^-1 (FP64, stored in T) and R*_0; zero without condensation
@@ -588,7 +628,7 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
             double knrm = 0.0;
 #pragma unroll
             for (int i = 0; i < 3; ++i) knrm = fmax(knrm, fabs(Kff[i][0]) + fabs(Kff[i][1]) + fabs(Kff[i][2]));
-            if (!(fabs(kdet) > 1e-14 * knrm * knrm * knrm)) atomicMin(&args.flags[1], e);
+            if (live && !(fabs(kdet) > 1e-14 * knrm * knrm * knrm)) atomicMin(&args.flags[1], e);
             const double kid = 1.0 / kdet;
             double Ki[3][3];
             Ki[0][0] = k00 * kid;
@@ -616,14 +656,14 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const double rs = Rc[r] - (Kcf[r][0] * zf[0] + Kcf[r][1] * zf[1] + Kcf[r][2] * zf[2]);
-                atomic_add(&rr[4 * la + r], -rs);
+                quad_add<QUADS, double, double>(&rr[4 * la + r], -rs, live, true, lead);
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
                     Yd[r][j] = Kcf[r][0] * Ki[0][j] + Kcf[r][1] * Ki[1][j] + Kcf[r][2] * Ki[2][j];
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) atomic_add(&rr[4 * la + r], -Rc[r]);
+            for (int r = 0; r < 4; ++r) quad_add<QUADS, double, double>(&rr[4 * la + r], -Rc[r], live, true, lead);
         }
 
         // block factors in T
@@ -664,8 +704,8 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
         F.idt = T(inv_dt);
         F.B1idt = T(B1 * inv_dt);
         F.Bm = T(Bm);
-        const uint32_t slot[4] = {rec.z & 0x7fffu, rec.z >> 16, rec.w & 0xffffu, rec.w >> 16};
-        add_blocks<T, TACC>(F, blk, slot);
+        const uint32_t slot[4] = {rec.z & 0x7fffu, rec.z >> 16, rec.w & 0xffffu, (rec.w >> 16) & 0x7fffu};
+        add_blocks<QUADS, T, TACC>(F, blk, slot, live, share1, lead);
     }
     __syncthreads();
     if (CONDENSE) {
