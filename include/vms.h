@@ -171,11 +171,17 @@ typedef struct {
     double rtol;               /* success iff ||b - A x||_2 <= rtol ||b||_2 (true residual) */
     vms_pc_kind pc;
     const float* pc_weights;   /* device, VMS_PC_LEARNED only (layout in vms_pc_*)       */
-    int32_t refine_max;        /* mixed ctx: FP64 iterative-refinement sweeps (<= 0: 30) */
-    double inner_rtol;         /* mixed ctx: FP32 GMRES tolerance per sweep (<= 0: 1e-4); a
-                                  sweep also ends when a cycle's own estimate reached it but
-                                  the recomputed FP32 residual did not (the FP32 rounding
-                                  floor)                                                   */
+    int32_t refine_max;        /* mixed ctx with inner_rtol > 0: FP64 iterative-refinement
+                                  sweeps (<= 0: 30)                                        */
+    double inner_rtol;         /* mixed ctx.  <= 0 (default): every FP32 restart cycle starts
+                                  from the FP64 residual b - A x (FP32-stored A, FP64 x and
+                                  arithmetic) scaled to unit norm, and its correction is added
+                                  to the FP64 x; each cycle is one refinement sweep.
+                                  > 0: a sweep runs FP32 cycles, restarted from the FP32
+                                  residual of the FP32 correction, until that residual falls
+                                  below inner_rtol (relative to the sweep's residual), or a
+                                  cycle's own estimate reached it but the recomputed residual
+                                  did not (the FP32 rounding floor); then x is refined in FP64 */
     int32_t cgs2;              /* nonzero: every basis vector gets a second classical
                                   Gram-Schmidt pass, delayed into the next Arnoldi step so
                                   that each step needs one reduction; 0: one pass (each
@@ -197,7 +203,8 @@ typedef struct {
 typedef struct {
     int32_t iters;             /* Arnoldi steps                                          */
     int32_t restarts;          /* cycles                                                 */
-    int32_t refinements;       /* outer FP64 sweeps (mixed)                              */
+    int32_t refinements;       /* FP64 refinement sweeps (mixed; with inner_rtol <= 0 one
+                                  per cycle)                                               */
     int32_t fell_back_to_bj;   /* learned preconditioner rejected: non-finite blocks, or
                                   no convergence within half of max_iters (the solve then
                                   continues from its iterate with plain block-Jacobi)     */

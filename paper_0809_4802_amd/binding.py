@@ -243,7 +243,7 @@ def _copy_device(dst, src_ptr, nbytes):
 
 
 def solve_opts(restart=50, max_iters=100000, rtol=1e-8, pc=VMS_PC_BLOCK_JACOBI, pc_weights=None,
-               refine_max=30, inner_rtol=1e-4, cgs2=1, coarse_pressure=1, log_residuals=None):
+               refine_max=30, inner_rtol=0.0, cgs2=1, coarse_pressure=1, log_residuals=None):
     """log_residuals: device float tensor [k, n_nodes, 4] receiving restart residuals (or None)."""
     return SolveOpts(restart, max_iters, rtol, pc,
                      pc_weights.data_ptr() if pc_weights is not None else None,

@@ -1185,12 +1185,13 @@ __global__ __launch_bounds__(kBlock) void free_pressure_sum_kernel(int n_nodes, 
     }
 }
 
-// x += P t = Minv t + z kappa (1_p^T t)  (x in TX: double for the FP64 solution, float for an inner
-// correction).  z is the indicator of the free pressure dofs 1_p, or the explicit vector zvec.
+// x += xscale P t = xscale (Minv t + z kappa (1_p^T t))  (x in TX: double for the FP64 solution,
+// float for an inner correction; xscale is the norm of the residual an FP32 cycle was given
+// scaled to one).  z is the indicator of the free pressure dofs 1_p, or the explicit vector zvec.
 template <typename T, typename TX>
 __global__ void precond_accumulate_kernel(int n_nodes, const T* __restrict__ Minv, const T* __restrict__ t,
                                           const uint8_t* __restrict__ dmask, const double* __restrict__ zvec,
-                                          const GmresState* gs, TX* __restrict__ x) {
+                                          const GmresState* gs, double xscale, TX* __restrict__ x) {
     if (gs->k == 0) return;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = tid >> 2, r = tid & 3;
@@ -1204,7 +1205,7 @@ __global__ void precond_accumulate_kernel(int n_nodes, const T* __restrict__ Min
         s += gs->kappa * gs->st * zvec[4 * (size_t)node + r];
     else if (r == 3 && !(dmask[node] & 8u))
         s += gs->kappa * gs->st;
-    x[4 * (size_t)node + r] = TX(double(x[4 * (size_t)node + r]) + s);
+    x[4 * (size_t)node + r] = TX(double(x[4 * (size_t)node + r]) + xscale * s);
 }
 
 // FP64 norm of a vector of any precision into out (device) via partials.
@@ -1327,7 +1328,7 @@ int wait_progress(vms_ctx* c, uint32_t gen, int need, hipStream_t s) {
 }
 
 // Launches one GMRES(m) cycle on A d = r0 with right preconditioner Minv, adding the Krylov
-// correction Minv (V y) (+ coarse term) to x (double or float).  r0 is the cycle's initial
+// correction xscale Minv (V y) (+ coarse term) to x (double or float).  r0 is the cycle's initial
 // residual (precision T).  The host follows the device's progress through the mapped word,
 // keeps at most kLeadSteps steps queued ahead of it and stops issuing steps once the cycle has
 // converged; nothing here synchronises the stream.  finish_cycle gives the number of steps
@@ -1340,7 +1341,7 @@ inline bool cycle_graphs_enabled() {
 
 template <typename T, typename TX>
 int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int m, int budget, int cgs2,
-              hipStream_t s) {
+              hipStream_t s, double xscale = 1.0) {
     const int n = 4 * c->n_nodes;
     const T* AP = (const T*)c->AP;
     const T* Az = (const T*)c->Az;
@@ -1446,7 +1447,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     combine_kernel<T><<<xcd_round(grid_for(n)), kBlock, 0, s>>>(n, V, c->gs, z);
     free_pressure_sum_kernel<T><<<red_grid(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, z, c->dmask, c->red, c->gs);
     precond_accumulate_kernel<T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, c->dmask, c->zfull, c->gs,
-                                                                    x);
+                                                                    xscale, x);
     return check_hip(c, hipGetLastError(), "gmres cycle launch");
 }
 
@@ -1567,7 +1568,10 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     const int max_iters = o->max_iters > 0 ? o->max_iters : 100000;
     const double rtol = o->rtol > 0 ? o->rtol : 1e-8;
     const int refine_max = o->refine_max > 0 ? o->refine_max : 30;
-    const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-4;
+    // mixed ctx: inner_rtol <= 0 restarts every FP32 cycle from the FP64 residual; a positive
+    // value runs FP32 restart cycles on the FP32 residual until it falls below inner_rtol
+    const bool sweeps = o->inner_rtol > 0;
+    const double inner_rtol = o->inner_rtol;
     int rc;
     // the constant-pressure coarse mode exists only when a pressure dof is prescribed
     const int coarse_pressure = o->coarse_pressure && c->n_pressure_pins > 0;
@@ -1677,6 +1681,19 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             // one restart cycle on the FP64 residual; the true residual is recomputed above
             if ((rc = run_cycle<double, double>(c, c->r64, (const double*)c->Minv, x, tol, m, cap - iters,
                                                 o->cgs2, s)))
+                return rc;
+            pending = true;
+        } else if (!sweeps) {
+            // FP64 refinement at every restart: one FP32 cycle on A d = r / ||r|| (r = b - A x in FP64,
+            // A the FP32-stored matrix), its correction added to the FP64 x as ||r|| P V y.  Every
+            // cycle thus starts from a residual that is exact to FP32 rounding of a unit vector; a
+            // residual recomputed in FP32 from an FP32 correction carries an error near
+            // eps32 |A| |d|, which on hard systems the following cycles spend their steps on.
+            inf.refinements++;
+            float* rr = (float*)c->r;
+            convert_kernel<double, float><<<grid_for(n), kBlock, 0, s>>>(n, c->r64, rr, 1.0 / rn);
+            if ((rc = run_cycle<float, double>(c, rr, (const float*)c->Minv, x, tol / rn, m, cap - iters, o->cgs2,
+                                               s, rn)))
                 return rc;
             pending = true;
         } else {

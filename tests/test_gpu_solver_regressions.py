@@ -9,6 +9,7 @@
 * Deliberately bad learned weights (Delta = -e_0 e_0^T on every node: P_i drops each node's
   first component, so A P is singular) on a mixed context: the solver must give up the learned
   blocks after half of max_iters and converge with block-Jacobi within max_iters.
+* The two refinement modes of the mixed solve reach the FP64 tolerance.
 * A zero diagonal block: the preconditioner setup counts it (vms_solve_info.singular_blocks).
 * NaN in the state: vms_newton_step returns VMS_ENONFINITE.
 """
@@ -17,7 +18,7 @@ import pytest
 import torch
 
 from workloads import cavity_mesh, cavity_bc, apply_dirichlet, build_workload
-from tests.gpu_common import DEV, make_context, to_dev
+from tests.gpu_common import DEV, bsr_to_csr, make_context, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +86,29 @@ def test_bad_learned_weights_fall_back_in_mixed_precision(vms_lib):
     x2 = ctx.new_vec()
     _, info2 = B.vms_gmres_solve(ctx, A, rhs, x2, B.solve_opts(restart=50, rtol=1e-8, max_iters=4000))
     assert info.iters <= 2000 + 2 * info2.iters + 100
+
+
+@pytest.mark.parametrize("inner_rtol", [0.0, 1e-4, 0.1])
+def test_mixed_refinement_modes(vms_lib, inner_rtol):
+    """Mixed GMRES with every cycle restarted from the FP64 residual (inner_rtol 0) and with
+    FP32 sweeps to a tolerance: both reach rtol by the FP64 residual of the FP32-stored matrix
+    (computed here on the host); per-cycle refinement counts one sweep per cycle."""
+    B = vms_lib
+    ctx, A, rhs = _cavity8_system(B, B.VMS_MIXED)
+    x = ctx.new_vec()
+    rc, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=30, rtol=1e-10, max_iters=20000,
+                                                              inner_rtol=inner_rtol, refine_max=1000))
+    Am = bsr_to_csr(ctx, A)                  # the FP32-stored matrix, exactly, in FP64
+    xs = x.cpu().numpy().ravel()
+    bs = rhs.cpu().numpy().ravel()
+    rel = np.linalg.norm(bs - Am @ xs) / np.linalg.norm(bs)
+    print(f"inner_rtol {inner_rtol}: iters {info.iters}, cycles {info.restarts}, sweeps {info.refinements}, "
+          f"residual {rel:.2e}")
+    assert rc == B.VMS_OK and rel <= 1.01e-10 and info.true_rel_res <= 1e-10
+    if inner_rtol == 0.0:
+        assert info.refinements == info.restarts
+    else:
+        assert 1 <= info.refinements <= info.restarts
 
 
 def test_singular_diagonal_block_is_reported(vms_lib):
