@@ -1,0 +1,35 @@
+"""Checkpoint selection of the learned correction (host logic, not gpu): the GMRES iteration
+counts and the training step are replaced by scripted stand-ins, so only the rule is tested."""
+import torch
+
+from paper_0809_4802_amd import binding as B
+from paper_0809_4802_amd import learned
+
+
+class _Ctx:
+    device = "cpu"
+
+
+def _select(monkeypatch, scores, **kw):
+    it = iter(scores)
+    monkeypatch.setattr(learned, "gmres_iterations", lambda ctx, A, b, w, **k: next(it))
+    monkeypatch.setattr(B, "vms_pc_train_step", lambda *a, **k: None)
+    data = [(None, torch.zeros((4, 3, 4)))]
+    return learned.train_validated(_Ctx(), data, [(None, None)], steps=len(scores) - 1, check_every=1, **kw)
+
+
+def test_a_checkpoint_must_save_a_tenth(monkeypatch):
+    # block-Jacobi 1000; checkpoints 950, 880, 960: 880 is the first to save 10%
+    w, rep = _select(monkeypatch, [1000, 950, 880, 960])
+    assert rep["selected"] == "learned" and rep["val_iters_selected"] == 880 and w is not None
+    assert [c["val_iters"] for c in rep["checkpoints"]] == [950, 880, 960]
+
+
+def test_small_gains_keep_block_jacobi(monkeypatch):
+    w, rep = _select(monkeypatch, [1000, 950, 920, 901])
+    assert rep["selected"] == "bj" and rep["val_iters_selected"] == 1000 and w is None
+
+
+def test_min_gain_zero_takes_any_improvement(monkeypatch):
+    w, rep = _select(monkeypatch, [1000, 999, 1200], min_gain=0.0)
+    assert rep["selected"] == "learned" and rep["val_iters_selected"] == 999
