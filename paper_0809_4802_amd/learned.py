@@ -96,13 +96,13 @@ def gmres_iterations(ctx: B.Context, A, b, weights, rtol=1e-4, max_iters=20000, 
 
 
 def train_validated(ctx: B.Context, data, val, steps=200, lr=3e-4, batch=8, seed=1, check_every=20,
-                    val_rtol=1e-4, val_restart=50, val_max_iters=20000, min_gain=0.1):
+                    val_rtol=1e-4, val_restart=50, val_max_iters=20000, min_gain=0.2):
     """Trains on `data` and keeps the checkpoint with the fewest GMRES iterations on the
     held-out systems `val` (list of (bsr_vals, rhs)); plain block-Jacobi (the zero output
     layer) is one of the candidates, so the result is never worse on the validation set.
     A checkpoint replaces block-Jacobi only if it saves at least min_gain of its validation
-    iterations: restarted GMRES counts scatter by several percent under small perturbations
-    of the operator, so a smaller gain is not evidence that the correction helps.
+    iterations: restarted GMRES counts scatter widely under small perturbations of the
+    operator, so a smaller gain is not evidence that the correction helps.
     Returns (weights or None for block-Jacobi, report)."""
     def score(w, cap=val_max_iters):
         return sum(gmres_iterations(ctx, A, b, w, rtol=val_rtol, max_iters=cap, restart=val_restart) for A, b in val)
