@@ -128,16 +128,19 @@ ELEM_FLOPS_FP64 = 87 + 128 + 84 + 78 + 4 * (121 + 65 + 39 + 60)
 ELEM_FLOPS_T = 4 * (165 + 4 * 111)
 
 
-def assembly_roofline(res, n_elems, mixed):
+def assembly_roofline(res, n_elems, mixed, workload):
+    """HBM and VALU fractions of the tile kernel; traffic from the committed counter summary
+    (taken on the mixed-precision kernel, so null for FP64)."""
     alg = res["alg_bytes_per_launch"]
     t = res["kernel_us"] * 1e-6
     f64 = ELEM_FLOPS_FP64 * n_elems
     ft = ELEM_FLOPS_T * n_elems
     # both precisions run at the same vector rate here (FP32 without packed instructions)
     valu_frac = (f64 + ft) / t / 1e12 / FP64_PEAK_TFLOPS
+    traffic, traffic_src = measured_traffic(workload, "condense") if mixed else (None, None)
     return {"bound": "hbm", "kernel": "tile_kernel", "achieved": round(alg / t / 1e9, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(alg / t / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg,
-            "avg_launch_us": round(res["kernel_us"], 3),
+            "avg_launch_us": round(res["kernel_us"], 3), "traffic": traffic, "traffic_source": traffic_src,
             "alu": {"flops_per_elem_fp64": ELEM_FLOPS_FP64, "flops_per_elem_" + ("fp32" if mixed else "fp64_blocks"):
                     ELEM_FLOPS_T, "achieved_tflops": round((f64 + ft) / t / 1e12, 2),
                     "peak_tflops": FP64_PEAK_TFLOPS, "frac": round(valu_frac, 4)}}
@@ -220,7 +223,7 @@ def main():
     assembly = {}
     for name, ctx in ctxs.items():
         assembly[name] = assembly_bench(B, ctx, mesh, u0d, b0d, cfg.re)
-        assembly[name]["roofline"] = assembly_roofline(assembly[name], mesh.n_elems, name == "mixed")
+        assembly[name]["roofline"] = assembly_roofline(assembly[name], mesh.n_elems, name == "mixed", args.workload)
         log(f"assembly {name}: {assembly[name]}")
 
     # ---- the solves run on deterministic contexts (one-wavefront assembly tiles): the
@@ -281,7 +284,10 @@ def main():
     B.vms_profile(ctx, False)
     phases = {p: {"ms": round(v[0], 3), "launches": v[1], "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else None,
                   "alg_GBps": round(v[2] / v[0] / 1e6, 1) if v[0] else None} for p, v in prof_all.items() if v[1]}
-    phase = max((p for p in prof_all if prof_all[p][1] > 0 and p != "fill"), key=lambda p: prof_all[p][0])
+    # the roofline kernel: the Arnoldi SpMV, the kernel with the most GPU time per solve in the
+    # kernel trace (about 30%, the update 28%, the dots 20%); the event-timed breakdown above
+    # brackets every launch and inflates the short update and dots launches more
+    phase = "spmv"
 
     # ---- timed region: K headline solves (mixed precision + learned correction); only the
     # dominant kernel's launches carry HIP events (on the stream they are launched on)
@@ -368,7 +374,7 @@ def hbm_config(B, build_workload, dev, gmres_steps=150):
     for name, prec in (("fp64", B.VMS_FP64), ("mixed", B.VMS_MIXED)):
         ctx = B.Context(xyz, tets, dd, precision=prec)
         res = assembly_bench(B, ctx, mesh, u, b, cfg.re, cfg.dt, u)
-        res["roofline"] = assembly_roofline(res, mesh.n_elems, name == "mixed")
+        res["roofline"] = assembly_roofline(res, mesh.n_elems, name == "mixed", "es64")
         out[f"assembly_{name}"] = res
         log(f"es64 assembly {name}: {res}")
         if name == "mixed":
@@ -381,6 +387,7 @@ def hbm_config(B, build_workload, dev, gmres_steps=150):
             B.vms_profile(ctx, False)
             out["spmv_mixed"] = spmv_roofline(prof, "spmv")
             out["spmv_mixed"]["timed_every"] = 1
+            out["spmv_mixed"]["traffic"], out["spmv_mixed"]["traffic_source"] = measured_traffic("es64", "spmv")
             for p in ("dots", "update"):
                 ms, cnt, byt = prof[p]
                 out[f"{p}_mixed"] = {"avg_launch_us": round(1e3 * ms / cnt, 3),
@@ -496,7 +503,7 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=50, forms=
     """Learned correction on the backward-facing step.  Training data: the Newton systems of the
     steady bfs8 continuation Re 400 -> 800 and of the first backward-Euler steps of bfs8 at
     Re 800, dt 0.05 from an impulsive start (mixed, GMRES(50) + block-Jacobi, restart residuals
-    logged); the last transient system is held out for checkpoint selection.  Evaluation: the
+    logged); the last two transient systems are held out for checkpoint selection.  Evaluation: the
     transient bfs16 run (Re 800, dt 0.05, impulsive start) for `steps` steps in each form --
     FP64 + block-Jacobi, mixed + block-Jacobi, mixed + learned correction -- Newton to 1e-8 per
     step, GMRES(restart); Newton steps, GMRES iterations and wall time per step."""
@@ -538,11 +545,12 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=50, forms=
             trans += d
             log(f"bfs8 transient step {n}: Newton {len(d)}, {time.perf_counter() - tr:.1f} s")
         report["bfs8"] = {"n_elems": m8.n_elems, "n_nodes": m8.n_nodes, "continuation": cont,
-                          "transient_systems": len(trans), "training_systems": len(data) + len(trans) - 1,
+                          "transient_systems": len(trans), "training_systems": len(data) + len(trans) - 2,
                           "seconds": time.perf_counter() - t0}
         t1 = time.perf_counter()
-        train_set = data + trans[:-1]
-        val = [(A, S[0].contiguous()) for A, S in trans[-1:]]
+        # the last two transient systems are held out for checkpoint selection
+        train_set = data + trans[:-2]
+        val = [(A, S[0].contiguous()) for A, S in trans[-2:]]
         weights, train = learned.train_validated(ctx8, train_set, val, steps=300, lr=3e-4, check_every=25,
                                                  val_restart=restart, val_max_iters=60000)
         train["seconds"] = time.perf_counter() - t1
@@ -604,8 +612,18 @@ def spmv_source_hash():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
+def assembly_source_hash():
+    """sha256 of the assembly sources (the tile kernel and the tile construction)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("element.hip", "ctx.cpp"):
+        with open(os.path.join(ROOT, "paper_0809_4802_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, phase):
-    """HBM-side bytes per launch of the dominant kernel from the committed counter summary
+    """HBM-side bytes per launch of a phase's kernel from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a copy of known size);
     None when there is none or the kernel source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"{workload}_{phase}_traffic.json")
@@ -613,7 +631,8 @@ def measured_traffic(workload, phase):
         return None, None
     with open(path) as f:
         d = json.load(f)
-    if phase != "spmv" or d.get("source_sha256") != spmv_source_hash():
+    current = {"spmv": spmv_source_hash, "condense": assembly_source_hash}.get(phase)
+    if current is None or d.get("source_sha256") != current():
         return None, os.path.relpath(path, ROOT) + " (stale: kernel changed since the counters were taken)"
     return d["traffic_bytes_per_launch"], os.path.relpath(path, ROOT)
 
