@@ -421,9 +421,9 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     const size_t acc_size = c->prec == VMS_FP64 ? sizeof(double) : kMixedAccSize;
     const bool det = opts && opts->deterministic;
     c->tile_threads = det ? 64 : 256;
-    // DPP quads in the one-wavefront FP32-block tiles (the FP64 kernel has no registers left
-    // for the quad sums)
-    const bool quads = det && c->prec == VMS_MIXED;
+    // DPP quads in the FP32-block tiles (the FP64 kernel has no registers left for the quad
+    // exchanges)
+    const bool quads = c->prec == VMS_MIXED;
     int64_t max_blocks = det ? kTileBlocksDet : acc_size == sizeof(double) ? kTileBlocksFP64 : kTileBlocksFP32;
     if (det) {
         // a one-wavefront tile still holds the longest row of the pattern
@@ -484,14 +484,15 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
             for (int64_t i = r0; i < r1; ++i) tnodes.push_back((int32_t)i);
             tnodes.insert(tnodes.end(), halo.begin(), halo.end());
             const int64_t ntn = (r1 - r0) + (int64_t)halo.size();
-            // Deterministic mixed-precision tiles take their items in quads: four consecutive items
-            // (the four lanes of a DPP quad) belong to one owned row, so the kernel sums their
-            // diagonal block and residual rows across the quad and lets one lane do the LDS
-            // additions (in a one-wavefront tile, a wavefront holds many items of each row).  A row's elements are grouped greedily
-            // by a shared edge (i, j) where four of them still share one; such a quad puts j at
-            // local position 1 in all four items and sums that block too.  A row's last quad is
-            // padded with zero-weight copies.  Quads go round-robin over the owned rows (the
-            // r-th quad of every row, then the (r+1)-th), so that the lanes of a wavefront mostly
+            // Mixed-precision tiles take their items in quads: four consecutive items (the four
+            // lanes of a DPP quad) belong to one owned row, so the kernel reduce-scatters their
+            // diagonal block and residual rows over the quad and each lane adds a quarter of
+            // them.  A row's elements are grouped greedily by a shared edge (i, j) where four of
+            // them still share one; such a quad puts j at local position 1 in all four items and
+            // shares that block too.  A row's last quad is padded with zero-weight copies.  The
+            // quads that share an edge come first, then the others, so that few wavefronts hold
+            // both kinds; within each kind they go round-robin over the owned rows (the r-th
+            // quad of every row, then the (r+1)-th), so that the quads of a wavefront mostly
             // add into different rows.
             // Without quads (quads == false) every quad holds one item: the items of the owned rows
             // go round-robin (the r-th element of every owned row, then the (r+1)-th, ...).
@@ -542,46 +543,56 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
                 rounds = std::max(rounds, (int32_t)qs.size());
             }
             const int32_t b0 = rowptr[r0];
-            for (int32_t r = 0; r < rounds; ++r)
-                for (int64_t i = r0; i < r1; ++i) {
-                    const auto& qs = row_quads[i - r0];
-                    if (r >= (int32_t)qs.size()) continue;
-                    const Quad& q = qs[r];
-                    for (int m = 0; m < (quads ? 4 : 1); ++m) {
-                        const bool dummy = m >= q.n;
-                        const int32_t e = q.e[dummy ? 0 : m];
-                        const int32_t* t = &tets[4 * (int64_t)e];
-                        int a = 0;
-                        while (t[a] != i) ++a;
-                        // vertex order: the owned vertex a first, then j (when the quad shares it),
-                        // then the others, as an even permutation of (0, 1, 2, 3)
-                        int ord[4] = {a, a ^ 1, a ^ 2, a ^ 3};
-                        if (q.j >= 0) {
-                            int pj = 1;
-                            while (t[ord[pj]] != q.j) ++pj;
-                            if (pj != 1) {
-                                // rotate positions 1..3 (an even permutation) until j is at 1
-                                while (t[ord[1]] != q.j) {
-                                    const int x = ord[1];
-                                    ord[1] = ord[2];
-                                    ord[2] = ord[3];
-                                    ord[3] = x;
+            for (int kind = 0; kind < 2; ++kind) {
+                for (int32_t r = 0; r < rounds; ++r)
+                    for (int64_t i = r0; i < r1; ++i) {
+                        // kind 0: the r-th quad of row i that shares an edge; kind 1: the r-th other one
+                        const auto& qs = row_quads[i - r0];
+                        int32_t seen = -1;
+                        const Quad* qp = nullptr;
+                        for (const Quad& cand : qs)
+                            if ((cand.j >= 0) == (kind == 0) && ++seen == r) {
+                                qp = &cand;
+                                break;
+                            }
+                        if (!qp) continue;
+                        const Quad& q = *qp;
+                        for (int m = 0; m < (quads ? 4 : 1); ++m) {
+                            const bool dummy = m >= q.n;
+                            const int32_t e = q.e[dummy ? 0 : m];
+                            const int32_t* t = &tets[4 * (int64_t)e];
+                            int a = 0;
+                            while (t[a] != i) ++a;
+                            // vertex order: the owned vertex a first, then j (when the quad shares it),
+                            // then the others, as an even permutation of (0, 1, 2, 3)
+                            int ord[4] = {a, a ^ 1, a ^ 2, a ^ 3};
+                            if (q.j >= 0) {
+                                int pj = 1;
+                                while (t[ord[pj]] != q.j) ++pj;
+                                if (pj != 1) {
+                                    // rotate positions 1..3 (an even permutation) until j is at 1
+                                    while (t[ord[1]] != q.j) {
+                                        const int x = ord[1];
+                                        ord[1] = ord[2];
+                                        ord[2] = ord[3];
+                                        ord[3] = x;
+                                    }
                                 }
                             }
+                            uint32_t pslot[4], l = 0;
+                            for (int b = 0; b < 4; ++b) {
+                                pslot[b] = (uint32_t)(find((int32_t)i, t[ord[b]]) - b0);
+                                l |= (uint32_t)loc[t[ord[b]]] << (8 * b);
+                            }
+                            // x: element (bit 31: zero-weight copy); y: local node numbers; z: slots
+                            // 0, 1 (bit 15: the element's vertex 0, counted once in the norm); w:
+                            // slots 2, 3 (bit 31: the quad shares slot 1)
+                            items.push_back(make_uint4((uint32_t)e | (dummy ? 0x80000000u : 0u), l,
+                                                       pslot[0] | ((a == 0 && !dummy) ? 0x8000u : 0u) | (pslot[1] << 16),
+                                                       pslot[2] | (pslot[3] << 16) | (q.j >= 0 ? 0x80000000u : 0u)));
                         }
-                        uint32_t pslot[4], l = 0;
-                        for (int b = 0; b < 4; ++b) {
-                            pslot[b] = (uint32_t)(find((int32_t)i, t[ord[b]]) - b0);
-                            l |= (uint32_t)loc[t[ord[b]]] << (8 * b);
-                        }
-                        // x: element (bit 31: zero-weight copy); y: local node numbers; z: slots
-                        // 0, 1 (bit 15: the element's vertex 0, counted once in the norm); w:
-                        // slots 2, 3 (bit 31: the quad shares slot 1)
-                        items.push_back(make_uint4((uint32_t)e | (dummy ? 0x80000000u : 0u), l,
-                                                   pslot[0] | ((a == 0 && !dummy) ? 0x8000u : 0u) | (pslot[1] << 16),
-                                                   pslot[2] | (pslot[3] << 16) | (q.j >= 0 ? 0x80000000u : 0u)));
                     }
-                }
+            }
             tnode0.push_back((int32_t)r1);
             tiptr.push_back((int32_t)items.size());
             tnptr.push_back((int32_t)tnodes.size());

@@ -374,36 +374,89 @@ struct BlockFactors {
     T m0, idt, B1idt, Bm;
 };
 
-// Sum over the four lanes of a DPP quad (all four active; every lane gets the sum).
-__device__ __forceinline__ float quad_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+// DPP lane moves inside a quad (all four lanes active): lane ^ 1 and lane ^ 2.
+template <int CTRL>
+__device__ __forceinline__ float quad_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
-__device__ __forceinline__ double quad_sum(double v) {
-    v += dpp_mov<0xB1>(v);
-    return v + dpp_mov<0x4E>(v);
+template <int CTRL>
+__device__ __forceinline__ double quad_mov(double v) {
+    return dpp_mov<CTRL>(v);
 }
 
-// Adds one value of an item to the staged rows.  With QUADS, quad-shared entries (the four
-// lanes of the quad add into the same entry) are summed across the quad and added by its first
-// lane, and every lane of the quad must call it; otherwise (and for unshared entries) every
-// live lane adds its own value.
-template <bool QUADS, typename T, typename TACC>
-__device__ __forceinline__ void quad_add(TACC* p, T v, bool live, bool shared, bool lead) {
-    if (QUADS) {
-        const T s = quad_sum(live ? v : T(0));
-        if (shared ? lead : live) atomic_add(p, TACC(shared ? s : v));
-    } else if (live) {
-        atomic_add(p, TACC(v));
+// Reduce-scatter over the four lanes of a DPP quad of N values held as 4 rows of N/4: lane q
+// receives in out the quad's sums of row 2 (q & 1) + (q >> 1).  Two exchange rounds, each
+// lane sending the half it does not keep; every sum forms in the same order on every run.
+template <int N, typename T>
+__device__ __forceinline__ void quad_reduce_scatter(const T (&v)[N], T (&out)[N / 4], bool x1, bool x2) {
+    constexpr int H = N / 2, Q = N / 4;
+    T s[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const T send = x1 ? v[i] : v[H + i];
+        const T keep = x1 ? v[H + i] : v[i];
+        s[i] = keep + quad_mov<0xB1>(send);      // quad_perm [1,0,3,2]: lane ^ 1
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T send = x2 ? s[i] : s[Q + i];
+        const T keep = x2 ? s[Q + i] : s[i];
+        out[i] = keep + quad_mov<0x4E>(send);    // quad_perm [2,3,0,1]: lane ^ 2
     }
 }
 
-// One item's four condensed blocks added to the staged rows.  Block 0 (the row's diagonal
-// block) is shared by the four items of a quad, block 1 when the quad's elements share the
-// edge to their vertex 1 (share1).
+// The lane of a quad and the row of a 4 x k array its reduce-scatter share holds.
+struct QuadLane {
+    bool x1, x2;
+    int row;
+};
+__device__ __forceinline__ QuadLane quad_lane() {
+    const int q = (int)threadIdx.x & 3;
+    return QuadLane{(q & 1) != 0, (q & 2) != 0, 2 * (q & 1) + (q >> 1)};
+}
+
+// Adds a 4-vector of an item (the owned row's residual entries) to rows[0..3].  With QUADS the
+// four lanes of the quad share the owned row: the vector is reduce-scattered over the quad and
+// each lane adds one entry (every lane of the quad must call it).
+template <bool QUADS>
+__device__ __forceinline__ void add_row4(double* rows, const double (&v)[4], bool live, const QuadLane& ql) {
+    if (QUADS) {
+        double z[4], o[1];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[r] = live ? v[r] : 0.0;
+        quad_reduce_scatter<4>(z, o, ql.x1, ql.x2);
+        atomic_add(&rows[ql.row], o[0]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (live) atomic_add(&rows[r], v[r]);
+    }
+}
+
+// Entry (r, c) of condensed block b of one item (c = 3: the pressure column); gb = g_b and the
+// block's scalars m_0b, s_b, d_b as in BlockFactors.
+template <typename T>
+__device__ __forceinline__ T block_entry(const BlockFactors<T>& F, const T* gb, T mab, T s_b, T d_b, int r, int c) {
+    if (c < 3) {
+        T x = F.P[r][c];
+        if (r < 3) x += mab * F.Gt[r][c];
+        x += F.q[r] * gb[c];
+        x -= F.Y[r][c] * d_b;
+        if (r == c) x += s_b;
+        return x;
+    }
+    const T yg = F.Y[r][0] * gb[0] + F.Y[r][1] * gb[1] + F.Y[r][2] * gb[2];
+    return (r < 3 ? F.pc[r] : T(0)) - F.Bm * yg;
+}
+
+// One item's four condensed blocks added to the staged rows.  With QUADS, block 0 (the row's
+// diagonal block) is shared by the four items of a quad, and block 1 when the quad's elements
+// share the edge to their vertex 1 (share1, the same for the four lanes): such a block is
+// reduce-scattered over the quad, two columns at a time, and each lane adds one row of it --
+// 4 LDS additions instead of 16.  The other blocks are added entry by entry by every live lane.
 template <bool QUADS, typename T, typename TACC>
 __device__ __forceinline__ void add_blocks(const BlockFactors<T>& F, TACC* __restrict__ blk, const uint32_t slot[4],
-                                           bool live, bool share1, bool lead) {
+                                           bool live, bool share1, const QuadLane& ql) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const T* gb = F.g[b];
@@ -411,26 +464,35 @@ __device__ __forceinline__ void add_blocks(const BlockFactors<T>& F, TACC* __res
         const T s_b = gb[0] * F.sv[0] + gb[1] * F.sv[1] + gb[2] * F.sv[2] + mab * F.idt;
         const T d_b = gb[0] * F.dv[0] + gb[1] * F.dv[1] + gb[2] * F.dv[2] + F.B1idt;
         TACC* dst = blk + (size_t)slot[b] * kLdsBlockStride;
+        if (QUADS && (b == 0 || (b == 1 && share1))) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+            for (int h = 0; h < 2; ++h) {
+                T v[8], o[2];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                T v = F.P[r][c];
-                if (r < 3) v += mab * F.Gt[r][c];
-                v += F.q[r] * gb[c];
-                v -= F.Y[r][c] * d_b;
-                if (r == c) v += s_b;
-                if (b < 2)
-                    quad_add<QUADS, T, TACC>(&dst[r * 4 + c], v, live, b == 0 || share1, lead);
-                else if (live)
-                    atomic_add(&dst[r * 4 + c], TACC(v));
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+                        v[2 * r + k] = live ? block_entry(F, gb, mab, s_b, d_b, r, 2 * h + k) : T(0);
+                quad_reduce_scatter<8>(v, o, ql.x1, ql.x2);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) atomic_add(&dst[ql.row * 4 + 2 * h + k], TACC(o[k]));
             }
-            const T yg = F.Y[r][0] * gb[0] + F.Y[r][1] * gb[1] + F.Y[r][2] * gb[2];
-            const T vp = (r < 3 ? F.pc[r] : T(0)) - F.Bm * yg;
-            if (b < 2)
-                quad_add<QUADS, T, TACC>(&dst[r * 4 + 3], vp, live, b == 0 || share1, lead);
-            else if (live)
-                atomic_add(&dst[r * 4 + 3], TACC(vp));
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    T v = F.P[r][c];
+                    if (r < 3) v += mab * F.Gt[r][c];
+                    v += F.q[r] * gb[c];
+                    v -= F.Y[r][c] * d_b;
+                    if (r == c) v += s_b;
+                    if (live) atomic_add(&dst[r * 4 + c], TACC(v));
+                }
+                const T yg = F.Y[r][0] * gb[0] + F.Y[r][1] * gb[1] + F.Y[r][2] * gb[2];
+                const T vp = (r < 3 ? F.pc[r] : T(0)) - F.Bm * yg;
+                if (live) atomic_add(&dst[r * 4 + 3], TACC(vp));
+            }
         }
     }
 }
@@ -440,8 +502,9 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
     ElemArgs args, TileArgs ta, T* __restrict__ Aval, double* __restrict__ rhs, double* __restrict__ rglob,
     double* __restrict__ tile_part) {
     extern __shared__ __align__(16) unsigned char smem[];
-    // DPP quads: the one-wavefront tiles of FP32 blocks (their items come in quads of one row)
-    constexpr bool QUADS = NT == kTileThreadsDet && sizeof(T) == 4;
+    // DPP quads: the tiles of FP32 blocks take their items in quads of one row
+    constexpr bool QUADS = sizeof(T) == 4;
+    const QuadLane ql = quad_lane();
     const int t = blockIdx.x;
     const int4 m0 = ta.meta[2 * t], m1 = ta.meta[2 * t + 1];
     const int n0 = m0.x, nn = m0.y - m0.x, b0 = m0.z, nbk = m0.w;
@@ -498,7 +561,6 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
         const int e = (int)(rec.x & 0x7fffffffu);
         const bool dummy = (rec.x >> 31) != 0;
         const bool share1 = (rec.w >> 31) != 0;
-        const bool lead = (threadIdx.x & 3) == 0;
         const int nl[4] = {(int)(rec.y & 255u), (int)((rec.y >> 8) & 255u), (int)((rec.y >> 16) & 255u),
                            (int)(rec.y >> 24)};
         // geometry
@@ -608,8 +670,13 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
                     0.25 * vol * ps * g[0][i] - m0 * (fs[i] + f0[i]) + inv_dt * m0 * (dvs[i] + dv0[i]);
         Rc[3] = -th * vol * 0.25 + Bm * bg0;
         const int la = nl[0];                           // owned nodes come first in the local numbering
+        if constexpr (QUADS) {
+            add_row4<QUADS>(&rg[4 * la], Rc, live, ql);
+        } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) quad_add<QUADS, double, double>(&rg[4 * la + r], Rc[r], live, true, lead);
+            for (int r = 0; r < 4; ++r)
+                if (live) atomic_add(&rg[4 * la + r], Rc[r]);
+        }
         if (!CONDENSE) continue;
 
         // Y = K_cf(0) K_ff^-1 (FP64, stored in T) and R*_0; zero without condensation
@@ -653,17 +720,34 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
             double zf[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) zf[i] = Ki[i][0] * Rf[0] + Ki[i][1] * Rf[1] + Ki[i][2] * Rf[2];
+            // R*_0 = R_c(0) - K_cf(0) K_ff^-1 R_f, staged negated
+            if constexpr (QUADS) {
+                double nrs[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double rs = Rc[r] - (Kcf[r][0] * zf[0] + Kcf[r][1] * zf[1] + Kcf[r][2] * zf[2]);
-                quad_add<QUADS, double, double>(&rr[4 * la + r], -rs, live, true, lead);
+                for (int r = 0; r < 4; ++r) {
+                    nrs[r] = -(Rc[r] - (Kcf[r][0] * zf[0] + Kcf[r][1] * zf[1] + Kcf[r][2] * zf[2]));
 #pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    Yd[r][j] = Kcf[r][0] * Ki[0][j] + Kcf[r][1] * Ki[1][j] + Kcf[r][2] * Ki[2][j];
+                    for (int j = 0; j < 3; ++j)
+                        Yd[r][j] = Kcf[r][0] * Ki[0][j] + Kcf[r][1] * Ki[1][j] + Kcf[r][2] * Ki[2][j];
+                }
+                add_row4<QUADS>(&rr[4 * la], nrs, live, ql);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double rs = Rc[r] - (Kcf[r][0] * zf[0] + Kcf[r][1] * zf[1] + Kcf[r][2] * zf[2]);
+                    if (live) atomic_add(&rr[4 * la + r], -rs);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        Yd[r][j] = Kcf[r][0] * Ki[0][j] + Kcf[r][1] * Ki[1][j] + Kcf[r][2] * Ki[2][j];
+                }
             }
+        } else if constexpr (QUADS) {
+            const double nrc[4] = {-Rc[0], -Rc[1], -Rc[2], -Rc[3]};
+            add_row4<QUADS>(&rr[4 * la], nrc, live, ql);
         } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) quad_add<QUADS, double, double>(&rr[4 * la + r], -Rc[r], live, true, lead);
+            for (int r = 0; r < 4; ++r)
+                if (live) atomic_add(&rr[4 * la + r], -Rc[r]);
         }
 
         // block factors in T
@@ -705,7 +789,7 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
         F.B1idt = T(B1 * inv_dt);
         F.Bm = T(Bm);
         const uint32_t slot[4] = {rec.z & 0x7fffu, rec.z >> 16, rec.w & 0xffffu, (rec.w >> 16) & 0x7fffu};
-        add_blocks<QUADS, T, TACC>(F, blk, slot, live, share1, lead);
+        add_blocks<QUADS, T, TACC>(F, blk, slot, live, share1, ql);
     }
     __syncthreads();
     if (CONDENSE) {
