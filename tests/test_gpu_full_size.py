@@ -7,6 +7,11 @@
   reach the same solution.
 * backward-facing step bfs8 (1,248,000 tets, open outlet, no pressure pin), steady Re 400 from
   rest, mixed, to 1e-8: the same sampled residual check.
+* the bfs8 continuation Re 400 -> 800 that produces the learned correction's training data
+  (mixed, GMRES(50) to 1e-4 with restart residuals logged): every Reynolds number converges,
+  every Newton system leaves its tangent and at least one logged residual (the first one is
+  the right-hand side: the solve starts from zero), and the final Re 800 state passes the
+  sampled residual check.
 """
 import numpy as np
 import pytest
@@ -65,3 +70,35 @@ def test_bfs8_steady_re400_sampled(vms_lib):
     _check_sampled_residual(m, bc.dofs, u, beta, 400.0, res.rnorms[0], 1e-8, seed=11)
     print(f"bfs8 Re 400: Newton {len(res.rnorms) - 1} steps, GMRES {sum(d['iters'] for d in res.lin)} "
           f"iterations, {res.seconds:.2f} s")
+
+
+def test_bfs8_continuation_logs_training_data(vms_lib):
+    from paper_0809_4802_amd import learned
+    B = vms_lib
+    cfg, m, u0, beta0, bc = build_workload("bfs8")
+    assert cfg.re_sweep == (400.0, 500.0, 600.0, 700.0, 800.0)
+    ctx = make_context(B, m, bc.dofs, B.VMS_MIXED)
+    u = torch.from_numpy(u0).to(DEV)
+    beta = torch.from_numpy(beta0).to(DEV)
+    lin = B.solve_opts(restart=50, rtol=1e-4, max_iters=20000)
+    systems = 0
+    for re in cfg.re_sweep:
+        A0, rhs0, _ = B.vms_condense_assemble(ctx, u, beta, re)
+        rhs0 = rhs0.float()
+        data, hist = learned.collect_newton_data(ctx, u, beta, re, tol=cfg.newton_tol, max_newton=12, lin=lin,
+                                                 per_step=32, allow_noconv=True)
+        print(f"bfs8 Re {re:g}: Newton {len(data)} steps, residuals {[f'{h:.2e}' for h in hist]}, "
+              f"logged {[int(S.shape[0]) for _, S in data]}")
+        assert hist[-1] <= cfg.newton_tol * hist[0], (re, hist)
+        assert len(data) == len(hist) - 1 >= 1
+        for A, S in data:
+            assert A.shape == (ctx.nb, 16) and A.dtype == torch.float32
+            assert S.dim() == 3 and S.shape[1:] == (m.n_nodes, 4) and 1 <= S.shape[0] <= 32
+            assert bool(torch.isfinite(S).all())
+        # the first logged residual of the first system is its right-hand side (x0 = 0)
+        assert rel_fro(data[0][1][0].cpu().numpy(), rhs0.cpu().numpy()) <= 1e-6
+        del A0, rhs0
+        systems += len(data)
+        r0_last = hist[0]
+    assert systems >= 15
+    _check_sampled_residual(m, bc.dofs, u.cpu().numpy(), beta.cpu().numpy(), 800.0, r0_last, cfg.newton_tol, seed=13)
