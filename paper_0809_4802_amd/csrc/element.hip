@@ -948,8 +948,22 @@ __global__ void update_kernel(int n_nodes, const uint8_t* __restrict__ dmask, co
 constexpr int kFinThreads = 1024;
 __global__ __launch_bounds__(kFinThreads) void norm_finalize_kernel(int n_tiles, const double* __restrict__ part,
                                                                      double* __restrict__ out) {
+    // a thread's partials are loaded eight at a time (one memory round per batch instead of a
+    // chain of dependent loads) and added in increasing index order, as before
+    constexpr int kBatch = 8;
+    const int n = 2 * n_tiles;
     double s = 0.0;
-    for (int i = threadIdx.x; i < 2 * n_tiles; i += kFinThreads) s += part[i];
+    for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * kFinThreads) {
+        double v[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int i = i0 + b * kFinThreads;
+            v[b] = part[min(i, n - 1)];
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+            if (i0 + b * kFinThreads < n) s += v[b];
+    }
     s = wave_sum(s);
     __shared__ double ws[kFinThreads / 64];
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
