@@ -12,6 +12,9 @@
   every Newton system leaves its tangent and at least one logged residual (the first one is
   the right-hand side: the solve starts from zero), and the final Re 800 state passes the
   sampled residual check.
+* the first backward-Euler step of bfs16 (2,496,000 tets, Re 800, dt 0.05, impulsive start),
+  mixed, GMRES(50) + block-Jacobi, Newton to 1e-8: the oracle's transient residual at sampled
+  interior nodes and elements of the final state.
 """
 import numpy as np
 import pytest
@@ -102,3 +105,29 @@ def test_bfs8_continuation_logs_training_data(vms_lib):
         r0_last = hist[0]
     assert systems >= 15
     _check_sampled_residual(m, bc.dofs, u.cpu().numpy(), beta.cpu().numpy(), 800.0, r0_last, cfg.newton_tol, seed=13)
+
+
+def test_bfs16_first_step_sampled(vms_lib):
+    from paper_0809_4802_amd import driver
+    B = vms_lib
+    cfg, m, u0, beta0, bc = build_workload("bfs16")
+    assert m.n_elems == 2_496_000 and cfg.re == 800.0 and cfg.dt == 0.05
+    ctx = make_context(B, m, bc.dofs, B.VMS_MIXED)
+    u = torch.from_numpy(u0).to(DEV)
+    beta = torch.from_numpy(beta0).to(DEV)
+    u_prev = u.clone()
+    driver.set_dirichlet(u, torch.from_numpy(bc.dofs.astype(np.int64)).to(DEV), torch.from_numpy(bc.values).to(DEV))
+    res = driver.newton_solve(ctx, u, beta, cfg.re, cfg.dt, u_prev, None, tol=cfg.newton_tol, forcing="ew",
+                              lin=B.solve_opts(restart=50, rtol=1e-9, max_iters=400000))
+    print(f"bfs16 step 1: Newton {len(res.rnorms) - 1} steps, GMRES {sum(d['iters'] for d in res.lin)} "
+          f"iterations, {res.seconds:.1f} s")
+    assert res.converged and len(res.rnorms) - 1 <= 8
+    rng = np.random.default_rng(17)
+    un, bn, upn = u.cpu().numpy(), beta.cpu().numpy(), u_prev.cpu().numpy()
+    interior = np.nonzero(~boundary_nodes(m.tets, m.n_nodes))[0]
+    nodes = np.sort(rng.choice(interior, size=64, replace=False))
+    elems = np.sort(rng.choice(m.n_elems, size=256, replace=False))
+    Rn, Rf = _patch_residuals(m, un, bn, 1.0 / cfg.re, cfg.dt, upn, nodes, elems)
+    r0 = res.rnorms[0]
+    assert np.abs(Rn).max() <= 1.01 * cfg.newton_tol * r0, (np.abs(Rn).max(), r0)
+    assert np.abs(Rf).max() <= 1.01 * cfg.newton_tol * r0, (np.abs(Rf).max(), r0)
