@@ -198,6 +198,17 @@ typedef struct {
                                   (refinement sweep in the mixed ctx) is copied here, as
                                   training samples for the learned preconditioner          */
     int32_t log_max;
+    int32_t deflate;           /* deflated restarting (GMRES-DR, Morgan 2002): a cycle that
+                                  follows a full one keeps the harmonic Ritz vectors of its
+                                  predecessor's `deflate` harmonic Ritz values of smallest
+                                  modulus (one more to keep a complex pair whole), restarts
+                                  from the true residual and adds restart - kept Arnoldi
+                                  steps; a cycle after one that stopped early restarts
+                                  plainly.  0 = plain restarts.  1 <= deflate <= 32 and
+                                  deflate <= restart - 2, else VMS_EINVAL; so is deflate with
+                                  inner_rtol > 0 (mixed ctx) or on the uncondensed system.
+                                  Turns cgs2 on.  The kept block's eigenproblem is solved on
+                                  the host between cycles (O(restart^3) flops).             */
 } vms_solve_opts;
 
 typedef struct {

@@ -61,7 +61,7 @@ class SolveOpts(ctypes.Structure):
                 ("pc", ctypes.c_int), ("pc_weights", ctypes.c_void_p), ("refine_max", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("cgs2", ctypes.c_int32),
                 ("coarse_pressure", ctypes.c_int32), ("log_residuals", ctypes.c_void_p),
-                ("log_max", ctypes.c_int32)]
+                ("log_max", ctypes.c_int32), ("deflate", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -243,13 +243,14 @@ def _copy_device(dst, src_ptr, nbytes):
 
 
 def solve_opts(restart=50, max_iters=100000, rtol=1e-8, pc=VMS_PC_BLOCK_JACOBI, pc_weights=None,
-               refine_max=30, inner_rtol=0.0, cgs2=1, coarse_pressure=1, log_residuals=None):
-    """log_residuals: device float tensor [k, n_nodes, 4] receiving restart residuals (or None)."""
+               refine_max=30, inner_rtol=0.0, cgs2=1, coarse_pressure=1, log_residuals=None, deflate=0):
+    """log_residuals: device float tensor [k, n_nodes, 4] receiving restart residuals (or None).
+    deflate: vectors kept by deflated restarting (0: plain restarts)."""
     return SolveOpts(restart, max_iters, rtol, pc,
                      pc_weights.data_ptr() if pc_weights is not None else None,
                      refine_max, inner_rtol, cgs2, coarse_pressure,
                      log_residuals.data_ptr() if log_residuals is not None else None,
-                     int(log_residuals.shape[0]) if log_residuals is not None else 0)
+                     int(log_residuals.shape[0]) if log_residuals is not None else 0, deflate)
 
 
 # ---- entry points (same names as the C ABI) ------------------------------------------

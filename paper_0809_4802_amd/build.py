@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvms.so")
-SOURCES = ["ctx.cpp", "element.hip", "krylov.hip", "newton.cpp", "learned_pc.hip"]
+SOURCES = ["ctx.cpp", "element.hip", "krylov.hip", "newton.cpp", "learned_pc.hip", "deflate.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -128,13 +128,16 @@ static void free_all(vms_ctx* c) {
     void* ptrs[] = {c->full_cc, c->full_epos, c->zfull, c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
                     c->tpos, c->tile_meta, c->tile_nodes, c->items, c->bmask, c->tile_part, c->A, c->rhs, c->du, c->rnorm, c->flags,
                     c->V, c->w, c->z, c->d, c->r, c->Minv, c->AP, c->Az, c->x64, c->r64, c->gs, c->red,
-                    c->feats, c->hid, c->pblk, c->gblk, c->gdel, c->tvec, c->wgrad, c->fscal};
+                    c->feats, c->hid, c->pblk, c->gblk, c->gdel, c->tvec, c->wgrad, c->fscal, c->dr_p};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto e : c->prof_ev)
         if (e) (void)hipEventDestroy(e);
     if (c->progress_host) (void)hipHostFree(c->progress_host);
+    if (c->dr_pinned) (void)hipHostFree(c->dr_pinned);
     if (c->cycle_exec) (void)hipGraphExecDestroy(c->cycle_exec);
+    for (hipGraphExec_t& e : c->dr_exec)
+        if (e) (void)hipGraphExecDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -646,6 +649,7 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->x64, N * sizeof(double), "alloc x64"));
     TRY(dev_alloc(c, &c->r64, N * sizeof(double), "alloc r64"));
     TRY(dev_alloc(c, &c->gs, sizeof(GmresState), "alloc gmres state"));
+    TRY(dev_alloc(c, &c->dr_p, sizeof(double) * kDrUpload, "alloc deflation upload"));
     TRY(dev_alloc(c, &c->red, sizeof(RedScratch), "alloc reduction scratch"));
     TRY(dev_alloc(c, &c->feats, nn * VMS_PC_NIN * sizeof(float), "alloc feats"));
     TRY(dev_alloc(c, &c->hid, nn * VMS_PC_NHID * sizeof(float), "alloc hidden"));

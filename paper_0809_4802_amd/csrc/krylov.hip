@@ -20,6 +20,7 @@
 #include <cstddef>
 #include <vector>
 
+#include "deflate.h"
 #include "vms_internal.h"
 
 namespace vms {
@@ -474,7 +475,45 @@ __global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __r
     }
 }
 
-// V[0] = r / beta
+// Deflated restarting: V[c] = sum_l P(l, c) V[l] for the kept columns c < kk (l < mv), in
+// place -- each thread owns one entry of every vector and reads all of them before it writes.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dr_basis_kernel(int n, int mv, int kk, const double* __restrict__ P,
+                                                          int ldp, T* __restrict__ V) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t N = (size_t)n;
+    double acc[kDrMax];
+#pragma unroll
+    for (int c = 0; c < kDrMax; ++c) acc[c] = 0.0;
+    for (int l = 0; l < mv; ++l) {
+        const double v = double(V[(size_t)l * N + i]);
+#pragma unroll
+        for (int c = 0; c < kDrMax; ++c)
+            if (c < kk) acc[c] += P[(size_t)c * ldp + l] * v;
+    }
+#pragma unroll
+    for (int c = 0; c < kDrMax; ++c)
+        if (c < kk) V[(size_t)c * N + i] = T(acc[c]);
+}
+
+// Deflated restarting: the kept block of H and its factors from the packed upload into the
+// cycle state (columns 0 .. kk-1 of H and R, zero below their last row), and dr_k = kk.  kk = 0
+// only switches deflation off.  One workgroup.
+__global__ __launch_bounds__(kBlock) void dr_load_kernel(int kk, const double* __restrict__ up, GmresState* gs) {
+    constexpr int ld = kMaxRestart + 1;
+    const int tid = threadIdx.x;
+    if (tid == 0) gs->dr_k = kk;
+    for (int e = tid; e < kk * ld; e += blockDim.x) {
+        const int col = e / ld, row = e % ld;
+        gs->H[e] = row <= kk ? up[kDrOffH + col * (kk + 1) + row] : 0.0;
+        gs->R[e] = row < kk ? up[kDrOffR + col * kk + row] : 0.0;
+    }
+    for (int e = tid; e < (kk + 1) * (kk + 1); e += blockDim.x) gs->dr_qt[e] = up[kDrOffQt + e];
+    for (int e = tid; e < kk; e += blockDim.x) gs->svs[e] = up[kDrOffSvs + e];
+}
+
+// V[0] = r / beta (V0 = V + j0 n for a deflated cycle)
 template <typename T>
 __global__ void cycle_v0_kernel(int n, const T* __restrict__ r, T* __restrict__ V0, const GmresState* gs) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -650,9 +689,10 @@ struct GivensCtx {
 // chain (inside a launch that streams vectors, every such access would queue behind the
 // stream); the LDS operands are fetched four at a time.
 __device__ int givens_column(int jc, const double* col, double* cl, double* sl, double gj, double* Rl,
-                             const GivensCtx& gc, GmresState* gs, int done_val) {
-    double x = col[0];
-    int i = 0;
+                             const GivensCtx& gc, GmresState* gs, int done_val, int i0 = 0, double x0 = 0.0) {
+    // i0 > 0: rows 0 .. i0-1 of the column were already rotated (Rl) and x0 is row i0
+    double x = i0 > 0 ? x0 : col[0];
+    int i = i0;
     for (; i + 4 <= jc; i += 4) {
         double c4[4], s4[4], y4[4];
 #pragma unroll
@@ -804,8 +844,15 @@ __device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
     __shared__ double cl[kMaxRestart], sl[kMaxRestart];
     __shared__ double hpart[kWaves][kMaxRestart];       // H s, per column class
     __shared__ double Rl[2][kMaxRestart + 1];           // rotated columns j-1 and j
+    __shared__ double dr_v[kDrMax + 1];                 // deflated restarting: c, then Q^T c
+    __shared__ double dr_x0;                            // row dk of a column after Q^T
     __shared__ int flags[1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // deflated restarting: columns 0 .. dk-1 of H are the kept block (rows 0 .. dk), set by the
+    // host together with their rotated form (R) and Q^T; step dk starts the Arnoldi recurrence
+    const int dk = gs->dr_k;
+    const bool dr_first = dk > 0 && j == dk;
+    auto rowmax = [&](int l) { return l < dk ? dk : l + 1; };   // last nonzero row of column l
     const int r = tid - 64;                             // row of column j (waves 1 ..)
     const bool last = in == nullptr;                    // the tail: column j-1 only
     const bool hs_on = !last && j > 1;                  // columns 0 .. j-2 take part in H s
@@ -832,7 +879,7 @@ __device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
 #pragma unroll
     for (int q = 0; q < kFirst; ++q) {
         const int l = wave + kWaves * q;
-        hv[q] = (hs_on && l <= j - 2 && lane <= l + 1) ? gs->H[(size_t)l * ld + lane] : 0.0;
+        hv[q] = (hs_on && l <= j - 2 && lane <= rowmax(l)) ? gs->H[(size_t)l * ld + lane] : 0.0;
     }
     if (done) return;                                   // uniform: written by an earlier launch
     if (tid < j) sv[tid] = reorth ? s_t : 0.0;
@@ -842,10 +889,16 @@ __device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
     }
     __syncthreads();
     if (j > 0 && tid <= j) {
-        const double h = tid < j ? hp + hprev * sv[tid] : hprev * rho;
-        Hc[tid] = h;
-        gs->H[(size_t)(j - 1) * ld + tid] = h;
+        if (dr_first) {
+            // column dk-1 is the kept block's last column: final as the host set it
+            Hc[tid] = gs->H[(size_t)(j - 1) * ld + tid];
+        } else {
+            const double h = tid < j ? hp + hprev * sv[tid] : hprev * rho;
+            Hc[tid] = h;
+            gs->H[(size_t)(j - 1) * ld + tid] = h;
+        }
     }
+    if (dr_first && tid <= dk) dr_v[tid] = gs->beta * (tid < dk ? sv[tid] : rho);
     if (hs_on) {
         double acc[2] = {0.0, 0.0};
 #pragma unroll
@@ -862,7 +915,7 @@ __device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
 #pragma unroll
                 for (int q = 0; q < kBatch; ++q) {
                     const int l = l0 + kWaves * q;
-                    hb[q] = (l <= j - 2 && i <= l + 1) ? gs->H[(size_t)l * ld + i] : 0.0;
+                    hb[q] = (l <= j - 2 && i <= rowmax(l)) ? gs->H[(size_t)l * ld + i] : 0.0;
                 }
 #pragma unroll
                 for (int q = 0; q < kBatch; ++q) {
@@ -875,11 +928,41 @@ __device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
         if (lane + 64 <= j) hpart[wave][lane + 64] = acc[1];
     }
     __syncthreads();
+    // deflated restarting: Q^T of the kept block on rows 0 .. dk -- of the cycle's right-hand
+    // side c = beta (s, rho) at step dk, of column j-1 at later steps
+    if (dk > 0 && j >= dk && !(j == dk && last)) {
+        double t = 0.0;
+        if (tid <= dk) {
+            const double* src = dr_first ? dr_v : Hc;
+            for (int l = 0; l <= dk; ++l) t += gs->dr_qt[l * (dk + 1) + tid] * src[l];
+        }
+        __syncthreads();
+        if (tid <= dk) {
+            if (dr_first) {
+                gs->dr_c[tid] = dr_v[tid];
+                if (tid < dk) gs->g[tid] = t;
+                else dr_x0 = t;
+            } else if (tid < dk) {
+                Rl[0][tid] = t;
+            } else {
+                dr_x0 = t;
+            }
+        }
+        __syncthreads();
+    }
     // wave 0: the rotation of column j-1;  waves 1 ..: column j
     if (tid == 0) {
         int st = 0;
-        if (j > 0) {
-            st = givens_column(j - 1, Hc, cl, sl, gprev, Rl[0], gc, gs, done_val);
+        if (dr_first) {
+            // the kept block's residual estimate; the columns 0 .. dk-1 are done
+            gs->gin[dk] = dr_x0;
+            gs->k = dk;
+            st = (fabs(dr_x0) <= gc.tol_abs || !(rho > 0.0) || !isfinite(dr_x0)) ? 1 : 0;
+            if (st) gs->done = done_val;
+            report_progress(gc.progress, gc.gen, dk, st);
+        } else if (j > 0) {
+            st = dk > 0 ? givens_column(j - 1, Hc, cl, sl, gprev, Rl[0], gc, gs, done_val, dk, dr_x0)
+                        : givens_column(j - 1, Hc, cl, sl, gprev, Rl[0], gc, gs, done_val);
             if (!(rho > 0.0)) {
                 st = 1;                      // u_j vanished: column j-1 closes the cycle
                 gs->done = done_val;
@@ -902,12 +985,23 @@ __device__ void arnoldi_columns(int j, GmresState* gs, const StepIn* in) {
         if (r == j) gs->H[(size_t)j * ld + j + 1] = hh;
     }
     __syncthreads();
-    if (j > 0 && tid < j) gs->R[(size_t)(j - 1) * ld + tid] = Rl[0][tid];
+    if (j > 0 && tid < j && !dr_first) gs->R[(size_t)(j - 1) * ld + tid] = Rl[0][tid];
     if (!(col_on && !flags[0] && !(hh > 0.0))) return;  // uniform
     // the Krylov space is invariant: column j is final with a zero subdiagonal
+    if (dk > 0) {                                       // Q^T of the kept block on its rows 0 .. dk
+        double t = 0.0;
+        if (tid <= dk)
+            for (int l = 0; l <= dk; ++l) t += gs->dr_qt[l * (dk + 1) + tid] * colj[l];
+        __syncthreads();
+        if (tid < dk) Rl[1][tid] = t;
+        if (tid == dk) dr_x0 = t;
+        __syncthreads();
+    }
     if (tid == 0) {
         colj[j + 1] = 0.0;
-        givens_column(j, colj, cl, sl, gs->gin[j], Rl[1], gc, gs, done_val);
+        const double gj = gs->gin[j];
+        if (dk > 0) givens_column(j, colj, cl, sl, gj, Rl[1], gc, gs, done_val, dk, dr_x0);
+        else givens_column(j, colj, cl, sl, gj, Rl[1], gc, gs, done_val);
         gs->done = done_val;
         report_progress(gc.progress, gc.gen, j + 1, 1);
     }
@@ -1341,7 +1435,7 @@ inline bool cycle_graphs_enabled() {
 
 template <typename T, typename TX>
 int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int m, int budget, int cgs2,
-              hipStream_t s, double xscale = 1.0) {
+              hipStream_t s, double xscale = 1.0, int j0 = 0) {
     const int n = 4 * c->n_nodes;
     const T* AP = (const T*)c->AP;
     const T* Az = (const T*)c->Az;
@@ -1351,8 +1445,9 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     const uint32_t gen = ++c->cycle_gen;
     c->cycle_timed.clear();
     cycle_start_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, r0, c->dmask, c->red, c->gs, tol_abs, cgs2, gen);
-    cycle_v0_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, r0, V, c->gs);
-    const int steps = std::min(m, budget);
+    // a deflated cycle puts the residual after the kept vectors and runs steps j0 .. m-1
+    cycle_v0_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, r0, V + (size_t)j0 * n, c->gs);
+    const int steps = std::min(m - j0, budget);
     const double vb = (double)n * sizeof(T);      // bytes of one Krylov vector
     // algorithmic bytes of the Arnoldi SpMV: blocks and column indices, row pointers, the input
     // and output vectors once (the coarse-pressure vector A z it also reads is not credited)
@@ -1377,8 +1472,9 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     // the Arnoldi steps and the tail on stream st; with lead, the host keeps at most kLeadSteps
     // steps queued ahead of the device and stops issuing once the cycle has converged
     auto issue = [&](int steps_, bool lead, hipStream_t st) -> int {
-        for (int j = 0; j < steps_; ++j) {
-            if (lead && j >= kLeadSteps) {
+        steps_ += j0;                                     // the last column index
+        for (int j = j0; j < steps_; ++j) {
+            if (lead && j - j0 >= kLeadSteps) {
                 const int sw = wait_progress(c, gen, j - kLeadSteps, st);
                 if (sw < 0) return VMS_EHIP;
                 if (sw == 1) break;
@@ -1406,9 +1502,47 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     };
     // With the phase timers on, every prof_every-th cycle is launched directly and every launch
     // of a timed phase in it is timed (events cannot time launches inside a graph).
-    const bool graphs = steps == m && cycle_graphs_enabled();
+    const bool graphs = steps == m - j0 && cycle_graphs_enabled();
     const bool sampled = c->prof_mask != 0 && c->prof_cycles++ % c->prof_every == 0;
-    if (graphs && !sampled) {
+    if (graphs && !sampled && j0 > 0) {
+        // a full deflated cycle: one recorded graph per (m, j0), kept in a small cache
+        const int key = m * 256 + j0;
+        int slot = -1;
+        for (int q = 0; q < 4; ++q)
+            if (c->dr_exec[q] && c->dr_exec_key[q] == key) slot = q;
+        if (slot < 0) {
+            slot = 0;
+            for (int q = 0; q < 4; ++q)
+                if (!c->dr_exec[q]) {
+                    slot = q;
+                    break;
+                }
+            int rc = VMS_OK;
+            if (!c->cap_stream &&
+                (rc = check_hip(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream")))
+                return rc;
+            if (c->dr_exec[slot]) {
+                (void)hipGraphExecDestroy(c->dr_exec[slot]);
+                c->dr_exec[slot] = nullptr;
+            }
+            if ((rc = check_hip(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
+                                "begin capture")))
+                return rc;
+            const uint32_t mask = c->prof_mask;
+            c->prof_mask = 0;
+            rc = issue(m - j0, false, c->cap_stream);
+            c->prof_mask = mask;
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+            if (rc) return rc;
+            if ((rc = check_hip(c, e, "end capture"))) return rc;
+            rc = check_hip(c, hipGraphInstantiate(&c->dr_exec[slot], g, nullptr, nullptr, 0), "graph instantiate");
+            (void)hipGraphDestroy(g);
+            if (rc) return rc;
+            c->dr_exec_key[slot] = key;
+        }
+        if (int rc = check_hip(c, hipGraphLaunch(c->dr_exec[slot], s), "graph launch")) return rc;
+    } else if (graphs && !sampled) {
         // a full cycle: replay the recorded steps (the kernels after convergence return at once)
         if (!c->cycle_exec || c->cycle_exec_m != m) {
             int rc = VMS_OK;
@@ -1462,6 +1596,83 @@ int finish_cycle(vms_ctx* c, int* stopped = nullptr) {
         if (c->cycle_timed[i] >= k) prof_void(c, (int)c->cycle_timed[i + 1], c->cycle_timed[i + 2]);
     c->cycle_timed.clear();
     return k;
+}
+
+// Deflated restarting after a full cycle of m steps that kept j0 vectors of its predecessor
+// (the stream drained): the cycle's Hessenberg matrix, solution y and right-hand side give the
+// harmonic Ritz vectors to keep (dr_setup); the kept block of H, its QR factors and the
+// free-pressure sums go to the cycle state, and the basis is recombined in place.  *kk: the
+// vectors the next cycle starts with (0: a plain restart; nothing was changed).
+template <typename T>
+int dr_restart(vms_ctx* c, int m, int j0, int deflate, hipStream_t s, int* kk) {
+    constexpr int ld = kMaxRestart + 1;
+    *kk = 0;
+    constexpr size_t kGsBytes = (sizeof(GmresState) + 255) & ~size_t(255);
+    if (!c->dr_pinned) {
+        if (int rc = check_hip(c, hipHostMalloc(&c->dr_pinned, kGsBytes + sizeof(double) * kDrUpload),
+                               "alloc deflation staging"))
+            return rc;
+    }
+    GmresState* h = reinterpret_cast<GmresState*>(c->dr_pinned);
+    double* up = reinterpret_cast<double*>(reinterpret_cast<char*>(c->dr_pinned) + kGsBytes);
+    const size_t tail = offsetof(GmresState, y);
+    int rc = check_hip(c, hipMemcpyAsync(h->H, c->gs->H, sizeof(double) * (size_t)m * ld, hipMemcpyDeviceToHost, s),
+                       "read Hessenberg matrix");
+    if (!rc)
+        rc = check_hip(c, hipMemcpyAsync(reinterpret_cast<char*>(h) + tail, reinterpret_cast<char*>(c->gs) + tail,
+                                         sizeof(GmresState) - tail, hipMemcpyDeviceToHost, s),
+                       "read cycle state");
+    if (!rc) rc = check_hip(c, hipStreamSynchronize(s), "sync");
+    if (rc) return rc;
+    const double rho = h->rho;
+    if (!(rho > 0.0) || !std::isfinite(rho)) return VMS_OK;
+    // Hbar (m+1) x m, entries below each column's last row cleared: the kept block's columns end
+    // at row j0, an Arnoldi column j at row j + 1
+    std::vector<double> Hb((size_t)(m + 1) * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        const int last = j < j0 ? j0 : j + 1;
+        for (int i = 0; i <= last; ++i) Hb[(size_t)j * (m + 1) + i] = h->H[(size_t)j * ld + i];
+    }
+    // rc = c - Hbar y, c = beta e_1 (plain cycle) or beta (s, rho) in the kept basis
+    std::vector<double> rcv(m + 1, 0.0);
+    if (j0 > 0)
+        for (int i = 0; i <= j0; ++i) rcv[i] = h->dr_c[i];
+    else
+        rcv[0] = h->beta;
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i <= m; ++i) rcv[i] -= Hb[(size_t)j * (m + 1) + i] * h->y[j];
+    DrSetup S;
+    const int k = dr_setup(m, deflate, Hb.data(), m + 1, rcv.data(), &S);
+    if (k <= 0 || k >= m || k > kDrMax) return VMS_OK;
+    // P for the stored basis: V[m] holds u_m, whose final vector is q_m = (u_m - V s) / rho
+    const int mp = m + 1;
+    for (int col = 0; col < k; ++col) {
+        const double pm = S.P[(size_t)col * mp + m];
+        for (int l = 0; l < m; ++l) up[col * mp + l] = S.P[(size_t)col * mp + l] - pm * h->scoef[l] / rho;
+        up[col * mp + m] = pm / rho;
+        double sv = 0.0;
+        for (int l = 0; l <= m; ++l) sv += S.P[(size_t)col * mp + l] * h->svs[l];
+        up[kDrOffSvs + col] = sv;
+    }
+    std::copy(S.Hk.begin(), S.Hk.end(), up + kDrOffH);
+    std::copy(S.R.begin(), S.R.end(), up + kDrOffR);
+    std::copy(S.Qt.begin(), S.Qt.end(), up + kDrOffQt);
+    if ((rc = check_hip(c, hipMemcpyAsync(c->dr_p, up, sizeof(double) * kDrUpload, hipMemcpyHostToDevice, s),
+                        "upload deflation data")))
+        return rc;
+    dr_load_kernel<<<1, kBlock, 0, s>>>(k, c->dr_p, c->gs);
+    const int n = 4 * c->n_nodes;
+    dr_basis_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, mp, k, c->dr_p, mp, (T*)c->V);
+    c->dr_k_dev = k;
+    *kk = k;
+    return check_hip(c, hipGetLastError(), "deflation launch");
+}
+
+// Switch deflated restarting off for the next cycle.
+void dr_off(vms_ctx* c, hipStream_t s) {
+    if (c->dr_k_dev == 0) return;
+    dr_load_kernel<<<1, kBlock, 0, s>>>(0, c->dr_p, c->gs);
+    c->dr_k_dev = 0;
 }
 
 }  // namespace
@@ -1572,6 +1783,18 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     // value runs FP32 restart cycles on the FP32 residual until it falls below inner_rtol
     const bool sweeps = o->inner_rtol > 0;
     const double inner_rtol = o->inner_rtol;
+    // deflated restarting keeps part of every full cycle's basis; it needs the second
+    // Gram-Schmidt pass (the cycle's residual is orthogonalised against the kept vectors)
+    const int deflate = o->deflate;
+    if (deflate != 0) {
+        if (deflate < 0 || deflate > kDrMax - 1 || deflate > m - 2)
+            return set_error(c, VMS_EINVAL, "gmres: deflate must lie in 1 .. min(32, restart - 2)");
+        if (c->prec != VMS_FP64 && sweeps)
+            return set_error(c, VMS_EINVAL, "gmres: deflate needs inner_rtol <= 0");
+        if (c->full_nodes > 0)
+            return set_error(c, VMS_EINVAL, "gmres: deflate is for condensed systems only");
+    }
+    const int cgs2 = deflate > 0 ? 1 : o->cgs2;
     int rc;
     // the constant-pressure coarse mode exists only when a pressure dof is prescribed
     const int coarse_pressure = o->coarse_pressure && c->n_pressure_pins > 0;
@@ -1639,14 +1862,19 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     const int learned_budget = learned ? max_iters / 2 : max_iters;
     bool using_learned = learned;
     bool pending = false;          // an FP64 cycle was launched and not yet counted
+    int j0 = 0;                    // vectors the cycle in flight kept from its predecessor
+    bool dr_ready = false;         // the last cycle ran all its steps: its basis can be deflated
+    dr_off(c, s);
     for (;;) {
         if ((rc = true_residual(c, A, b, x, &rn, s))) return rc;      // synchronises
         int last_k = -1;
         if (pending) {
-            last_k = finish_cycle(c);
-            iters += last_k;
+            int stopped = 0;
+            last_k = finish_cycle(c, &stopped);
+            iters += last_k - j0;
             inf.restarts++;
             pending = false;
+            dr_ready = deflate > 0 && last_k == m && !stopped;
         }
         if (o->log_residuals && inf.logged < o->log_max) {
             convert_kernel<double, float><<<grid_for(n), kBlock, 0, s>>>(
@@ -1673,14 +1901,25 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             if ((rc = launch_ap_setup(c, A, s))) return rc;
             using_learned = false;
             inf.fell_back_to_bj = 1;
+            dr_ready = false;      // the kept basis belongs to the old operator
         }
+        // the next cycle's kept vectors (0: a plain restart)
+        int kk = 0;
+        if (dr_ready) {
+            rc = c->prec == VMS_FP64 ? dr_restart<double>(c, m, j0, deflate, s, &kk)
+                                     : dr_restart<float>(c, m, j0, deflate, s, &kk);
+            if (rc) return rc;
+            dr_ready = false;
+        }
+        if (kk == 0) dr_off(c, s);
+        j0 = kk;
         // while the learned blocks are on trial, no cycle runs past half of the budget, so that
         // the switch to block-Jacobi above happens there
         const int cap = using_learned ? learned_budget : max_iters;
         if (c->prec == VMS_FP64) {
             // one restart cycle on the FP64 residual; the true residual is recomputed above
             if ((rc = run_cycle<double, double>(c, c->r64, (const double*)c->Minv, x, tol, m, cap - iters,
-                                                o->cgs2, s)))
+                                                cgs2, s, 1.0, j0)))
                 return rc;
             pending = true;
         } else if (!sweeps) {
@@ -1692,8 +1931,8 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             inf.refinements++;
             float* rr = (float*)c->r;
             convert_kernel<double, float><<<grid_for(n), kBlock, 0, s>>>(n, c->r64, rr, 1.0 / rn);
-            if ((rc = run_cycle<float, double>(c, rr, (const float*)c->Minv, x, tol / rn, m, cap - iters, o->cgs2,
-                                               s, rn)))
+            if ((rc = run_cycle<float, double>(c, rr, (const float*)c->Minv, x, tol / rn, m, cap - iters, cgs2,
+                                               s, rn, j0)))
                 return rc;
             pending = true;
         } else {
@@ -1714,7 +1953,7 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             int progress = 0;
             while (iters < cap) {
                 if ((rc = run_cycle<float, float>(c, cycle_r, (const float*)c->Minv, d, inner_tol, m,
-                                                  cap - iters, o->cgs2, s)))
+                                                  cap - iters, cgs2, s)))
                     return rc;
                 spmv_kernel<float, float, float, float, 1, float><<<spmv_grid(c->n_nodes), kBlock, 0, s>>>(
                     c->n_nodes, c->rowptr, c->colidx, (const float*)A, d, rr, q, nullptr, nullptr);

@@ -17,6 +17,16 @@ namespace vms {
 constexpr int kBlock = 256;          // threads per workgroup for streaming kernels
 constexpr int kRedBlocks = 1024;     // workgroups of the grid-wide reductions
 constexpr int kMaxRestart = 128;
+constexpr int kDrMax = 33;           // vectors kept by deflated restarting (k <= 32, +1 for a complex pair)
+// Deflated restarting: what the host hands the device between two cycles, packed (doubles,
+// each block column-major): the basis coefficients P ((m+1) x kk, ld m+1), the kept block of H
+// ((kk+1) x kk), its triangle R (kk x kk), Q^T ((kk+1) x (kk+1)) and the free-pressure sums of
+// the kept vectors (kk).
+constexpr int kDrOffH = (kMaxRestart + 1) * kDrMax;
+constexpr int kDrOffR = kDrOffH + (kDrMax + 1) * kDrMax;
+constexpr int kDrOffQt = kDrOffR + kDrMax * kDrMax;
+constexpr int kDrOffSvs = kDrOffQt + (kDrMax + 1) * (kDrMax + 1);
+constexpr int kDrUpload = kDrOffSvs + kDrMax;
 #ifndef VMS_DOT_CHUNKS
 #define VMS_DOT_CHUNKS 64          // upper bound on the workgroups (partials) per GMRES dot slot
 #endif
@@ -126,6 +136,12 @@ struct GmresState {
     unsigned counter;              // arrival counter of last-block reductions
     unsigned gen;                  // cycle number (host-assigned) reported with the progress word
     uint64_t* progress;            // host-mapped progress word: gen << 32 | k << 1 | done
+    // deflated restarting: the cycle starts with dr_k kept vectors V[0 .. dr_k-1], whose
+    // columns of H (rows 0 .. dr_k) and R the host set; dr_qt is Q^T of the QR factors of that
+    // (dr_k + 1) x dr_k block (column-major), dr_c the cycle's least-squares right-hand side
+    int dr_k;
+    double dr_qt[(kDrMax + 1) * (kDrMax + 1)];
+    double dr_c[kDrMax + 1];
 };
 
 // Grid-wide reduction scratch.
@@ -210,6 +226,12 @@ struct vms_ctx {
     hipStream_t cap_stream = nullptr;    // stream the graph is captured on
     hipGraphExec_t cycle_exec = nullptr;
     int cycle_exec_m = 0;                // restart length of cycle_exec
+    // graphs of deflated cycles (steps j0 .. m-1), keyed by (m, j0)
+    hipGraphExec_t dr_exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    int dr_exec_key[4] = {0, 0, 0, 0};
+    double* dr_p = nullptr;              // [kDrUpload] device copy of the packed upload
+    void* dr_pinned = nullptr;           // pinned host: a GmresState read back, then the packed upload
+    int dr_k_dev = 0;                    // the dr_k last written to the device state
     int64_t prof_cycles = 0;             // cycles seen while the phase timers are on
     bool prof_force = false;             // a sampled cycle: every launch of a timed phase is timed
 

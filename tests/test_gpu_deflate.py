@@ -1,0 +1,83 @@
+"""Deflated restarting (GMRES-DR: Morgan, SIAM J. Sci. Comput. 24 (2002)) through the C ABI.
+
+Two condensed systems on which restarted GMRES loses most of its progress at every restart:
+the first Newton tangent of the lid-driven cavity on an 8^3 mesh at Re 400 (one pressure dof
+pinned, coarse pressure correction on), and of the backward-facing step with (1, 2, 1) cells
+per unit length at Re 50 (open outlet, no pressure pin).  With and without deflation, FP64 and
+mixed: the true residual of the returned x, computed on the host with the stored matrix, meets
+rtol; x agrees with scipy's direct solve; the deflated solve restarted several times (so the
+kept basis, its Hessenberg block and the prefix transform of the Givens chain were exercised)
+and took fewer Arnoldi steps.  The invalid option combinations are refused.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from workloads import backward_facing_step, bfs_bc, cavity_bc, cavity_mesh, apply_dirichlet
+from tests.gpu_common import bsr_to_csr, make_context, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# restart length, vectors kept, bound on (deflated steps) / (plain steps)
+CASES = {"cavity8": (20, 6, 0.9), "bfs121": (30, 10, 0.5)}
+
+
+def _system(B, case, precision):
+    if case == "cavity8":
+        m = cavity_mesh(8)
+        bc = cavity_bc(m)
+        re = 400.0
+    else:
+        m = backward_facing_step(1, 2, 1)
+        bc = bfs_bc(m)
+        re = 50.0
+    u = np.zeros((m.n_nodes, 4))
+    apply_dirichlet(u, bc)
+    ctx = make_context(B, m, bc.dofs, precision)
+    A, rhs, _ = B.vms_condense_assemble(ctx, to_dev(u), to_dev(np.zeros((m.n_elems, 3))), re)
+    return ctx, A, rhs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_deflated_restarts_reach_the_direct_solution_in_fewer_steps(vms_lib, case, precision):
+    B = vms_lib
+    restart, k, ratio = CASES[case]
+    print(f"deflation: {case}, precision {precision}, restart {restart}, k {k}", flush=True)
+    ctx, A, rhs = _system(B, case, precision)
+    Am = bsr_to_csr(ctx, A)
+    bs = rhs.cpu().numpy().ravel()
+    xd = spla.spsolve(Am.tocsc(), bs)
+    infos = {}
+    for kk in (0, k):
+        x = ctx.new_vec()
+        rc, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=restart, rtol=1e-10, max_iters=20000,
+                                                                  deflate=kk))
+        xs = x.cpu().numpy().ravel()
+        rel = np.linalg.norm(bs - Am @ xs) / np.linalg.norm(bs)
+        err = np.linalg.norm(xs - xd) / np.linalg.norm(xd)
+        print(f"  deflate {kk}: rc {rc}, steps {info.iters}, cycles {info.restarts}, residual {rel:.2e}, "
+              f"error vs direct {err:.2e}", flush=True)
+        assert rc == B.VMS_OK and info.true_rel_res <= 1e-10 and rel <= 1.01e-10
+        assert err <= 1e-6
+        infos[kk] = info
+    assert infos[k].restarts >= 3
+    assert infos[k].iters <= ratio * infos[0].iters
+
+
+def test_deflation_options_are_checked(vms_lib):
+    B = vms_lib
+    ctx, A, rhs = _system(B, "cavity8", B.VMS_FP64)
+    for opts in (dict(restart=20, deflate=19), dict(restart=50, deflate=33), dict(restart=20, deflate=-1)):
+        with pytest.raises(B.VmsError) as e:
+            B.vms_gmres_solve(ctx, A, rhs, ctx.new_vec(), B.solve_opts(rtol=1e-8, **opts))
+        assert e.value.code == B.VMS_EINVAL, opts
+    mctx, mA, mrhs = _system(B, "cavity8", B.VMS_MIXED)
+    with pytest.raises(B.VmsError) as e:
+        B.vms_gmres_solve(mctx, mA, mrhs, mctx.new_vec(), B.solve_opts(restart=20, deflate=5, inner_rtol=1e-4))
+    assert e.value.code == B.VMS_EINVAL
+    # the largest kept count a restart length allows
+    x = ctx.new_vec()
+    rc, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=20, deflate=18, rtol=1e-10, max_iters=20000))
+    print(f"deflate 18 of 20: rc {rc}, steps {info.iters}, cycles {info.restarts}")
+    assert rc == B.VMS_OK and info.true_rel_res <= 1e-10
