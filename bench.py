@@ -41,6 +41,7 @@ COPY_MIB = 256               # --counters: size of the reference copy
 KERNEL_OF_PHASE = {"condense": "tile_kernel", "spmv": "spmv_kernel", "dots": "dots_kernel",
                    "update": "update_fused_kernel", "pc_apply": "ap_blocks_kernel"}
 TRAIN_RE = (75.0, 125.0)     # Reynolds numbers of the learned correction's training systems
+DEFLATE = 10                 # harmonic Ritz vectors kept by the deflated-restart forms (GMRES(50))
 WORKLOAD_TEXT = ("lid-driven cavity 32^3 cells x 6 tets ({ne} tets, {nn} nodes), Re {re:g}, steady Newton to "
                  "1e-8 with Eisenstat-Walker forcing, GMRES(50) right-preconditioned by 4x4 block-Jacobi "
                  "(learned correction in the headline form) plus the constant-pressure coarse correction; "
@@ -67,7 +68,7 @@ def parse():
                     help="time steps of the transient run in --study bfs (bfs16) and --study jet (jet8)")
     ap.add_argument("--study-restart", type=int, default=50,
                     help="GMRES restart length of the bfs16 evaluation in --study bfs")
-    ap.add_argument("--study-forms", default="fp64_bj,mixed_bj,mixed_learned",
+    ap.add_argument("--study-forms", default="fp64_bj,mixed_bj,mixed_learned,fp64_dr,mixed_dr",
                     help="comma-separated forms of the bfs16 evaluation in --study bfs")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter passes: one condensed assembly and GMRES on the "
@@ -205,17 +206,17 @@ def main():
     b0d = torch.from_numpy(beta0).to(dev)
     log(f"workload {args.workload}: {mesh.n_elems} tets, {mesh.n_nodes} nodes, Re {cfg.re}")
 
-    def lin_opts(weights=None):
+    def lin_opts(weights=None, deflate=0, b64=0):
         return B.solve_opts(restart=50, rtol=1e-9, max_iters=60000,
                             pc=B.VMS_PC_LEARNED if weights is not None else B.VMS_PC_BLOCK_JACOBI,
-                            pc_weights=weights)
+                            pc_weights=weights, deflate=deflate, basis_fp64=b64)
 
-    def solve(ctx, weights=None, re=cfg.re):
+    def solve(ctx, weights=None, re=cfg.re, deflate=0, b64=0):
         u = u0d.clone()
         beta = b0d.clone()
         torch.cuda.synchronize()
-        return driver.newton_solve(ctx, u, beta, re, tol=cfg.newton_tol, lin=lin_opts(weights), forcing="ew",
-                                   max_newton=30)
+        return driver.newton_solve(ctx, u, beta, re, tol=cfg.newton_tol, lin=lin_opts(weights, deflate, b64),
+                                   forcing="ew", max_newton=30)
 
     ctxs = {"fp64": B.Context(xyz, tets, dd, precision=B.VMS_FP64),
             "mixed": B.Context(xyz, tets, dd, precision=B.VMS_MIXED)}
@@ -259,15 +260,22 @@ def main():
     log(f"learned PC: { {k: v for k, v in train_report.items() if k != 'runs'} }")
     del train, val
 
-    # ---- metric 2: time to 1e-8 in every form (one warm-up + one timed solve each)
+    # ---- metric 2: time to 1e-8 in every form (one warm-up + one timed solve each); the _dr
+    # forms restart GMRES with deflation
     forms = {}
-    for name, ctx_name, w in (("fp64_bj", "fp64", None), ("mixed_bj", "mixed", None),
-                              ("mixed_learned", "mixed", weights)):
-        if name == "mixed_learned" and w is None:
-            forms[name] = dict(forms["mixed_bj"], note="validation selected plain block-Jacobi")
+    for name, ctx_name, w, defl, b64 in (("fp64_bj", "fp64", None, 0, 0), ("mixed_bj", "mixed", None, 0, 0),
+                                         ("mixed_learned", "mixed", weights, 0, 0),
+                                         ("fp64_bj_dr", "fp64", None, DEFLATE, 0),
+                                         ("mixed_bj_dr", "mixed", None, DEFLATE, 0),
+                                         ("mixed_learned_dr", "mixed", weights, DEFLATE, 0),
+                                         ("mixed_b64_dr", "mixed", None, DEFLATE, 1),
+                                         ("mixed_learned_b64_dr", "mixed", weights, DEFLATE, 1)):
+        if name.startswith("mixed_learned") and w is None:
+            plain = name.replace("mixed_learned", "mixed_bj" if not b64 else "mixed")
+            forms[name] = dict(forms[plain], note="validation selected plain block-Jacobi")
             continue
-        solve(ctxs[ctx_name], w)
-        r = solve(ctxs[ctx_name], w)
+        solve(ctxs[ctx_name], w, deflate=defl, b64=b64)
+        r = solve(ctxs[ctx_name], w, deflate=defl, b64=b64)
         forms[name] = {"seconds": r.seconds, "newton_steps": len(r.rnorms) - 1,
                        "gmres_iters": int(sum(d["iters"] for d in r.lin)),
                        # GMRES cycles (inner FP32 cycles in the mixed form); a cycle replayed
@@ -275,6 +283,7 @@ def main():
                        # return at once
                        "gmres_cycles": int(sum(d["restarts"] for d in r.lin)),
                        "fell_back_to_bj": int(sum(d["fell_back_to_bj"] for d in r.lin)),
+                       "deflation_stopped": int(sum(d["deflation_stopped"] for d in r.lin)),
                        "final_rel_residual": r.rnorms[-1] / r.rnorms[0]}
         log(f"time-to-1e-8 {name}: {forms[name]}")
 
@@ -513,7 +522,7 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=50, forms=
     import torch
     report = {"study": "bfs", "forms": list(forms)}
     weights = None
-    if "mixed_learned" in forms:
+    if any(f.startswith("mixed_learned") for f in forms):
         t0 = time.perf_counter()
         cfg8, m8, u8, b8, bc8 = build_workload("bfs8")
         ctx8 = B.Context(torch.from_numpy(m8.xyz).to(dev), torch.from_numpy(m8.tets).to(dev),
@@ -569,8 +578,12 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=50, forms=
                        "restart": restart}
     for name in forms:
         prec = B.VMS_FP64 if name.startswith("fp64") else B.VMS_MIXED
-        w = weights if name == "mixed_learned" else None
-        if name == "mixed_learned" and w is None:
+        # a form ending in _dr restarts GMRES with deflation (DEFLATE harmonic Ritz vectors kept);
+        # one with b64 runs a mixed context's GMRES on an FP64 basis
+        defl = DEFLATE if name.endswith("_dr") else 0
+        b64 = 1 if "_b64" in name else 0
+        w = weights if name.startswith("mixed_learned") else None
+        if name.startswith("mixed_learned") and w is None:
             report["bfs16"][name] = "validation selected plain block-Jacobi"
             continue
         ctx = B.Context(torch.from_numpy(m.xyz).to(dev), torch.from_numpy(m.tets).to(dev),
@@ -583,12 +596,14 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=50, forms=
             u_prev.copy_(u)
             driver.set_dirichlet(u, dofs, vals)
             lin = B.solve_opts(restart=restart, rtol=1e-9, max_iters=400000,
-                               pc=B.VMS_PC_LEARNED if w is not None else B.VMS_PC_BLOCK_JACOBI, pc_weights=w)
+                               pc=B.VMS_PC_LEARNED if w is not None else B.VMS_PC_BLOCK_JACOBI, pc_weights=w,
+                               deflate=defl, basis_fp64=b64)
             r = driver.newton_solve(ctx, u, beta, cfg.re, cfg.dt, u_prev, None, tol=cfg.newton_tol, lin=lin,
                                     forcing="ew")
             per_step.append({"seconds": r.seconds, "newton": len(r.rnorms) - 1,
                              "gmres": int(sum(d["iters"] for d in r.lin)),
                              "fell_back": int(sum(d["fell_back_to_bj"] for d in r.lin)),
+                             "deflation_stopped": int(sum(d["deflation_stopped"] for d in r.lin)),
                              "rel_residual": r.rnorms[-1] / r.rnorms[0]})
             log(f"bfs16 {name} step {n}: {per_step[-1]}")
         secs = [p["seconds"] for p in per_step]

@@ -208,7 +208,18 @@ typedef struct {
                                   deflate <= restart - 2, else VMS_EINVAL; so is deflate with
                                   inner_rtol > 0 (mixed ctx) or on the uncondensed system.
                                   Turns cgs2 on.  The kept block's eigenproblem is solved on
-                                  the host between cycles (O(restart^3) flops).             */
+                                  the host between cycles (O(restart^3) flops).  With an
+                                  FP32 basis (mixed ctx without basis_fp64) the kept block
+                                  drifts from the stored vectors over many cycles; see
+                                  vms_solve_info.deflation_stopped.                         */
+    int32_t basis_fp64;        /* mixed ctx: nonzero runs GMRES with an FP64 Krylov basis
+                                  and FP64 vector arithmetic on the FP32-stored matrix and
+                                  preconditioner, applied one after the other at every step
+                                  (so that the Arnoldi operator is exactly the one the FP64
+                                  residual sees); every cycle starts from the FP64 residual
+                                  (inner_rtol and refine_max are not used).  The FP64 basis
+                                  ((max_restart + 3) vectors) is allocated on first use.  No
+                                  effect on an FP64 ctx.                                    */
 } vms_solve_opts;
 
 typedef struct {
@@ -224,6 +235,9 @@ typedef struct {
     int32_t singular_blocks;   /* node diagonal blocks found numerically singular by the last
                                   preconditioner setup; each is applied as the identity (the
                                   true residual still decides convergence)                */
+    int32_t deflation_stopped; /* deflate > 0: 1 if a deflated cycle raised the true
+                                  residual (or made it non-finite); its correction was
+                                  undone and the solve went on with plain restarts        */
 } vms_solve_info;
 
 /* Right-preconditioned restarted GMRES(m) on A x = b (Section 6 names a
@@ -336,7 +350,8 @@ enum {
     VMS_PH_RESIDUAL = 1,       /* residual-only element kernel                            */
     VMS_PH_RECOVER = 2,        /* fine-scale recovery kernel                              */
     VMS_PH_PCSETUP = 3,        /* preconditioner block setup                              */
-    VMS_PH_PCAPPLY = 4,        /* A P formed once per solve (the Arnoldi SpMV applies P)  */
+    VMS_PH_PCAPPLY = 4,        /* A P formed once per solve (the Arnoldi SpMV applies P);
+                                  with basis_fp64 on a mixed ctx, P applied at every step  */
     VMS_PH_SPMV = 5,           /* block-CSR SpMV with A P in the Arnoldi step             */
     VMS_PH_DOTS = 6,           /* Gram-Schmidt dot products (Q^T u, Q^T w, norms)         */
     VMS_PH_UPDATE = 7,         /* Gram-Schmidt update (q_j and the next vector), with the

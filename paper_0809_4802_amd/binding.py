@@ -61,13 +61,14 @@ class SolveOpts(ctypes.Structure):
                 ("pc", ctypes.c_int), ("pc_weights", ctypes.c_void_p), ("refine_max", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("cgs2", ctypes.c_int32),
                 ("coarse_pressure", ctypes.c_int32), ("log_residuals", ctypes.c_void_p),
-                ("log_max", ctypes.c_int32), ("deflate", ctypes.c_int32)]
+                ("log_max", ctypes.c_int32), ("deflate", ctypes.c_int32), ("basis_fp64", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("refinements", ctypes.c_int32),
                 ("fell_back_to_bj", ctypes.c_int32), ("true_rel_res", ctypes.c_double),
-                ("logged", ctypes.c_int32), ("singular_blocks", ctypes.c_int32)]
+                ("logged", ctypes.c_int32), ("singular_blocks", ctypes.c_int32),
+                ("deflation_stopped", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -243,14 +244,16 @@ def _copy_device(dst, src_ptr, nbytes):
 
 
 def solve_opts(restart=50, max_iters=100000, rtol=1e-8, pc=VMS_PC_BLOCK_JACOBI, pc_weights=None,
-               refine_max=30, inner_rtol=0.0, cgs2=1, coarse_pressure=1, log_residuals=None, deflate=0):
+               refine_max=30, inner_rtol=0.0, cgs2=1, coarse_pressure=1, log_residuals=None, deflate=0,
+               basis_fp64=0):
     """log_residuals: device float tensor [k, n_nodes, 4] receiving restart residuals (or None).
-    deflate: vectors kept by deflated restarting (0: plain restarts)."""
+    deflate: vectors kept by deflated restarting (0: plain restarts).  basis_fp64: on a mixed
+    context, an FP64 Krylov basis over the FP32-stored matrix and preconditioner."""
     return SolveOpts(restart, max_iters, rtol, pc,
                      pc_weights.data_ptr() if pc_weights is not None else None,
                      refine_max, inner_rtol, cgs2, coarse_pressure,
                      log_residuals.data_ptr() if log_residuals is not None else None,
-                     int(log_residuals.shape[0]) if log_residuals is not None else 0, deflate)
+                     int(log_residuals.shape[0]) if log_residuals is not None else 0, deflate, basis_fp64)
 
 
 # ---- entry points (same names as the C ABI) ------------------------------------------

@@ -128,7 +128,8 @@ static void free_all(vms_ctx* c) {
     void* ptrs[] = {c->full_cc, c->full_epos, c->zfull, c->xyz4, c->tets, c->dmask, c->dlist, c->rowptr, c->colidx, c->diagpos,
                     c->tpos, c->tile_meta, c->tile_nodes, c->items, c->bmask, c->tile_part, c->A, c->rhs, c->du, c->rnorm, c->flags,
                     c->V, c->w, c->z, c->d, c->r, c->Minv, c->AP, c->Az, c->x64, c->r64, c->gs, c->red,
-                    c->feats, c->hid, c->pblk, c->gblk, c->gdel, c->tvec, c->wgrad, c->fscal, c->dr_p};
+                    c->feats, c->hid, c->pblk, c->gblk, c->gdel, c->tvec, c->wgrad, c->fscal, c->dr_p,
+                    c->V64, c->w64, c->z64};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto e : c->prof_ev)

@@ -558,6 +558,32 @@ __global__ void coarse_column_kernel(int n_rows, const int32_t* __restrict__ row
     Az[4 * (size_t)row + r] = T(acc);
 }
 
+// t = P v = Minv v + z kappa S(v), S(v) = gs->su (the free-pressure sum of the step's vector):
+// the preconditioner of an Arnoldi step applied on its own, for steps whose matrix is stored
+// in a lower precision than the basis (the step then multiplies by A itself, so that its
+// operator is exactly A P, the one the FP64 residual and the correction P V y see).  Idle once
+// the cycle has stopped.
+template <typename TM, typename T>
+__global__ void precond_apply_kernel(int n_nodes, const TM* __restrict__ Minv, const T* __restrict__ v,
+                                     const uint8_t* __restrict__ dmask, const double* __restrict__ zvec,
+                                     const GmresState* gs, T* __restrict__ t) {
+    if (gs->done) return;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int node = tid >> 2, r = tid & 3;
+    if (node >= n_nodes) return;
+    using M4 = typename Vec4<TM>::type;
+    using V4 = typename Vec4<T>::type;
+    const M4 m = *reinterpret_cast<const M4*>(Minv + (size_t)node * 16 + r * 4);
+    const V4 x = *reinterpret_cast<const V4*>(v + 4 * (size_t)node);
+    double acc = double(m.x) * double(x.x) + double(m.y) * double(x.y) + double(m.z) * double(x.z) +
+                 double(m.w) * double(x.w);
+    if (zvec)
+        acc += gs->kappa * gs->su * zvec[4 * (size_t)node + r];
+    else if (r == 3 && !(dmask[node] & 8u))
+        acc += gs->kappa * gs->su;
+    t[4 * (size_t)node + r] = T(acc);
+}
+
 // ------------------------------------------------------------------- Arnoldi step kernels
 // Gram-Schmidt with delayed reorthogonalisation and a single reduction per step (the DCGS2
 // scheme of Swirydowicz et al. / Bielich et al., written here for right-preconditioned
@@ -565,8 +591,9 @@ __global__ void coarse_column_kernel(int n_rows, const int32_t* __restrict__ row
 // after one classical Gram-Schmidt pass, normalised by an estimate; column j-1 of H is
 // provisional.  B = A P is the preconditioned operator, S(v) the sum of the free pressure
 // entries of v.
-//   arnoldi_pc   z = P u_j (block inverse + coarse pressure term, S(u_j) carried in gs)
-//   spmv         w = A z = B u_j
+//   spmv         w = (A P) u_j + kappa S(u_j) A z = B u_j, from the stored blocks of A P (S(u_j)
+//                carried in gs); a step whose matrix is stored in a lower precision than its
+//                basis instead applies P (precond_apply) and then A
 //   dots         slots per (chunk, y): y < j -> (q_y . u_j, q_y . w);  y = j -> (u_j . u_j,
 //                u_j . w);  y = j + 1 -> (w . w, S(w))    -> part[slot][chunk], stride = chunks
 //   update       every workgroup sums the slots itself (step_scalars, same order everywhere):
@@ -1282,16 +1309,17 @@ __global__ __launch_bounds__(kBlock) void free_pressure_sum_kernel(int n_nodes, 
 // x += xscale P t = xscale (Minv t + z kappa (1_p^T t))  (x in TX: double for the FP64 solution,
 // float for an inner correction; xscale is the norm of the residual an FP32 cycle was given
 // scaled to one).  z is the indicator of the free pressure dofs 1_p, or the explicit vector zvec.
-template <typename T, typename TX>
-__global__ void precond_accumulate_kernel(int n_nodes, const T* __restrict__ Minv, const T* __restrict__ t,
+template <typename TM, typename T, typename TX>
+__global__ void precond_accumulate_kernel(int n_nodes, const TM* __restrict__ Minv, const T* __restrict__ t,
                                           const uint8_t* __restrict__ dmask, const double* __restrict__ zvec,
                                           const GmresState* gs, double xscale, TX* __restrict__ x) {
     if (gs->k == 0) return;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = tid >> 2, r = tid & 3;
     if (node >= n_nodes) return;
+    using M4 = typename Vec4<TM>::type;
     using V4 = typename Vec4<T>::type;
-    const V4 m = *reinterpret_cast<const V4*>(Minv + (size_t)node * 16 + r * 4);
+    const M4 m = *reinterpret_cast<const M4*>(Minv + (size_t)node * 16 + r * 4);
     const V4 v = *reinterpret_cast<const V4*>(t + 4 * (size_t)node);
     double s = double(m.x) * double(v.x) + double(m.y) * double(v.y) + double(m.z) * double(v.z) +
                double(m.w) * double(v.w);
@@ -1433,15 +1461,31 @@ inline bool cycle_graphs_enabled() {
     return !(e && e[0] == '0');
 }
 
-template <typename T, typename TX>
-int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int m, int budget, int cgs2,
-              hipStream_t s, double xscale = 1.0, int j0 = 0) {
+// The Krylov basis and work vectors of precision T: the context's own (its precision), or the
+// FP64 set a mixed context allocates for solves with an FP64 basis.
+template <typename T>
+T* basis_vectors(vms_ctx* c, int which) {
+    const bool own = sizeof(T) == elt_size(c);
+    void* p[3] = {own ? c->V : c->V64, own ? c->w : c->w64, own ? c->z : c->z64};
+    return static_cast<T*>(p[which]);
+}
+
+// One restart cycle: T the precision of the basis and of its arithmetic, TM that of the stored
+// matrix, its A P blocks, A z and the preconditioner blocks, TX that of the iterate x.
+// With TM != T the steps apply P and A (Amat) in two passes instead of the stored A P blocks.
+template <typename T, typename TX, typename TM = T>
+int run_cycle(vms_ctx* c, const T* r0, const TM* Minv, TX* x, double tol_abs, int m, int budget, int cgs2,
+              hipStream_t s, double xscale = 1.0, int j0 = 0, const TM* Amat = nullptr) {
+    constexpr bool split = !std::is_same<TM, T>::value;
+    if (split && !Amat) return set_error(c, VMS_EINVAL, "gmres: no matrix for the split operator");
     const int n = 4 * c->n_nodes;
-    const T* AP = (const T*)c->AP;
-    const T* Az = (const T*)c->Az;
-    T* V = (T*)c->V;
-    T* w = (T*)c->w;
-    T* z = (T*)c->z;
+    const TM* AP = (const TM*)c->AP;
+    const TM* Az = (const TM*)c->Az;
+    T* V = basis_vectors<T>(c, 0);
+    T* w = basis_vectors<T>(c, 1);
+    T* z = basis_vectors<T>(c, 2);
+    // recorded graphs are told apart by restart length, kept vectors and basis precision
+    const int pbit = sizeof(T) == 8 ? 1 : 0;
     const uint32_t gen = ++c->cycle_gen;
     c->cycle_timed.clear();
     cycle_start_kernel<T><<<red_grid(n), kBlock, 0, s>>>(n, r0, c->dmask, c->red, c->gs, tol_abs, cgs2, gen);
@@ -1451,7 +1495,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     const double vb = (double)n * sizeof(T);      // bytes of one Krylov vector
     // algorithmic bytes of the Arnoldi SpMV: blocks and column indices, row pointers, the input
     // and output vectors once (the coarse-pressure vector A z it also reads is not credited)
-    const double spmv_bytes = (double)c->nb * (16.0 * sizeof(T) + 4.0) + 4.0 * (c->n_nodes + 1) + 2.0 * vb;
+    const double spmv_bytes = (double)c->nb * (16.0 * sizeof(TM) + 4.0) + 4.0 * (c->n_nodes + 1) + 2.0 * vb;
     const int nch = std::max(1, std::min(kFusedChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
     double* part = c->red->partial;
     const double eps_dot = sizeof(T) == 8 ? 1e-14 : 1e-6;
@@ -1479,11 +1523,22 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
                 if (sw < 0) return VMS_EHIP;
                 if (sw == 1) break;
             }
-            // w = A P u_j = (A P) u_j + kappa S(u_j) A z
-            timed(VMS_PH_SPMV, spmv_bytes, j, st, [&] {
-                spmv_kernel<T, T, T, T, 2, T><<<spmv_grid(c->n_nodes), kBlock, 0, st>>>(
-                    c->n_nodes, c->rowptr, c->colidx, AP, V + (size_t)j * n, Az, w, &c->gs->done, c->gs);
-            });
+            // w = A P u_j = (A P) u_j + kappa S(u_j) A z, or A (P u_j) with z = P u_j
+            if constexpr (split) {
+                timed(VMS_PH_PCAPPLY, (double)c->n_nodes * (16.0 * sizeof(TM) + 8.0 * sizeof(T)), j, st, [&] {
+                    precond_apply_kernel<TM, T><<<grid_for(n), kBlock, 0, st>>>(c->n_nodes, Minv, V + (size_t)j * n,
+                                                                              c->dmask, c->zfull, c->gs, z);
+                });
+                timed(VMS_PH_SPMV, spmv_bytes, j, st, [&] {
+                    spmv_kernel<TM, T, T, T, 0><<<spmv_grid(c->n_nodes), kBlock, 0, st>>>(
+                        c->n_nodes, c->rowptr, c->colidx, Amat, z, (const double*)nullptr, w, &c->gs->done, c->gs);
+                });
+            } else {
+                timed(VMS_PH_SPMV, spmv_bytes, j, st, [&] {
+                    spmv_kernel<TM, T, T, T, 2, TM><<<spmv_grid(c->n_nodes), kBlock, 0, st>>>(
+                        c->n_nodes, c->rowptr, c->colidx, AP, V + (size_t)j * n, Az, w, &c->gs->done, c->gs);
+                });
+            }
             timed(VMS_PH_DOTS, (j + 2) * vb, j, st, [&] {
                 dots_kernel<T><<<dim3(nch, j + 2), kDotThreads, 0, st>>>(c->n_nodes, j, V, w, c->dmask, part,
                                                                          c->gs);
@@ -1506,7 +1561,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     const bool sampled = c->prof_mask != 0 && c->prof_cycles++ % c->prof_every == 0;
     if (graphs && !sampled && j0 > 0) {
         // a full deflated cycle: one recorded graph per (m, j0), kept in a small cache
-        const int key = m * 256 + j0;
+        const int key = (m * 256 + j0) * 2 + pbit;
         int slot = -1;
         for (int q = 0; q < 4; ++q)
             if (c->dr_exec[q] && c->dr_exec_key[q] == key) slot = q;
@@ -1544,7 +1599,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
         if (int rc = check_hip(c, hipGraphLaunch(c->dr_exec[slot], s), "graph launch")) return rc;
     } else if (graphs && !sampled) {
         // a full cycle: replay the recorded steps (the kernels after convergence return at once)
-        if (!c->cycle_exec || c->cycle_exec_m != m) {
+        if (!c->cycle_exec || c->cycle_exec_m != m * 2 + pbit) {
             int rc = VMS_OK;
             if (!c->cap_stream &&
                 (rc = check_hip(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream")))
@@ -1567,7 +1622,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
             rc = check_hip(c, hipGraphInstantiate(&c->cycle_exec, g, nullptr, nullptr, 0), "graph instantiate");
             (void)hipGraphDestroy(g);
             if (rc) return rc;
-            c->cycle_exec_m = m;
+            c->cycle_exec_m = m * 2 + pbit;
         }
         if (int rc = check_hip(c, hipGraphLaunch(c->cycle_exec, s), "graph launch")) return rc;
     } else {
@@ -1580,7 +1635,7 @@ int run_cycle(vms_ctx* c, const T* r0, const T* Minv, TX* x, double tol_abs, int
     backsub_kernel<<<1, kBlock, 0, s>>>(c->gs);
     combine_kernel<T><<<xcd_round(grid_for(n)), kBlock, 0, s>>>(n, V, c->gs, z);
     free_pressure_sum_kernel<T><<<red_grid(c->n_nodes), kBlock, 0, s>>>(c->n_nodes, z, c->dmask, c->red, c->gs);
-    precond_accumulate_kernel<T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, c->dmask, c->zfull, c->gs,
+    precond_accumulate_kernel<TM, T, TX><<<grid_for(n), kBlock, 0, s>>>(c->n_nodes, Minv, z, c->dmask, c->zfull, c->gs,
                                                                     xscale, x);
     return check_hip(c, hipGetLastError(), "gmres cycle launch");
 }
@@ -1662,7 +1717,7 @@ int dr_restart(vms_ctx* c, int m, int j0, int deflate, hipStream_t s, int* kk) {
         return rc;
     dr_load_kernel<<<1, kBlock, 0, s>>>(k, c->dr_p, c->gs);
     const int n = 4 * c->n_nodes;
-    dr_basis_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, mp, k, c->dr_p, mp, (T*)c->V);
+    dr_basis_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, mp, k, c->dr_p, mp, basis_vectors<T>(c, 0));
     c->dr_k_dev = k;
     *kk = k;
     return check_hip(c, hipGetLastError(), "deflation launch");
@@ -1785,17 +1840,26 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     const double inner_rtol = o->inner_rtol;
     // deflated restarting keeps part of every full cycle's basis; it needs the second
     // Gram-Schmidt pass (the cycle's residual is orthogonalised against the kept vectors)
+    // mixed ctx with an FP64 basis: FP64 cycles on the FP32-stored matrix and preconditioner
+    const bool basis64 = c->prec != VMS_FP64 && o->basis_fp64;
     const int deflate = o->deflate;
     if (deflate != 0) {
         if (deflate < 0 || deflate > kDrMax - 1 || deflate > m - 2)
             return set_error(c, VMS_EINVAL, "gmres: deflate must lie in 1 .. min(32, restart - 2)");
-        if (c->prec != VMS_FP64 && sweeps)
+        if (c->prec != VMS_FP64 && !basis64 && sweeps)
             return set_error(c, VMS_EINVAL, "gmres: deflate needs inner_rtol <= 0");
         if (c->full_nodes > 0)
             return set_error(c, VMS_EINVAL, "gmres: deflate is for condensed systems only");
     }
     const int cgs2 = deflate > 0 ? 1 : o->cgs2;
     int rc;
+    if (basis64 && !c->V64) {
+        const size_t vb = sizeof(double) * (size_t)n;
+        if ((rc = check_hip(c, hipMalloc(&c->V64, vb * (c->max_restart + 1)), "alloc FP64 basis")) ||
+            (rc = check_hip(c, hipMalloc(&c->w64, vb), "alloc FP64 basis")) ||
+            (rc = check_hip(c, hipMalloc(&c->z64, vb), "alloc FP64 basis")))
+            return rc;
+    }
     // the constant-pressure coarse mode exists only when a pressure dof is prescribed
     const int coarse_pressure = o->coarse_pressure && c->n_pressure_pins > 0;
 
@@ -1864,6 +1928,8 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     bool pending = false;          // an FP64 cycle was launched and not yet counted
     int j0 = 0;                    // vectors the cycle in flight kept from its predecessor
     bool dr_ready = false;         // the last cycle ran all its steps: its basis can be deflated
+    bool dr_live = deflate > 0;    // deflation still in use in this solve
+    double rn_start = 0.0;         // true residual before the cycle in flight
     dr_off(c, s);
     for (;;) {
         if ((rc = true_residual(c, A, b, x, &rn, s))) return rc;      // synchronises
@@ -1874,7 +1940,19 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             iters += last_k - j0;
             inf.restarts++;
             pending = false;
-            dr_ready = deflate > 0 && last_k == m && !stopped;
+            dr_ready = dr_live && last_k == m && !stopped;
+            if (j0 > 0 && !(rn <= rn_start)) {
+                // A deflated cycle cannot raise the residual in exact arithmetic (y = 0 is
+                // feasible); when it does, the kept block's Arnoldi relation has drifted from the
+                // stored vectors (in FP32 storage the rounding of the recombined basis adds up
+                // over cycles).  Its correction is undone and the solve restarts plainly.
+                if ((rc = check_hip(c, hipMemcpyAsync(x, c->x64, sizeof(double) * n, hipMemcpyDeviceToDevice, s),
+                                    "restore iterate")))
+                    return rc;
+                if ((rc = true_residual(c, A, b, x, &rn, s))) return rc;
+                dr_live = dr_ready = false;
+                inf.deflation_stopped = 1;
+            }
         }
         if (o->log_residuals && inf.logged < o->log_max) {
             convert_kernel<double, float><<<grid_for(n), kBlock, 0, s>>>(
@@ -1906,13 +1984,17 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
         // the next cycle's kept vectors (0: a plain restart)
         int kk = 0;
         if (dr_ready) {
-            rc = c->prec == VMS_FP64 ? dr_restart<double>(c, m, j0, deflate, s, &kk)
-                                     : dr_restart<float>(c, m, j0, deflate, s, &kk);
+            rc = (c->prec == VMS_FP64 || basis64) ? dr_restart<double>(c, m, j0, deflate, s, &kk)
+                                                   : dr_restart<float>(c, m, j0, deflate, s, &kk);
             if (rc) return rc;
             dr_ready = false;
         }
         if (kk == 0) dr_off(c, s);
         j0 = kk;
+        rn_start = rn;
+        if (j0 > 0 &&
+            (rc = check_hip(c, hipMemcpyAsync(c->x64, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "save iterate")))
+            return rc;
         // while the learned blocks are on trial, no cycle runs past half of the budget, so that
         // the switch to block-Jacobi above happens there
         const int cap = using_learned ? learned_budget : max_iters;
@@ -1920,6 +2002,13 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
             // one restart cycle on the FP64 residual; the true residual is recomputed above
             if ((rc = run_cycle<double, double>(c, c->r64, (const double*)c->Minv, x, tol, m, cap - iters,
                                                 cgs2, s, 1.0, j0)))
+                return rc;
+            pending = true;
+        } else if (basis64) {
+            // the same on the FP32-stored matrix and preconditioner, applied one after the other
+            // (the stored A P blocks are rounded products, not the operator the residual sees)
+            if ((rc = run_cycle<double, double, float>(c, c->r64, (const float*)c->Minv, x, tol, m, cap - iters,
+                                                       cgs2, s, 1.0, j0, (const float*)A)))
                 return rc;
             pending = true;
         } else if (!sweeps) {

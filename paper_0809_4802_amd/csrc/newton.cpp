@@ -97,6 +97,7 @@ extern "C" int vms_full_newton_step(vms_ctx* c, double* u, double* beta, const d
     lin.pc = VMS_PC_BLOCK_JACOBI;           // the learned correction is trained on condensed blocks
     lin.pc_weights = nullptr;
     lin.deflate = 0;                        // deflated restarting is not built for the uncondensed system
+    lin.basis_fp64 = 0;                     // nor the FP64 basis of a mixed context
     lin.log_residuals = nullptr;
     lin.log_max = 0;
     const int lrc = gmres_solve(f, f->A, f->rhs, f->du, &lin, &inf.lin, s);   // not phase-timed

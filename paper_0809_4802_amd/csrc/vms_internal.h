@@ -206,7 +206,11 @@ struct vms_ctx {
     void* Minv = nullptr;            // [n_nodes][16] preconditioner blocks
     void* AP = nullptr;              // [nb][16] A P: each block times the preconditioner block of its column
     void* Az = nullptr;              // [4 n_nodes] A z, z = 1 on every free pressure dof
-    double* x64 = nullptr;           // [4 n_nodes]
+    double* x64 = nullptr;           // [4 n_nodes] the iterate before a deflated GMRES cycle
+    // mixed context, GMRES with an FP64 basis: its basis, w and z (allocated on first use)
+    double* V64 = nullptr;           // [(max_restart + 1)][4 n_nodes]
+    double* w64 = nullptr;
+    double* z64 = nullptr;
     double* r64 = nullptr;           // [4 n_nodes]
     vms::GmresState* gs = nullptr;
     vms::RedScratch* red = nullptr;
@@ -225,7 +229,7 @@ struct vms_ctx {
     // a full restart cycle's Arnoldi steps recorded once as a graph (replayed with one launch)
     hipStream_t cap_stream = nullptr;    // stream the graph is captured on
     hipGraphExec_t cycle_exec = nullptr;
-    int cycle_exec_m = 0;                // restart length of cycle_exec
+    int cycle_exec_m = 0;                // restart length of cycle_exec, times 2, + 1 for an FP64 basis
     // graphs of deflated cycles (steps j0 .. m-1), keyed by (m, j0)
     hipGraphExec_t dr_exec[4] = {nullptr, nullptr, nullptr, nullptr};
     int dr_exec_key[4] = {0, 0, 0, 0};

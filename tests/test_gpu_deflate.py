@@ -7,11 +7,17 @@ per unit length at Re 50 (open outlet, no pressure pin).  With and without defla
 mixed: the true residual of the returned x, computed on the host with the stored matrix, meets
 rtol; x agrees with scipy's direct solve; the deflated solve restarted several times (so the
 kept basis, its Hessenberg block and the prefix transform of the Givens chain were exercised)
-and took fewer Arnoldi steps.  The invalid option combinations are refused.
+and took fewer Arnoldi steps.  On the backward-facing step, whose preconditioner is plain
+block-Jacobi (no pressure pin, so no coarse correction), the FP64 steps and cycles match the
+oracle's GMRES-DR (oracle/gmres_dr.py) run on the same stored matrix.  The invalid option
+combinations are refused.
 """
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
+
+from oracle import vms as O
+from oracle.gmres_dr import gmres_dr
 
 from workloads import backward_facing_step, bfs_bc, cavity_bc, cavity_mesh, apply_dirichlet
 from tests.gpu_common import bsr_to_csr, make_context, to_dev
@@ -63,6 +69,49 @@ def test_deflated_restarts_reach_the_direct_solution_in_fewer_steps(vms_lib, cas
         infos[kk] = info
     assert infos[k].restarts >= 3
     assert infos[k].iters <= ratio * infos[0].iters
+
+
+@pytest.mark.parametrize("restart,k", [(30, 10), (20, 5), (40, 16)])
+def test_deflated_steps_match_the_oracle(vms_lib, restart, k):
+    B = vms_lib
+    print(f"deflation parity: bfs121 FP64, restart {restart}, k {k}", flush=True)
+    ctx, A, rhs = _system(B, "bfs121", B.VMS_FP64)
+    Am = bsr_to_csr(ctx, A)
+    bs = rhs.cpu().numpy().ravel()
+    ref = gmres_dr(Am, bs, restart=restart, k=k, rtol=1e-10, max_iters=20000,
+                   Minv_blocks=O.block_jacobi_inverse(Am, ctx.n_nodes))
+    x = ctx.new_vec()
+    rc, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=restart, rtol=1e-10, max_iters=20000,
+                                                              deflate=k))
+    print(f"  GPU {info.iters} steps / {info.restarts} cycles; oracle {ref.iters} / {ref.restarts}")
+    assert rc == B.VMS_OK and ref.converged
+    # rounding (the device's Gram-Schmidt and reduction orders) may move the stop by a step or two
+    assert abs(info.iters - ref.iters) <= max(3, 0.01 * ref.iters)
+    assert abs(info.restarts - ref.restarts) <= 1
+    xs = x.cpu().numpy().ravel()
+    assert np.linalg.norm(xs - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("k", [0, 10])
+def test_fp64_basis_on_a_mixed_context(vms_lib, k):
+    """Mixed context, FP64 Krylov basis: FP64 GMRES (cycles on the FP64 residual, no refinement
+    sweeps) on the FP32-stored matrix.  The oracle runs on that matrix exactly; the device's
+    A P and preconditioner blocks are FP32-rounded, so the steps may differ by a few."""
+    B = vms_lib
+    print(f"FP64 basis on a mixed context: bfs121, restart 30, k {k}", flush=True)
+    ctx, A, rhs = _system(B, "bfs121", B.VMS_MIXED)
+    Am = bsr_to_csr(ctx, A)
+    bs = rhs.cpu().numpy().ravel()
+    ref = gmres_dr(Am, bs, restart=30, k=k, rtol=1e-10, max_iters=20000,
+                   Minv_blocks=O.block_jacobi_inverse(Am, ctx.n_nodes))
+    x = ctx.new_vec()
+    rc, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=30, rtol=1e-10, max_iters=20000, deflate=k,
+                                                              basis_fp64=1))
+    xs = x.cpu().numpy().ravel()
+    rel = np.linalg.norm(bs - Am @ xs) / np.linalg.norm(bs)
+    print(f"  GPU {info.iters} steps / {info.restarts} cycles, residual {rel:.2e}; oracle {ref.iters} / {ref.restarts}")
+    assert rc == B.VMS_OK and rel <= 1.01e-10 and info.refinements == 0 and info.deflation_stopped == 0
+    assert abs(info.iters - ref.iters) <= max(5, 0.03 * ref.iters)
 
 
 def test_deflation_options_are_checked(vms_lib):
