@@ -15,10 +15,13 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvms.so")
-SOURCES = ["ctx.cpp", "element.hip", "krylov.hip", "newton.cpp", "learned_pc.hip", "deflate.cpp"]
+SOURCES = ["ctx.cpp", "element.hip", "krylov.hip", "newton.cpp", "learned_pc.hip"]
+HOST_SOURCES = ["deflate.cpp"]       # plain C++ (no HIP): built with the host compiler
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CXX", "g++")
+HOST_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wall"]
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
          "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
@@ -33,6 +36,13 @@ def build(verbose: bool = False, out: str = LIB, defines=(), build_dir: str = BU
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS + [f"-D{d}" for d in defines]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    for src in HOST_SOURCES:
+        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+        objs.append(obj)
+        cmd = [CXX, "-c", os.path.join(CSRC, src), "-o", obj] + HOST_FLAGS
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
