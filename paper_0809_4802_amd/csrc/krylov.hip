@@ -61,6 +61,22 @@ __global__ void fill_kernel(uint4* p, size_t n16) {
 constexpr int kSpmvLanes = 8;
 constexpr int kSpmvXcdMaxGrid = 2048;
 constexpr int kSpmvUnroll = 8;
+
+// Component I of a quad's four values (lane r of the quad holds component r): a DPP quad_perm
+// broadcast.  Every lane of the quad must be active.
+template <int I>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), I * 0x55, 0xF, 0xF, false));
+}
+template <int I>
+__device__ __forceinline__ double quad_bcast(double v) {
+    return dpp_mov<I * 0x55>(v);
+}
+
+// The four lanes of a block row need the same 4-vector x of the block's column: each loads one
+// component and the quad exchanges them by DPP, so that x is requested once per quad instead
+// of four times (as many bytes as the matrix block otherwise).  The four lanes share the row
+// and the block sequence, so a quad is active or inactive as a whole.
 template <typename TA, typename TX, typename TY, typename TACC, int MODE, typename TB = double>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colidx,
@@ -72,7 +88,6 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
     const int skip = done ? *done : 0;
     constexpr int Q = kSpmvLanes / 4;
     using VA = typename Vec4<TA>::type;
-    using VX = typename Vec4<TX>::type;
     const int slot = gridDim.x <= kSpmvXcdMaxGrid ? xcd_slot(blockIdx.x, gridDim.x) : blockIdx.x;
     const int tid = slot * blockDim.x + threadIdx.x;
     const int row = tid / kSpmvLanes, sub = tid % kSpmvLanes;
@@ -87,26 +102,30 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n_rows, const int32_t*
             cols[u] = k < k1 ? colidx[k] : -1;
         }
         VA av[kSpmvUnroll];
-        VX xv[kSpmvUnroll];
+        TX xr[kSpmvUnroll];
 #pragma unroll
         for (int u = 0; u < kSpmvUnroll; ++u) {
             if (cols[u] >= 0) {
                 av[u] = *reinterpret_cast<const VA*>(A + (size_t)(k0 + q + u * Q) * 16 + r * 4);
-                xv[u] = *reinterpret_cast<const VX*>(x + (size_t)cols[u] * 4);
+                xr[u] = x[(size_t)cols[u] * 4 + r];
             } else {
                 av[u] = VA{TA(0), TA(0), TA(0), TA(0)};
-                xv[u] = VX{TX(0), TX(0), TX(0), TX(0)};
+                xr[u] = TX(0);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kSpmvUnroll; ++u)
-            acc += TACC(av[u].x) * TACC(xv[u].x) + TACC(av[u].y) * TACC(xv[u].y) + TACC(av[u].z) * TACC(xv[u].z) +
-                   TACC(av[u].w) * TACC(xv[u].w);
+        for (int u = 0; u < kSpmvUnroll; ++u) {
+            const TX x0 = quad_bcast<0>(xr[u]), x1 = quad_bcast<1>(xr[u]), x2 = quad_bcast<2>(xr[u]),
+                     x3 = quad_bcast<3>(xr[u]);
+            acc += TACC(av[u].x) * TACC(x0) + TACC(av[u].y) * TACC(x1) + TACC(av[u].z) * TACC(x2) +
+                   TACC(av[u].w) * TACC(x3);
+        }
         // rows longer than kSpmvUnroll blocks per lane (other meshes)
         for (int k = k0 + q + kSpmvUnroll * Q; k < k1; k += Q) {
             const VA a = *reinterpret_cast<const VA*>(A + (size_t)k * 16 + r * 4);
-            const VX xx = *reinterpret_cast<const VX*>(x + (size_t)colidx[k] * 4);
-            acc += TACC(a.x) * TACC(xx.x) + TACC(a.y) * TACC(xx.y) + TACC(a.z) * TACC(xx.z) + TACC(a.w) * TACC(xx.w);
+            const TX xc = x[(size_t)colidx[k] * 4 + r];
+            const TX x0 = quad_bcast<0>(xc), x1 = quad_bcast<1>(xc), x2 = quad_bcast<2>(xc), x3 = quad_bcast<3>(xc);
+            acc += TACC(a.x) * TACC(x0) + TACC(a.y) * TACC(x1) + TACC(a.z) * TACC(x2) + TACC(a.w) * TACC(x3);
         }
     }
     acc += __shfl_xor(acc, 4, 64);       // lanes 4q + r of a row: q = 0 and q = 1
@@ -1051,6 +1070,31 @@ constexpr int kFusedPer = kFusedChunks / kFusedLanes;                // partials
 constexpr int kFusedSlots = kBlock / kFusedLanes;                    // slots per round
 constexpr int kFusedRounds = (2 * (kMaxRestart + 2) + kFusedSlots - 1) / kFusedSlots;
 static_assert(kFusedChunks % kXcds == 0 && kFusedChunks <= kDotChunks, "fused dot chunks");
+// Large meshes: the dots write kWideChunks partials per slot (more workgroups streaming the
+// basis when j is small), slot_sum_kernel adds them, and the update reads one sum per slot.
+constexpr int kWideChunks = 64;
+constexpr int kWideMinNodes = 131072;
+constexpr int kWideSumOffset = 2 * (kMaxRestart + 2) * kWideChunks;   // sums after the partials
+static_assert(kWideChunks <= kDotChunks && kWideChunks % kXcds == 0, "wide dot chunks");
+static_assert(kWideSumOffset + 2 * (kMaxRestart + 2) <= kRedBlocks * (kMaxRestart + 1), "wide sums exceed scratch");
+
+// sums[y] = the nchunks partials of slot y added in chunk order (one workgroup; idle once the
+// cycle has stopped).
+__global__ __launch_bounds__(kBlock) void slot_sum_kernel(int j, int nchunks, const double* __restrict__ part,
+                                                          double* __restrict__ sums, const GmresState* gs) {
+    if (gs->done) return;
+    const int ns = 2 * (j + 2);
+    for (int y = threadIdx.x; y < ns; y += blockDim.x) {
+        const double* p = part + (size_t)y * nchunks;
+        double v[kWideChunks];
+#pragma unroll
+        for (int c = 0; c < kWideChunks; ++c) v[c] = c < nchunks ? p[c] : 0.0;
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < kWideChunks; ++c) t += v[c];
+        sums[y] = t;
+    }
+}
 
 struct StepLds {
     double sums[2 * (kMaxRestart + 2)];
@@ -1496,7 +1540,8 @@ int run_cycle(vms_ctx* c, const T* r0, const TM* Minv, TX* x, double tol_abs, in
     // algorithmic bytes of the Arnoldi SpMV: blocks and column indices, row pointers, the input
     // and output vectors once (the coarse-pressure vector A z it also reads is not credited)
     const double spmv_bytes = (double)c->nb * (16.0 * sizeof(TM) + 4.0) + 4.0 * (c->n_nodes + 1) + 2.0 * vb;
-    const int nch = std::max(1, std::min(kFusedChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
+    const bool wide = c->n_nodes >= kWideMinNodes;
+    const int nch = wide ? kWideChunks : std::max(1, std::min(kFusedChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
     double* part = c->red->partial;
     const double eps_dot = sizeof(T) == 8 ? 1e-14 : 1e-6;
     // timed launches per step, so that steps issued after convergence (their kernels return
@@ -1544,7 +1589,10 @@ int run_cycle(vms_ctx* c, const T* r0, const TM* Minv, TX* x, double tol_abs, in
                                                                          c->gs);
             });
             timed(VMS_PH_UPDATE, (j + 4) * vb, j, st, [&] {
-                update_fused_kernel<T><<<1 + xcd_round(grid_for(n)), kBlock, 0, st>>>(n, j, V, w, nch, part, c->gs,
+                if (wide) slot_sum_kernel<<<1, kBlock, 0, st>>>(j, nch, part, part + kWideSumOffset, c->gs);
+                update_fused_kernel<T><<<1 + xcd_round(grid_for(n)), kBlock, 0, st>>>(n, j, V, w, wide ? 1 : nch,
+                                                                                    wide ? part + kWideSumOffset : part,
+                                                                                    c->gs,
                                                                                     eps_dot);
             });
         }
