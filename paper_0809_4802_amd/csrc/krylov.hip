@@ -496,24 +496,42 @@ __global__ __launch_bounds__(kBlock) void cycle_start_kernel(int n, const T* __r
 
 // Deflated restarting: V[c] = sum_l P(l, c) V[l] for the kept columns c < kk (l < mv), in
 // place -- each thread owns one entry of every vector and reads all of them before it writes.
-template <typename T>
+// P is staged in LDS (every thread reads the same entry: a broadcast); KMAX >= kk bounds the
+// accumulators.
+template <typename T, int KMAX>
 __global__ __launch_bounds__(kBlock) void dr_basis_kernel(int n, int mv, int kk, const double* __restrict__ P,
                                                           int ldp, T* __restrict__ V) {
+    __shared__ double Pl[(kMaxRestart + 1) * KMAX];     // Pl[l KMAX + c]
+    for (int e = threadIdx.x; e < mv * KMAX; e += blockDim.x) {
+        const int l = e / KMAX, c = e % KMAX;
+        Pl[e] = c < kk ? P[(size_t)c * ldp + l] : 0.0;
+    }
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const size_t N = (size_t)n;
-    double acc[kDrMax];
+    double acc[KMAX];
 #pragma unroll
-    for (int c = 0; c < kDrMax; ++c) acc[c] = 0.0;
+    for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
+#pragma unroll 4
     for (int l = 0; l < mv; ++l) {
         const double v = double(V[(size_t)l * N + i]);
 #pragma unroll
-        for (int c = 0; c < kDrMax; ++c)
-            if (c < kk) acc[c] += P[(size_t)c * ldp + l] * v;
+        for (int c = 0; c < KMAX; ++c) acc[c] += Pl[l * KMAX + c] * v;
     }
 #pragma unroll
-    for (int c = 0; c < kDrMax; ++c)
+    for (int c = 0; c < KMAX; ++c)
         if (c < kk) V[(size_t)c * N + i] = T(acc[c]);
+}
+
+template <typename T>
+void launch_dr_basis(int n, int mv, int kk, const double* P, int ldp, T* V, hipStream_t s) {
+    if (kk <= 12)
+        dr_basis_kernel<T, 12><<<grid_for(n), kBlock, 0, s>>>(n, mv, kk, P, ldp, V);
+    else if (kk <= 20)
+        dr_basis_kernel<T, 20><<<grid_for(n), kBlock, 0, s>>>(n, mv, kk, P, ldp, V);
+    else
+        dr_basis_kernel<T, kDrMax><<<grid_for(n), kBlock, 0, s>>>(n, mv, kk, P, ldp, V);
 }
 
 // Deflated restarting: the kept block of H and its factors from the packed upload into the
@@ -1765,7 +1783,7 @@ int dr_restart(vms_ctx* c, int m, int j0, int deflate, hipStream_t s, int* kk) {
         return rc;
     dr_load_kernel<<<1, kBlock, 0, s>>>(k, c->dr_p, c->gs);
     const int n = 4 * c->n_nodes;
-    dr_basis_kernel<T><<<grid_for(n), kBlock, 0, s>>>(n, mp, k, c->dr_p, mp, basis_vectors<T>(c, 0));
+    launch_dr_basis<T>(n, mp, k, c->dr_p, mp, basis_vectors<T>(c, 0), s);
     c->dr_k_dev = k;
     *kk = k;
     return check_hip(c, hipGetLastError(), "deflation launch");

@@ -71,7 +71,7 @@ def test_deflated_restarts_reach_the_direct_solution_in_fewer_steps(vms_lib, cas
     assert infos[k].iters <= ratio * infos[0].iters
 
 
-@pytest.mark.parametrize("restart,k", [(30, 10), (20, 5), (40, 16)])
+@pytest.mark.parametrize("restart,k", [(30, 10), (20, 5), (40, 16), (50, 24)])
 def test_deflated_steps_match_the_oracle(vms_lib, restart, k):
     B = vms_lib
     print(f"deflation parity: bfs121 FP64, restart {restart}, k {k}", flush=True)
