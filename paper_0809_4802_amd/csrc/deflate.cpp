@@ -257,7 +257,9 @@ VMS_HOST_CLONES bool hessenberg_eigenvalues(int n, std::vector<double>& a, std::
 }
 
 // An eigenvector of the upper Hessenberg G (n x n, row-major) for the eigenvalue theta by
-// inverse iteration: two solves with (G - theta I).  Its LU with partial pivoting keeps the
+// inverse iteration: one solve with (G - theta I) from the vector of ones (theta comes from the
+// QR iteration to rounding accuracy, so one step leaves an error of the order of rounding over
+// the gap to the next eigenvalue).  Its LU with partial pivoting keeps the
 // Hessenberg structure (each column has one entry below the diagonal, and the pivot is one of
 // two rows), so a factorisation costs O(n^2).
 VMS_HOST_CLONES void inverse_iteration(int n, const std::vector<double>& G, cd theta, std::vector<cd>& x) {
@@ -288,7 +290,7 @@ VMS_HOST_CLONES void inverse_iteration(int n, const std::vector<double>& G, cd t
     }
     if (mag2(M[(size_t)(n - 1) * n + n - 1]) < tiny * tiny) M[(size_t)(n - 1) * n + n - 1] = tiny;
     x.assign(n, cd(1.0, 0.0));
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < 1; ++pass) {
         for (int col = 0; col + 1 < n; ++col) {
             if (swapped[col]) std::swap(x[col], x[col + 1]);
             x[col + 1] -= cmul(mult[col], x[col]);
