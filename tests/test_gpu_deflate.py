@@ -10,7 +10,9 @@ kept basis, its Hessenberg block and the prefix transform of the Givens chain we
 and took fewer Arnoldi steps.  On the backward-facing step, whose preconditioner is plain
 block-Jacobi (no pressure pin, so no coarse correction), the FP64 steps and cycles match the
 oracle's GMRES-DR (oracle/gmres_dr.py) run on the same stored matrix.  The invalid option
-combinations are refused.
+combinations are refused.  A transient backward-facing-step Newton solve in mixed precision
+exercises the safeguard (deflated cycles that raise the true residual are undone) and shows the
+FP64 basis needs none.
 """
 import numpy as np
 import pytest
@@ -130,3 +132,37 @@ def test_deflation_options_are_checked(vms_lib):
     rc, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=20, deflate=18, rtol=1e-10, max_iters=20000))
     print(f"deflate 18 of 20: rc {rc}, steps {info.iters}, cycles {info.restarts}")
     assert rc == B.VMS_OK and info.true_rel_res <= 1e-10
+
+
+def test_safeguard_undoes_deflated_cycles_that_raise_the_residual(vms_lib):
+    """First backward-Euler step of the backward-facing step (1, 2, 1) at Re 800, dt 0.05, from
+    rest, mixed precision, deterministic context (bitwise reproducible assemblies and solves).
+    With an FP32 basis, deflated cycles of some Newton systems raise the true residual (the
+    kept block drifts from the FP32-rounded basis): each is undone and that solve continues with
+    plain restarts (deflation_stopped), and the Newton solve still reaches 1e-8, by the
+    oracle's FP64 residual of the returned state.  With an FP64 basis no cycle is undone."""
+    from paper_0809_4802_amd import driver
+    import torch
+    B = vms_lib
+    m = backward_facing_step(1, 2, 1)
+    bc = bfs_bc(m)
+    u0 = np.zeros((m.n_nodes, 4))
+    apply_dirichlet(u0, bc)
+    ctx = B.Context(to_dev(m.xyz), to_dev(m.tets.astype(np.int32)), to_dev(np.asarray(bc.dofs, dtype=np.int32)),
+                    precision=B.VMS_MIXED, deterministic=True)
+    stopped = {}
+    for b64 in (0, 1):
+        print(f"safeguard: bfs121 transient Re 800, mixed, basis_fp64 {b64}", flush=True)
+        u = to_dev(u0)
+        beta = torch.zeros((m.n_elems, 3), dtype=torch.float64, device=u.device)
+        u_prev = torch.zeros_like(u)
+        lin = B.solve_opts(restart=50, rtol=1e-9, max_iters=400000, deflate=10, basis_fp64=b64)
+        r = driver.newton_solve(ctx, u, beta, 800.0, 0.05, u_prev, None, tol=1e-8, lin=lin, forcing="ew")
+        stopped[b64] = [d["deflation_stopped"] for d in r.lin]
+        print(f"  Newton {len(r.rnorms) - 1}, GMRES {[d['iters'] for d in r.lin]}, undone {stopped[b64]}")
+        assert r.converged
+        prob = O.Problem(m.xyz, m.tets, bc.dofs, nu=1.0 / 800.0, dt=0.05, u_prev=np.zeros((m.n_nodes, 4)))
+        rn = O.residual_norm_at(prob, u.cpu().numpy(), beta.cpu().numpy())
+        assert rn <= 1.01e-8 * r.rnorms[0], (rn, r.rnorms[0])
+    assert sum(stopped[0]) >= 1
+    assert sum(stopped[1]) == 0
