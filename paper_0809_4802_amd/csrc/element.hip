@@ -51,8 +51,17 @@ struct ElemArgs {
     double inv_dt;
     double adv;                          // 1: Newton tangent; 0: fixed-point tangent (advecting velocity held)
     int n_elems;
-    int32_t* flags;                      // [0] first degenerate element, [1] first singular K_ff
+    unsigned long long* eflags;          // [0] degenerate element, [1] singular K_ff (flag_element)
+    uint32_t gen;                        // call number written with a flag
 };
+
+// Element error flags: word `kind` (0: det J <= 0, 1: singular K_ff) holds gen << 32 | (2^32 - 1 - e)
+// for the latest call number gen that met such an element, e the smallest of its elements: the
+// maximum keeps the newest call and, within it, the smallest element.  A word of an earlier call
+// reads as "no error", so no launch has to clear the flags before a kernel that sets them.
+__device__ __forceinline__ void flag_element(const ElemArgs& a, int kind, int e) {
+    atomicMax(&a.eflags[kind], ((unsigned long long)a.gen << 32) | (0xFFFFFFFFull - (unsigned)e));
+}
 
 // FP64 state of one element: geometry, nodal data and the derived fields.
 struct Elem {
@@ -583,7 +592,7 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
         const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
         // a degenerate element is flagged and contributes nothing (its lane stays in its quad)
         const bool degenerate = !(det > 0.0);
-        if (degenerate) atomicMin(&args.flags[0], e);
+        if (degenerate) flag_element(args, 0, e);
         const bool live = !dummy && !degenerate;
         const bool first = live && (rec.z & 0x8000u) != 0;   // the element's vertex 0 (R_f counted once)
         const double id = degenerate ? 0.0 : 1.0 / det;
@@ -695,7 +704,7 @@ __global__ __launch_bounds__(NT, VMS_TILE_WAVES_PER_SIMD) void tile_kernel(
             double knrm = 0.0;
 #pragma unroll
             for (int i = 0; i < 3; ++i) knrm = fmax(knrm, fabs(Kff[i][0]) + fabs(Kff[i][1]) + fabs(Kff[i][2]));
-            if (live && !(fabs(kdet) > 1e-14 * knrm * knrm * knrm)) atomicMin(&args.flags[1], e);
+            if (live && !(fabs(kdet) > 1e-14 * knrm * knrm * knrm)) flag_element(args, 1, e);
             const double kid = 1.0 / kdet;
             double Ki[3][3];
             Ki[0][0] = k00 * kid;
@@ -849,7 +858,7 @@ __global__ __launch_bounds__(kBlock) void raw_kernel(ElemArgs args, double* __re
     if (e >= args.n_elems) return;
     Elem E;
     if (!load_element(args, e, E)) {
-        atomicMin(&args.flags[0], e);
+        flag_element(args, 0, e);
         return;
     }
     const double nu = args.nu, inv_dt = E.transient ? args.inv_dt : 0.0;
@@ -894,7 +903,7 @@ __global__ __launch_bounds__(kBlock) void raw_kernel(ElemArgs args, double* __re
             for (int c = 0; c < 4; ++c) K[(16 + k) * 19 + 4 * a + c] = double(Kfc[k][c]);
     }
     double Ki[3][3], Kff[3][3];
-    if (!fine_block_inverse(E, nu, Ki, Kff)) atomicMin(&args.flags[1], e);
+    if (!fine_block_inverse(E, nu, Ki, Kff)) flag_element(args, 1, e);
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) K[(16 + i) * 19 + 16 + j] = Kff[i][j];
 }
@@ -906,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void recover_kernel(ElemArgs args, const do
     if (e >= args.n_elems) return;
     Elem E;
     if (!load_element(args, e, E)) {
-        atomicMin(&args.flags[0], e);
+        flag_element(args, 0, e);
         return;
     }
     const double nu = args.nu, inv_dt = E.transient ? args.inv_dt : 0.0;
@@ -927,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void recover_kernel(ElemArgs args, const do
             rhs[i] -= Kfc[i][0] * dd[0] + Kfc[i][1] * dd[1] + Kfc[i][2] * dd[2] + Kfc[i][3] * dd[3];
     }
     double Ki[3][3], Kff[3][3];
-    if (!fine_block_inverse(E, nu, Ki, Kff)) atomicMin(&args.flags[1], e);
+    if (!fine_block_inverse(E, nu, Ki, Kff)) flag_element(args, 1, e);
     double* bo = beta_out + 3 * (size_t)e;
 #pragma unroll
     for (int i = 0; i < 3; ++i) bo[i] = E.be[i] + (Ki[i][0] * rhs[0] + Ki[i][1] * rhs[1] + Ki[i][2] * rhs[2]);
@@ -975,11 +984,6 @@ __global__ __launch_bounds__(kFinThreads) void norm_finalize_kernel(int n_tiles,
     }
 }
 
-__global__ void flags_reset_kernel(int32_t* flags) {
-    if (threadIdx.x < 2) flags[threadIdx.x] = INT_MAX;
-    if (threadIdx.x == 2) flags[2] = 0;
-}
-
 inline int grid_for(int64_t n, int block = kBlock) { return (int)((n + block - 1) / block); }
 
 ElemArgs make_args(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
@@ -996,7 +1000,8 @@ ElemArgs make_args(vms_ctx* c, const double* u, const double* u_prev, const doub
     a.inv_dt = u_prev ? inv_dt : 0.0;
     a.adv = c->linearization == VMS_LIN_PICARD ? 0.0 : 1.0;
     a.n_elems = c->n_elems;
-    a.flags = c->flags;
+    a.eflags = element_flags(c);
+    a.gen = c->elem_gen;
     return a;
 }
 
@@ -1060,7 +1065,7 @@ __global__ __launch_bounds__(kBlock) void full_element_kernel(ElemArgs args, int
     if (e >= args.n_elems) return;
     Elem E;
     if (!load_element(args, e, E)) {
-        atomicMin(&args.flags[0], e);
+        flag_element(args, 0, e);
         return;
     }
     const double nu = args.nu, inv_dt = E.transient ? args.inv_dt : 0.0;
@@ -1132,7 +1137,7 @@ __global__ void full_update_kernel(int n_nodes, int n_elems, const double* __res
 
 int launch_full_assemble(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
                          double inv_dt, const double* body, void* vals, double* rhs, hipStream_t s) {
-    flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
+    ++c->elem_gen;                       // a new call number for the element flags
     ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
     const int64_t nb16 = c->nb * 16;
     const int n4 = 4 * c->n_nodes;
@@ -1165,15 +1170,12 @@ int launch_full_update(vms_ctx* c, const double* dx, double* u, double* beta, hi
 // device addresses: the context's own buffers, or the static scratch of the no-allocation entry.
 static int launch_condense_in(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
                               double inv_dt, const double* body, void* A, double* rhs, double* rglob,
-                              int32_t* flags, double* tile_part, hipStream_t s) {
+                              unsigned long long* eflags, double* tile_part, hipStream_t s) {
     const size_t es = elt_size(c);
     const double nn = c->n_nodes, ne = c->n_elems;
-    {
-        PhaseScope ph(c, VMS_PH_FILL, 0.0, s);
-        flags_reset_kernel<<<1, 64, 0, s>>>(flags);
-    }
+    ++c->elem_gen;                       // a new call number for the element flags
     ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
-    a.flags = flags;
+    a.eflags = eflags;
     // algorithmic bytes: connectivity + beta per element; coordinates, state (and previous
     // velocity, body force) per node; block-CSR values and rhs written once (and the residual
     // rows, when asked for)
@@ -1189,12 +1191,13 @@ static int launch_condense_in(vms_ctx* c, const double* u, const double* u_prev,
 
 int launch_condense(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
                     double inv_dt, const double* body, void* A, double* rhs, double* rglob, hipStream_t s) {
-    return launch_condense_in(c, u, u_prev, beta, nu, inv_dt, body, A, rhs, rglob, c->flags, c->tile_part, s);
+    return launch_condense_in(c, u, u_prev, beta, nu, inv_dt, body, A, rhs, rglob, element_flags(c), c->tile_part,
+                              s);
 }
 
 int launch_residual(vms_ctx* c, const double* u, const double* u_prev, const double* beta, double nu,
                     double inv_dt, const double* body, double* rglob, hipStream_t s) {
-    flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
+    ++c->elem_gen;                       // a new call number for the element flags
     ElemArgs a = make_args(c, u, u_prev, beta, nu, inv_dt, body);
     {
         const double nn = c->n_nodes, ne = c->n_elems;
@@ -1258,14 +1261,16 @@ int noalloc_scratch_init(vms_ctx* c) {
 }
 
 int check_element_flags(vms_ctx* c, hipStream_t s) {
-    int32_t h[3];
-    int rc = check_hip(c, hipMemcpyAsync(h, c->flags, sizeof h, hipMemcpyDeviceToHost, s), "flags");
+    unsigned long long h[2];
+    int rc = check_hip(c, hipMemcpyAsync(h, element_flags(c), sizeof h, hipMemcpyDeviceToHost, s), "flags");
     if (rc) return rc;
     if ((rc = check_hip(c, hipStreamSynchronize(s), "sync"))) return rc;
-    if (h[0] != INT_MAX)
-        return set_error(c, VMS_EDEGENERATE, "element " + std::to_string(h[0]) + " has det J <= 0");
-    if (h[1] != INT_MAX)
-        return set_error(c, VMS_ESINGULAR_KFF, "K_ff singular in element " + std::to_string(h[1]));
+    // flags of the current call number only (flag_element)
+    auto elem = [&](int k) -> long long {
+        return (uint32_t)(h[k] >> 32) == c->elem_gen ? (long long)(0xFFFFFFFFull - (h[k] & 0xFFFFFFFFull)) : -1;
+    };
+    if (elem(0) >= 0) return set_error(c, VMS_EDEGENERATE, "element " + std::to_string(elem(0)) + " has det J <= 0");
+    if (elem(1) >= 0) return set_error(c, VMS_ESINGULAR_KFF, "K_ff singular in element " + std::to_string(elem(1)));
     return VMS_OK;
 }
 
@@ -1287,7 +1292,7 @@ extern "C" int vms_element_tangents(vms_ctx* c, const double* u, const double* u
                                     hipStream_t s) {
     int rc = check_state_args(c, u, beta, Re, dt, u_prev, "vms_element_tangents");
     if (rc) return rc;
-    flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
+    ++c->elem_gen;                       // a new call number for the element flags
     ElemArgs a = make_args(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body);
     if (c->prec == VMS_FP64)
         raw_kernel<double><<<grid_for(c->n_elems), kBlock, 0, s>>>(a, Ke, Rvec);
@@ -1321,7 +1326,7 @@ extern "C" int vms_condense_assemble_noalloc(vms_ctx* c, const double* u, const 
                                             std::to_string(kNoallocMaxTiles) + ")");
     unsigned char* base = nullptr;
     if ((rc = noalloc_scratch(c, &base))) return rc;
-    int32_t* flags = reinterpret_cast<int32_t*>(base);
+    unsigned long long* flags = reinterpret_cast<unsigned long long*>(base);
     double* part = reinterpret_cast<double*>(base + kNoallocFlagBytes);
     rc = launch_condense_in(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body,
                             bsr_vals, rhs, nullptr, flags, part, s);
@@ -1359,7 +1364,7 @@ extern "C" int vms_recover_update(vms_ctx* c, double* u, double* beta, const dou
     int rc = check_state_args(c, u, beta, Re, dt, u_prev, "vms_recover_update");
     if (rc) return rc;
     if (!du) return set_error(c, VMS_EINVAL, "vms_recover_update: NULL du");
-    flags_reset_kernel<<<1, 64, 0, s>>>(c->flags);
+    ++c->elem_gen;                       // a new call number for the element flags
     ElemArgs a = make_args(c, u, dt > 0 ? u_prev : nullptr, beta, 1.0 / Re, dt > 0 ? 1.0 / dt : 0.0, body);
     // beta is read and written by the same lane only, so the update is in place.
     {

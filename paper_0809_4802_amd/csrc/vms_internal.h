@@ -195,7 +195,9 @@ struct vms_ctx {
     double* rhs = nullptr;           // [4 n_nodes]
     double* du = nullptr;            // [4 n_nodes]
     double* rnorm = nullptr;         // [4] device scalars
-    int32_t* flags = nullptr;        // [4] device error flags (bad element, singular K_ff)
+    int32_t* flags = nullptr;        // [8] device flags: [2] singular preconditioner blocks, [3] non-finite
+                                     // learned blocks; [4..7] the two 64-bit element flags (element.hip)
+    uint32_t elem_gen = 0;           // call number of the element flags (advanced by each element launch)
 
     // Krylov workspaces (device); T = double (FP64 ctx) or float (mixed)
     void* V = nullptr;               // [(max_restart + 1)][4 n_nodes]
@@ -281,6 +283,7 @@ namespace vms {
 int set_error(vms_ctx* ctx, int code, const std::string& msg);
 int check_hip(vms_ctx* ctx, hipError_t e, const char* what);
 inline size_t elt_size(const vms_ctx* c) { return c->prec == VMS_FP64 ? 8 : 4; }
+inline unsigned long long* element_flags(vms_ctx* c) { return reinterpret_cast<unsigned long long*>(c->flags + 4); }
 
 // phase timers (ctx.cpp): a scope records an event pair around the launches it encloses
 int prof_begin(vms_ctx* c, int phase, double bytes, hipStream_t s);
