@@ -166,3 +166,28 @@ def test_safeguard_undoes_deflated_cycles_that_raise_the_residual(vms_lib):
         assert rn <= 1.01e-8 * r.rnorms[0], (rn, r.rnorms[0])
     assert sum(stopped[0]) >= 1
     assert sum(stopped[1]) == 0
+
+
+def test_learned_fallback_drops_the_kept_basis(vms_lib):
+    """Deliberately bad learned weights (Delta = -e_0 e_0^T on every node: a singular A P) with
+    deflated restarts, mixed context: the solve gives up the learned blocks after half of
+    max_iters, and the kept basis, which belongs to the old operator, is dropped with them
+    (the first cycle on block-Jacobi restarts plainly); it then converges to rtol with
+    block-Jacobi, by the FP64 residual of the stored matrix.  (On the singular operator a
+    deflated cycle may already have raised the residual, in which case the safeguard stopped
+    deflation before the switch.)"""
+    import torch
+    B = vms_lib
+    ctx, A, rhs = _system(B, "cavity8", B.VMS_MIXED)
+    w = torch.zeros(B.PC_NWEIGHTS, dtype=torch.float32, device=A.device)
+    w[-16] = -1.0                          # b2: Delta[0][0] = -1 on every node
+    x = ctx.new_vec()
+    rc, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=20, rtol=1e-10, max_iters=4000, deflate=6,
+                                                              pc=B.VMS_PC_LEARNED, pc_weights=w))
+    Am = bsr_to_csr(ctx, A)
+    bs = rhs.cpu().numpy().ravel()
+    rel = np.linalg.norm(bs - Am @ x.cpu().numpy().ravel()) / np.linalg.norm(bs)
+    print(f"bad weights + deflation: rc {rc}, steps {info.iters}, fell back {info.fell_back_to_bj}, "
+          f"undone {info.deflation_stopped}, residual {rel:.2e}")
+    assert rc == B.VMS_OK and info.fell_back_to_bj == 1 and rel <= 1.01e-10
+    assert info.iters <= 4000
