@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--no-hbm-config", action="store_true", help="skip the 64^3 jittered-cube measurements")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle sample (0: every element of the workload)")
-    ap.add_argument("--study", choices=["bfs", "nr", "picard", "jet"], default=None,
+    ap.add_argument("--study", choices=["bfs", "nr", "picard", "jet", "es"], default=None,
                     help="bfs: the learned-correction study on the backward-facing step (train on the steady "
                          "Re 400..800 continuation of bfs8, compare block-Jacobi FP64, block-Jacobi mixed and "
                          "the learned correction over the transient bfs16 run); prints its own JSON report "
@@ -195,6 +195,9 @@ def main():
         return
     if args.study == "jet":
         jet_study(B, driver, build_workload, dev, args.study_steps)
+        return
+    if args.study == "es":
+        es_study(B, driver, build_workload, dev)
         return
     cfg, mesh, u0, beta0, bc = build_workload(args.workload)
     if args.counters:
@@ -512,6 +515,51 @@ def jet_study(B, driver, build_workload, dev, steps):
                         "gmres_iters": sum(p["gmres_iters"] for p in per_step), "per_step": per_step}
         log(f"jet {name}: {report[name]['seconds']:.3f} s, {report[name]['gmres_iters']} GMRES iterations")
         ctx.close()
+    print(json.dumps(report), flush=True)
+
+
+def es_study(B, driver, build_workload, dev, forms=("fp64_bj", "mixed_bj", "fp64_dr", "mixed_dr", "mixed_b64_dr")):
+    """The Ethier-Steinman transient of config 3 (es64: 64^3 jittered cube, 1,572,864 tets,
+    Re 1000, backward Euler dt 0.01, 10 steps, the exact boundary values at every t_{n+1}): per
+    form the Newton steps (to 1e-8, Eisenstat-Walker forcing), GMRES(50) iterations and seconds
+    of every time step.  Forms as in the bfs study: fp64 / mixed precision, _dr with deflated
+    restarts (DEFLATE kept), b64 with an FP64 basis on the mixed context."""
+    import numpy as np
+    import torch
+    from workloads import ethier_steinman_bc
+    cfg, mesh, u0, beta0, bc = build_workload("es64")
+    nu_l = 2.0 / cfg.re
+    dofs = torch.from_numpy(bc.dofs.astype(np.int64)).to(dev)
+    report = {"study": "es", "workload": "es64", "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes, "re": cfg.re,
+              "dt": cfg.dt, "steps": cfg.steps, "restart": 50}
+    values = [torch.from_numpy(ethier_steinman_bc(mesh, (n + 1) * cfg.dt, nu_l).values).to(dev)
+              for n in range(cfg.steps)]
+    for name in forms:
+        prec = B.VMS_FP64 if name.startswith("fp64") else B.VMS_MIXED
+        defl = DEFLATE if name.endswith("_dr") else 0
+        b64 = 1 if "_b64" in name else 0
+        ctx = B.Context(torch.from_numpy(mesh.xyz).to(dev), torch.from_numpy(mesh.tets).to(dev),
+                        torch.from_numpy(bc.dofs).to(dev), precision=prec)
+        u = torch.from_numpy(u0).to(dev)
+        beta = torch.from_numpy(beta0).to(dev)
+        u_prev = torch.empty_like(u)
+        per_step = []
+        for n in range(cfg.steps):
+            u_prev.copy_(u)
+            driver.set_dirichlet(u, dofs, values[n])
+            r = driver.newton_solve(ctx, u, beta, cfg.re, cfg.dt, u_prev, None, tol=cfg.newton_tol, forcing="ew",
+                                    lin=B.solve_opts(restart=50, rtol=1e-9, max_iters=400000, deflate=defl,
+                                                     basis_fp64=b64))
+            per_step.append({"newton": len(r.rnorms) - 1, "gmres_iters": int(sum(d["iters"] for d in r.lin)),
+                             "seconds": r.seconds,
+                             "deflation_stopped": int(sum(d["deflation_stopped"] for d in r.lin))})
+        report[name] = {"seconds": sum(p["seconds"] for p in per_step),
+                        "newton_steps": sum(p["newton"] for p in per_step),
+                        "gmres_iters": sum(p["gmres_iters"] for p in per_step), "per_step": per_step}
+        log(f"es64 {name}: {report[name]['seconds']:.3f} s, {report[name]['newton_steps']} Newton steps, "
+            f"{report[name]['gmres_iters']} GMRES iterations")
+        ctx.close()
+        torch.cuda.empty_cache()
     print(json.dumps(report), flush=True)
 
 
