@@ -69,7 +69,7 @@ def parse():
                     help="time steps of the transient run in --study bfs (bfs16) and --study jet (jet8)")
     ap.add_argument("--study-restart", type=int, default=50,
                     help="GMRES restart length of the bfs16 evaluation in --study bfs")
-    ap.add_argument("--study-forms", default="fp64_bj,mixed_bj,mixed_learned,fp64_dr,mixed_dr",
+    ap.add_argument("--study-forms", default="fp64_bj,mixed_bj,mixed_learned,fp64_dr,mixed_b64_dr",
                     help="comma-separated forms of the bfs16 evaluation in --study bfs")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter passes: one condensed assembly and GMRES on the "
