@@ -42,13 +42,59 @@ inline cd cdiv(cd a, cd b) {
 inline double mag2(cd a) { return a.real() * a.real() + a.imag() * a.imag(); }
 
 // Solve A^T x = e_last for an m x m matrix A (column-major, leading dimension lda) by Gaussian
-// elimination with partial pivoting.  Returns false if A is singular.
+// elimination with partial pivoting: O(m^2) when A is upper Hessenberg (every cycle leaves H_m
+// in that form), the dense elimination otherwise.  Returns false if A is singular.
 VMS_HOST_CLONES bool solve_transposed_last(int m, const double* A, int lda, std::vector<double>& x) {
+    bool hess = true;
+    for (int c = 0; c < m && hess; ++c)
+        for (int r = c + 2; r < m; ++r)
+            if (A[(size_t)c * lda + r] != 0.0) {
+                hess = false;
+                break;
+            }
+    x.assign(m, 0.0);
+    x[m - 1] = 1.0;
+    if (hess) {
+        // A = P L U by elimination with partial pivoting, which for an upper Hessenberg matrix
+        // only ever exchanges rows c and c+1 and leaves one multiplier per column (L unit lower
+        // bidiagonal).  Then A^T x = U^T L^T P^T x = e_last: U^T z = e_last forward, L^T w = z
+        // backward with the exchanges undone in reverse order.
+        std::vector<double> U((size_t)m * m);       // row-major copy of A
+        for (int r = 0; r < m; ++r)
+            for (int c = 0; c < m; ++c) U[(size_t)r * m + c] = c + 1 >= r ? A[(size_t)c * lda + r] : 0.0;
+        std::vector<double> mult(m, 0.0);
+        std::vector<char> swapped(m, 0);
+        for (int c = 0; c + 1 < m; ++c) {
+            double* a = &U[(size_t)c * m];
+            double* b = &U[(size_t)(c + 1) * m];
+            if (std::fabs(b[c]) > std::fabs(a[c])) {
+                for (int j = c; j < m; ++j) std::swap(a[j], b[j]);
+                swapped[c] = 1;
+            }
+            if (!(std::fabs(a[c]) > 0.0)) return false;
+            const double f = b[c] / a[c];
+            mult[c] = f;
+            b[c] = 0.0;
+            if (f != 0.0)
+                for (int j = c + 1; j < m; ++j) b[j] -= f * a[j];
+        }
+        if (!(std::fabs(U[(size_t)(m - 1) * m + m - 1]) > 0.0)) return false;
+        // U^T z = e_last: z_c = (e_last[c] - sum_{r<c} U(r, c) z_r) / U(c, c)
+        for (int c = 0; c < m; ++c) {
+            double s = x[c];
+            for (int r = 0; r < c; ++r) s -= U[(size_t)r * m + c] * x[r];
+            x[c] = s / U[(size_t)c * m + c];
+        }
+        // L^T w = z (L has the multiplier of step c at row c+1, column c), then x = P w
+        for (int c = m - 2; c >= 0; --c) {
+            x[c] -= mult[c] * x[c + 1];
+            if (swapped[c]) std::swap(x[c], x[c + 1]);
+        }
+        return true;
+    }
     std::vector<double> M((size_t)m * m);           // M = A^T, row-major
     for (int r = 0; r < m; ++r)
         for (int c = 0; c < m; ++c) M[(size_t)r * m + c] = A[(size_t)r * lda + c];
-    x.assign(m, 0.0);
-    x[m - 1] = 1.0;
     for (int col = 0; col < m; ++col) {
         int piv = col;
         double best = std::fabs(M[(size_t)col * m + col]);
@@ -202,26 +248,29 @@ VMS_HOST_CLONES bool hessenberg_eigenvalues(int n, std::vector<double>& a, std::
         for (int k = lo; k <= hi - 2; ++k) {
             const double nrm = std::sqrt(x * x + y * y + z * z);
             if (nrm > 0.0) {
+                // reflector I - tau u u^T with u = (1, u1, u2): v = (x - alpha, y, z) scaled by
+                // its first entry, and tau = 2 v0^2 / v^T v = -v0 / alpha, as v^T v = -2 alpha v0
                 const double alpha = x >= 0.0 ? -nrm : nrm;
-                double v0 = x - alpha, v1 = y, v2 = z;
-                const double vn = std::sqrt(v0 * v0 + v1 * v1 + v2 * v2);
-                v0 /= vn;
-                v1 /= vn;
-                v2 /= vn;
+                const double v0 = x - alpha;
+                const double iv = 1.0 / v0;
+                const double u1 = y * iv, u2 = z * iv, tau = -v0 / alpha;
                 // eigenvalues only: the transformations are applied inside the active block
                 const int c0 = std::max(lo, k - 1);
-                for (int c = c0; c <= hi; ++c) {                 // rows k..k+2 from the left
-                    const double d = 2.0 * (v0 * A(k, c) + v1 * A(k + 1, c) + v2 * A(k + 2, c));
-                    A(k, c) -= d * v0;
-                    A(k + 1, c) -= d * v1;
-                    A(k + 2, c) -= d * v2;
-                }
                 const int r1 = std::min(k + 3, hi);
-                for (int r = lo; r <= r1; ++r) {                 // columns k..k+2 from the right
-                    const double d = 2.0 * (A(r, k) * v0 + A(r, k + 1) * v1 + A(r, k + 2) * v2);
-                    A(r, k) -= d * v0;
-                    A(r, k + 1) -= d * v1;
-                    A(r, k + 2) -= d * v2;
+                for (int c = c0; c <= hi; ++c) {                 // rows k..k+2 from the left
+                    const double d = tau * (A(k, c) + u1 * A(k + 1, c) + u2 * A(k + 2, c));
+                    A(k, c) -= d;
+                    A(k + 1, c) -= d * u1;
+                    A(k + 2, c) -= d * u2;
+                }
+                // columns k..k+2 from the right, bottom row first: rows k+1..k+3 of column k
+                // hold the next reflector's vector, which can then be formed while the other
+                // rows are still being updated
+                for (int r = r1; r >= lo; --r) {
+                    const double d = tau * (A(r, k) + A(r, k + 1) * u1 + A(r, k + 2) * u2);
+                    A(r, k) -= d;
+                    A(r, k + 1) -= d * u1;
+                    A(r, k + 2) -= d * u2;
                 }
             }
             x = A(k + 1, k);
@@ -233,25 +282,27 @@ VMS_HOST_CLONES bool hessenberg_eigenvalues(int n, std::vector<double>& a, std::
             const double nrm = std::sqrt(x * x + y * y);
             if (nrm > 0.0) {
                 const double alpha = x >= 0.0 ? -nrm : nrm;
-                double v0 = x - alpha, v1 = y;
-                const double vn = std::sqrt(v0 * v0 + v1 * v1);
-                v0 /= vn;
-                v1 /= vn;
+                const double v0 = x - alpha;
+                const double u1 = y / v0, tau = -v0 / alpha;
                 for (int c = std::max(lo, k - 1); c <= hi; ++c) {
-                    const double d = 2.0 * (v0 * A(k, c) + v1 * A(k + 1, c));
-                    A(k, c) -= d * v0;
-                    A(k + 1, c) -= d * v1;
+                    const double d = tau * (A(k, c) + u1 * A(k + 1, c));
+                    A(k, c) -= d;
+                    A(k + 1, c) -= d * u1;
                 }
                 for (int r = lo; r <= hi; ++r) {
-                    const double d = 2.0 * (A(r, k) * v0 + A(r, k + 1) * v1);
-                    A(r, k) -= d * v0;
-                    A(r, k + 1) -= d * v1;
+                    const double d = tau * (A(r, k) + A(r, k + 1) * u1);
+                    A(r, k) -= d;
+                    A(r, k + 1) -= d * u1;
                 }
             }
         }
-        // the reflectors leave rounding below the subdiagonal; it is not part of the iteration
-        for (int r = lo + 2; r <= hi; ++r)
-            for (int c = lo; c < r - 1; ++c) A(r, c) = 0.0;
+        // the reflectors leave rounding below the subdiagonal; it is not part of the iteration.
+        // A bulge reaches at most three rows below the diagonal, and the input is Hessenberg,
+        // so the entries further down are exact zeros already
+        for (int r = lo + 2; r <= hi; ++r) {
+            A(r, r - 2) = 0.0;
+            if (r - 3 >= lo) A(r, r - 3) = 0.0;
+        }
     }
     return true;
 }

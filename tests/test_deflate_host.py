@@ -85,6 +85,28 @@ def _hessenberg(m, seed, shift=0.0, j0=0):
                                                (64, 32, 7, 0.0, 33)])
 def test_kept_space_is_the_smallest_harmonic_ritz_vectors(lib, m, k, seed, shift, j0):
     H, rc = _hessenberg(m, seed, shift, j0)
+    _check_kept_space(lib, H, rc, k)
+
+
+def test_small_subdiagonals(lib):
+    """Subdiagonal entries spread over six decades, as near a breakdown of the Arnoldi process.
+    H_m is then ill-conditioned.  Every harmonic Ritz residual is parallel to the left null
+    vector (-h f; 1) of Hbar, so closure holds only as far as that vector, computed from
+    f = H_m^{-T} e_m, and the given rc agree: to about cond(H_m) times the rounding unit.  The
+    span of the kept vectors is still checked tightly against numpy."""
+    m, k = 50, 10
+    H, _ = _hessenberg(m, 8)
+    rng = np.random.default_rng(9)
+    H[np.arange(1, m + 1), np.arange(m)] *= 10.0 ** rng.uniform(-6.0, 0.0, m)
+    c = rng.standard_normal(m + 1)
+    rc = c - H @ np.linalg.lstsq(H, c, rcond=None)[0]
+    cond = np.linalg.cond(H[:m])
+    assert cond > 1e10
+    _check_kept_space(lib, H, rc, k, closure_rtol=100 * cond * np.finfo(float).eps)
+
+
+def _check_kept_space(lib, H, rc, k, closure_rtol=1e-10):
+    m = H.shape[1]
     kk, P, Hk, Qt, R = _call(lib, H, rc, k)
     assert kk in (k, k + 1)
     # P orthonormal, the first kk columns with a zero last row, the last one the residual direction
@@ -96,7 +118,7 @@ def test_kept_space_is_the_smallest_harmonic_ritz_vectors(lib, m, k, seed, shift
     assert np.abs(np.tril(Hk, -2)).max() == 0.0
     # closure: Hbar P_k stays inside span(P) and Hk is its matrix
     HP = H @ P[:m, :kk]
-    assert np.allclose(HP, P @ Hk, atol=1e-10 * np.abs(HP).max())
+    assert np.allclose(HP, P @ Hk, atol=closure_rtol * np.abs(HP).max())
     # the span is numpy's eigenvectors of G for the kk harmonic Ritz values of smallest modulus
     Hm, h = H[:m], H[m, m - 1]
     f = np.linalg.solve(Hm.T, np.eye(m)[-1])
