@@ -241,7 +241,7 @@ def main():
     for c in ctxs.values():
         c.close()
     ctxs = {"fp64": B.Context(xyz, tets, dd, precision=B.VMS_FP64, deterministic=True),
-            "mixed": B.Context(xyz, tets, dd, precision=B.VMS_MIXED, deterministic=True)}
+            "mixed": B.Context(xyz, tets, dd, precision=B.VMS_MIXED, deterministic=True, basis_fp64=True)}
 
     # ---- learned block-Jacobi correction, held out: trained on the method's own condensed
     # tangents and GMRES restart residuals from mixed-precision Newton solves of this mesh at
@@ -539,7 +539,7 @@ def es_study(B, driver, build_workload, dev, forms=("fp64_bj", "mixed_bj", "fp64
         defl = DEFLATE if name.endswith("_dr") else 0
         b64 = 1 if "_b64" in name else 0
         ctx = B.Context(torch.from_numpy(mesh.xyz).to(dev), torch.from_numpy(mesh.tets).to(dev),
-                        torch.from_numpy(bc.dofs).to(dev), precision=prec)
+                        torch.from_numpy(bc.dofs).to(dev), precision=prec, basis_fp64=bool(b64))
         u = torch.from_numpy(u0).to(dev)
         beta = torch.from_numpy(beta0).to(dev)
         u_prev = torch.empty_like(u)
@@ -640,7 +640,8 @@ def bfs_study(B, driver, learned, build_workload, dev, steps, restart=50, forms=
             report["bfs16"][name] = "validation selected plain block-Jacobi"
             continue
         ctx = B.Context(torch.from_numpy(m.xyz).to(dev), torch.from_numpy(m.tets).to(dev),
-                        torch.from_numpy(bc.dofs).to(dev), precision=prec, max_restart=max(50, restart))
+                        torch.from_numpy(bc.dofs).to(dev), precision=prec, max_restart=max(50, restart),
+                        basis_fp64=bool(b64))
         u = torch.from_numpy(u0).to(dev)
         beta = torch.from_numpy(beta0).to(dev)
         u_prev = torch.empty_like(u)

@@ -89,6 +89,11 @@ typedef struct {
                                   threads, whose LDS additions interleave in
                                   an order that varies from run to run
                                   (results agree to rounding)               */
+    int32_t basis_fp64;        /* VMS_MIXED: 1 also allocates an FP64 Krylov
+                                  basis ((max_restart + 3) vectors of
+                                  4 n_nodes doubles) for solves with
+                                  vms_solve_opts.basis_fp64.  Ignored for
+                                  VMS_FP64 (its basis is FP64 already)       */
 } vms_create_opts;
 
 /* Builds the 4x4 block-CSR pattern of the condensed system (one block per
@@ -217,9 +222,9 @@ typedef struct {
                                   preconditioner, applied one after the other at every step
                                   (so that the Arnoldi operator is exactly the one the FP64
                                   residual sees); every cycle starts from the FP64 residual
-                                  (inner_rtol and refine_max are not used).  The FP64 basis
-                                  ((max_restart + 3) vectors) is allocated on first use.  No
-                                  effect on an FP64 ctx.                                    */
+                                  (inner_rtol and refine_max are not used).  Needs a ctx
+                                  created with vms_create_opts.basis_fp64 (VMS_EINVAL
+                                  otherwise).  No effect on an FP64 ctx.                    */
 } vms_solve_opts;
 
 typedef struct {

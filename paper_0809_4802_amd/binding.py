@@ -53,7 +53,7 @@ class MeshDesc(ctypes.Structure):
 
 class CreateOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("max_restart", ctypes.c_int32), ("full_system", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32)]
+                ("deterministic", ctypes.c_int32), ("basis_fp64", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -153,7 +153,7 @@ class Context:
     """Owns a vms_ctx*.  Tensors passed to it must be CUDA (HIP) tensors."""
 
     def __init__(self, xyz, tets, dirichlet_dofs, precision=VMS_FP64, max_restart=50, full_system=False,
-                 stream=None, deterministic=False):
+                 stream=None, deterministic=False, basis_fp64=False):
         xyz = _dev(xyz, torch.float64).contiguous()
         tets = _dev(tets, torch.int32).contiguous()
         dd = _dev(dirichlet_dofs, torch.int32).contiguous()
@@ -163,7 +163,8 @@ class Context:
         self.dtype = torch.float64 if precision == VMS_FP64 else torch.float32
         desc = MeshDesc(self.n_nodes, self.n_elems, xyz.data_ptr(), tets.data_ptr(), int(dd.numel()),
                         dd.data_ptr() if dd.numel() else None)
-        opts = CreateOpts(precision, max_restart, 1 if full_system else 0, 1 if deterministic else 0)
+        opts = CreateOpts(precision, max_restart, 1 if full_system else 0, 1 if deterministic else 0,
+                          1 if basis_fp64 else 0)
         h = ctypes.c_void_p()
         _check(_lib.vms_create(ctypes.byref(desc), ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
         self.handle = h
@@ -248,7 +249,8 @@ def solve_opts(restart=50, max_iters=100000, rtol=1e-8, pc=VMS_PC_BLOCK_JACOBI, 
                basis_fp64=0):
     """log_residuals: device float tensor [k, n_nodes, 4] receiving restart residuals (or None).
     deflate: vectors kept by deflated restarting (0: plain restarts).  basis_fp64: on a mixed
-    context, an FP64 Krylov basis over the FP32-stored matrix and preconditioner."""
+    context (created with basis_fp64=True), an FP64 Krylov basis over the FP32-stored matrix
+    and preconditioner."""
     return SolveOpts(restart, max_iters, rtol, pc,
                      pc_weights.data_ptr() if pc_weights is not None else None,
                      refine_max, inner_rtol, cgs2, coarse_pressure,

@@ -651,6 +651,12 @@ extern "C" int vms_create(const vms_mesh_desc* mesh, const vms_create_opts* opts
     TRY(dev_alloc(c, &c->r64, N * sizeof(double), "alloc r64"));
     TRY(dev_alloc(c, &c->gs, sizeof(GmresState), "alloc gmres state"));
     TRY(dev_alloc(c, &c->dr_p, sizeof(double) * kDrUpload, "alloc deflation upload"));
+    TRY(check_hip(c, hipHostMalloc(&c->dr_pinned, kDrStagingBytes), "alloc deflation staging"));
+    if (c->prec == VMS_MIXED && opts && opts->basis_fp64) {
+        TRY(dev_alloc(c, &c->V64, (size_t)(c->max_restart + 1) * N * sizeof(double), "alloc FP64 Krylov basis"));
+        TRY(dev_alloc(c, &c->w64, N * sizeof(double), "alloc FP64 w"));
+        TRY(dev_alloc(c, &c->z64, N * sizeof(double), "alloc FP64 z"));
+    }
     TRY(dev_alloc(c, &c->red, sizeof(RedScratch), "alloc reduction scratch"));
     TRY(dev_alloc(c, &c->feats, nn * VMS_PC_NIN * sizeof(float), "alloc feats"));
     TRY(dev_alloc(c, &c->hid, nn * VMS_PC_NHID * sizeof(float), "alloc hidden"));

@@ -1728,14 +1728,8 @@ template <typename T>
 int dr_restart(vms_ctx* c, int m, int j0, int deflate, hipStream_t s, int* kk) {
     constexpr int ld = kMaxRestart + 1;
     *kk = 0;
-    constexpr size_t kGsBytes = (sizeof(GmresState) + 255) & ~size_t(255);
-    if (!c->dr_pinned) {
-        if (int rc = check_hip(c, hipHostMalloc(&c->dr_pinned, kGsBytes + sizeof(double) * kDrUpload),
-                               "alloc deflation staging"))
-            return rc;
-    }
     GmresState* h = reinterpret_cast<GmresState*>(c->dr_pinned);
-    double* up = reinterpret_cast<double*>(reinterpret_cast<char*>(c->dr_pinned) + kGsBytes);
+    double* up = reinterpret_cast<double*>(reinterpret_cast<char*>(c->dr_pinned) + kDrStateBytes);
     const size_t tail = offsetof(GmresState, y);
     int rc = check_hip(c, hipMemcpyAsync(h->H, c->gs->H, sizeof(double) * (size_t)m * ld, hipMemcpyDeviceToHost, s),
                        "read Hessenberg matrix");
@@ -1879,7 +1873,7 @@ int launch_ap_setup(vms_ctx* c, const void* A, hipStream_t s) {
     return check_hip(c, hipGetLastError(), "A P setup launch");
 }
 
-// FP64 residual r64 = b - A x64 and its norm (synchronising).
+// FP64 residual r64 = b - A x and its norm (synchronising).
 static int true_residual(vms_ctx* c, const void* A, const double* b, const double* x, double* rn, hipStream_t s) {
     const int n = 4 * c->n_nodes;
     if (c->prec == VMS_FP64)
@@ -1919,13 +1913,8 @@ int gmres_solve(vms_ctx* c, const void* A, const double* b, double* x, const vms
     }
     const int cgs2 = deflate > 0 ? 1 : o->cgs2;
     int rc;
-    if (basis64 && !c->V64) {
-        const size_t vb = sizeof(double) * (size_t)n;
-        if ((rc = check_hip(c, hipMalloc(&c->V64, vb * (c->max_restart + 1)), "alloc FP64 basis")) ||
-            (rc = check_hip(c, hipMalloc(&c->w64, vb), "alloc FP64 basis")) ||
-            (rc = check_hip(c, hipMalloc(&c->z64, vb), "alloc FP64 basis")))
-            return rc;
-    }
+    if (basis64 && !c->V64)
+        return set_error(c, VMS_EINVAL, "gmres: basis_fp64 needs a context created with basis_fp64");
     // the constant-pressure coarse mode exists only when a pressure dof is prescribed
     const int coarse_pressure = o->coarse_pressure && c->n_pressure_pins > 0;
 

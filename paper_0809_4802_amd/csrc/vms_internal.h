@@ -143,6 +143,10 @@ struct GmresState {
     double dr_qt[(kDrMax + 1) * (kDrMax + 1)];
     double dr_c[kDrMax + 1];
 };
+// the host staging of deflated restarting: a GmresState (padded), then the packed upload
+constexpr size_t kDrStateBytes = (sizeof(GmresState) + 255) & ~size_t(255);
+constexpr size_t kDrStagingBytes = kDrStateBytes + sizeof(double) * kDrUpload;
+
 
 // Grid-wide reduction scratch.
 struct RedScratch {
@@ -236,7 +240,8 @@ struct vms_ctx {
     hipGraphExec_t dr_exec[4] = {nullptr, nullptr, nullptr, nullptr};
     int dr_exec_key[4] = {0, 0, 0, 0};
     double* dr_p = nullptr;              // [kDrUpload] device copy of the packed upload
-    void* dr_pinned = nullptr;           // pinned host: a GmresState read back, then the packed upload
+    void* dr_pinned = nullptr;           // pinned host [kDrStagingBytes]: a GmresState read back
+                                         // (kDrStateBytes), then the packed upload
     int dr_k_dev = 0;                    // the dr_k last written to the device state
     int64_t prof_cycles = 0;             // cycles seen while the phase timers are on
     bool prof_force = false;             // a sampled cycle: every launch of a timed phase is timed

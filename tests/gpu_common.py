@@ -14,10 +14,10 @@ def to_dev(a, dtype=None):
     return t.to(DEV)
 
 
-def make_context(B, mesh, dirichlet_dofs, precision=0, max_restart=50):
+def make_context(B, mesh, dirichlet_dofs, precision=0, max_restart=50, basis_fp64=False):
     return B.Context(to_dev(mesh.xyz), to_dev(mesh.tets.astype(np.int32)),
                      to_dev(np.asarray(dirichlet_dofs, dtype=np.int32)), precision=precision,
-                     max_restart=max_restart)
+                     max_restart=max_restart, basis_fp64=basis_fp64)
 
 
 def bsr_to_csr(ctx, vals):

@@ -30,7 +30,7 @@ pytestmark = pytest.mark.gpu
 CASES = {"cavity8": (20, 6, 0.9), "bfs121": (30, 10, 0.5)}
 
 
-def _system(B, case, precision):
+def _system(B, case, precision, basis_fp64=False):
     if case == "cavity8":
         m = cavity_mesh(8)
         bc = cavity_bc(m)
@@ -41,7 +41,7 @@ def _system(B, case, precision):
         re = 50.0
     u = np.zeros((m.n_nodes, 4))
     apply_dirichlet(u, bc)
-    ctx = make_context(B, m, bc.dofs, precision)
+    ctx = make_context(B, m, bc.dofs, precision, basis_fp64=basis_fp64)
     A, rhs, _ = B.vms_condense_assemble(ctx, to_dev(u), to_dev(np.zeros((m.n_elems, 3))), re)
     return ctx, A, rhs
 
@@ -101,7 +101,7 @@ def test_fp64_basis_on_a_mixed_context(vms_lib, k):
     A P and preconditioner blocks are FP32-rounded, so the steps may differ by a few."""
     B = vms_lib
     print(f"FP64 basis on a mixed context: bfs121, restart 30, k {k}", flush=True)
-    ctx, A, rhs = _system(B, "bfs121", B.VMS_MIXED)
+    ctx, A, rhs = _system(B, "bfs121", B.VMS_MIXED, basis_fp64=True)
     Am = bsr_to_csr(ctx, A)
     bs = rhs.cpu().numpy().ravel()
     ref = gmres_dr(Am, bs, restart=30, k=k, rtol=1e-10, max_iters=20000,
@@ -127,6 +127,13 @@ def test_deflation_options_are_checked(vms_lib):
     with pytest.raises(B.VmsError) as e:
         B.vms_gmres_solve(mctx, mA, mrhs, mctx.new_vec(), B.solve_opts(restart=20, deflate=5, inner_rtol=1e-4))
     assert e.value.code == B.VMS_EINVAL
+    # an FP64 basis is allocated by vms_create only: a mixed context created without one refuses
+    # it, and an FP64 context ignores the option
+    with pytest.raises(B.VmsError) as e:
+        B.vms_gmres_solve(mctx, mA, mrhs, mctx.new_vec(), B.solve_opts(restart=20, deflate=5, basis_fp64=1))
+    assert e.value.code == B.VMS_EINVAL
+    rc, info = B.vms_gmres_solve(ctx, A, rhs, ctx.new_vec(), B.solve_opts(restart=20, rtol=1e-8, basis_fp64=1))
+    assert rc == B.VMS_OK and info.true_rel_res <= 1e-8
     # the largest kept count a restart length allows
     x = ctx.new_vec()
     rc, info = B.vms_gmres_solve(ctx, A, rhs, x, B.solve_opts(restart=20, deflate=18, rtol=1e-10, max_iters=20000))
@@ -149,7 +156,7 @@ def test_safeguard_undoes_deflated_cycles_that_raise_the_residual(vms_lib):
     u0 = np.zeros((m.n_nodes, 4))
     apply_dirichlet(u0, bc)
     ctx = B.Context(to_dev(m.xyz), to_dev(m.tets.astype(np.int32)), to_dev(np.asarray(bc.dofs, dtype=np.int32)),
-                    precision=B.VMS_MIXED, deterministic=True)
+                    precision=B.VMS_MIXED, deterministic=True, basis_fp64=True)
     stopped = {}
     for b64 in (0, 1):
         print(f"safeguard: bfs121 transient Re 800, mixed, basis_fp64 {b64}", flush=True)
