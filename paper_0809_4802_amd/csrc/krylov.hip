@@ -1207,8 +1207,10 @@ __device__ __forceinline__ bool step_scalars(int j, int nchunks, const double* _
     return true;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void update_fused_kernel(int n, int j, T* __restrict__ V,
+// The vector rows are split in eighths of xrows rows, one per XCD: the rows whose dot products
+// the dots launch formed on that XCD, so that their reads here hit its L2.
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void update_fused_kernel(int n, int xrows, int j, T* __restrict__ V,
                                                               const T* __restrict__ w, int nchunks,
                                                               const double* __restrict__ part, GmresState* gs,
                                                               double eps_dot) {
@@ -1227,48 +1229,77 @@ __global__ __launch_bounds__(kBlock) void update_fused_kernel(int n, int j, T* _
         arnoldi_columns(j, gs, &in);
         return;
     }
-    const int g8 = (gridDim.x - 1) / kXcds, bb = blockIdx.x - 1;
-    const int slot = ((bb % kXcds + 1) % kXcds) * g8 + bb / kXcds;
-    const int idx = slot * blockDim.x + threadIdx.x;
-    const bool live = idx < n;
-    const int ix = live ? idx : n - 1;            // every thread takes part in the step's sums
+    // R rows per thread, each row's loads coalesced across the workgroup; workgroup b runs on
+    // XCD b mod 8 and takes the (b-1)/8-th block of R * blockDim rows of that XCD's eighth
+    const int bb = blockIdx.x - 1;
+    const int base = ((bb + 1) % kXcds) * xrows, end = min(n, base + xrows);
+    int idx[R], ix[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        idx[r] = base + ((bb / kXcds) * R + r) * (int)blockDim.x + (int)threadIdx.x;
+        ix[r] = idx[r] < n ? idx[r] : n - 1;     // every thread takes part in the step's sums
+    }
     const size_t N = (size_t)n;
     T* uj = V + (size_t)j * N;
-    const double u0 = double(uj[ix]), w0 = double(w[ix]);
-    T v0[8];
+    double aq[R], aw[R];
+    T v0[8][R];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v0[q] = V[(size_t)min(q, max(j - 1, 0)) * N + ix];
+    for (int r = 0; r < R; ++r) {
+        aq[r] = double(uj[ix[r]]);
+        aw[r] = double(w[ix[r]]);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v0[q][r] = V[(size_t)min(q, max(j - 1, 0)) * N + ix[r]];
     if (!step_scalars(j, nchunks, part, gs, eps_dot, L, o)) return;
     const bool reorth = L.flags[1] != 0;
-    double aq = u0, aw = w0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         if (q < j) {
-            aq -= (reorth ? L.sums[2 * q] : 0.0) * double(v0[q]);
-            aw -= L.sums[2 * q + 1] * double(v0[q]);
+            const double sq = reorth ? L.sums[2 * q] : 0.0, tq = L.sums[2 * q + 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                aq[r] -= sq * double(v0[q][r]);
+                aw[r] -= tq * double(v0[q][r]);
+            }
         }
     }
     int i = 8;
     for (; i + 8 <= j; i += 8) {
-        double vv[8];
+        double vv[8][R];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) vv[q] = double(V[(size_t)(i + q) * N + ix]);
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) vv[q][r] = double(V[(size_t)(i + q) * N + ix[r]]);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            aq -= (reorth ? L.sums[2 * (i + q)] : 0.0) * vv[q];
-            aw -= L.sums[2 * (i + q) + 1] * vv[q];
+            const double sq = reorth ? L.sums[2 * (i + q)] : 0.0, tq = L.sums[2 * (i + q) + 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                aq[r] -= sq * vv[q][r];
+                aw[r] -= tq * vv[q][r];
+            }
         }
     }
     for (; i < j; ++i) {
-        const double v = double(V[(size_t)i * N + ix]);
-        aq -= (reorth ? L.sums[2 * i] : 0.0) * v;
-        aw -= L.sums[2 * i + 1] * v;
+        const double sq = reorth ? L.sums[2 * i] : 0.0, tq = L.sums[2 * i + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double v = double(V[(size_t)i * N + ix[r]]);
+            aq[r] -= sq * v;
+            aw[r] -= tq * v;
+        }
     }
     const double rho = o.rho, cj = o.cj, hh = o.hh;
-    if (!live || !(rho > 0.0)) return;
-    const double q = aq / rho;
-    uj[idx] = T(q);
-    if (hh > 0.0) V[(size_t)(j + 1) * N + idx] = T((aw - cj * q) / (rho * hh));
+    if (!(rho > 0.0)) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (idx[r] >= end) continue;             // beyond the vector or this XCD's eighth
+        const double q = aq[r] / rho;
+        uj[idx[r]] = T(q);
+        if (hh > 0.0) V[(size_t)(j + 1) * N + idx[r]] = T((aw[r] - cj * q) / (rho * hh));
+    }
 }
 
 // y = R^{-1} g for the k x k triangle of the rotated Hessenberg matrix (one workgroup): the
@@ -1560,6 +1591,10 @@ int run_cycle(vms_ctx* c, const T* r0, const TM* Minv, TX* x, double tol_abs, in
     const double spmv_bytes = (double)c->nb * (16.0 * sizeof(TM) + 4.0) + 4.0 * (c->n_nodes + 1) + 2.0 * vb;
     const bool wide = c->n_nodes >= kWideMinNodes;
     const int nch = wide ? kWideChunks : std::max(1, std::min(kFusedChunks, (c->n_nodes + kDotThreads - 1) / kDotThreads));
+    // rows of the vectors whose dots the workgroups on one XCD form (the dots take their chunks
+    // in xcd_slot order when there are a multiple of 8 of them), which the update reads there too
+    const int xrows = nch % kXcds == 0 ? 4 * ((c->n_nodes + nch - 1) / nch) * (nch / kXcds)
+                                       : (n + kXcds - 1) / kXcds;
     double* part = c->red->partial;
     const double eps_dot = sizeof(T) == 8 ? 1e-14 : 1e-6;
     // timed launches per step, so that steps issued after convergence (their kernels return
@@ -1608,10 +1643,17 @@ int run_cycle(vms_ctx* c, const T* r0, const TM* Minv, TX* x, double tol_abs, in
             });
             timed(VMS_PH_UPDATE, (j + 4) * vb, j, st, [&] {
                 if (wide) slot_sum_kernel<<<1, kBlock, 0, st>>>(j, nch, part, part + kWideSumOffset, c->gs);
-                update_fused_kernel<T><<<1 + xcd_round(grid_for(n)), kBlock, 0, st>>>(n, j, V, w, wide ? 1 : nch,
-                                                                                    wide ? part + kWideSumOffset : part,
-                                                                                    c->gs,
-                                                                                    eps_dot);
+                // two vector rows per thread halve the workgroups that each form the step's
+                // scalars, except for FP64 vectors on small meshes, where one row per thread
+                // keeps more waves streaming the basis
+                const double* sums = wide ? part + kWideSumOffset : part;
+                const int nsum = wide ? 1 : nch;
+                if (sizeof(T) == 4 || wide)
+                    update_fused_kernel<T, 2><<<1 + kXcds * grid_for(xrows, 2 * kBlock), kBlock, 0, st>>>(
+                        n, xrows, j, V, w, nsum, sums, c->gs, eps_dot);
+                else
+                    update_fused_kernel<T, 1><<<1 + kXcds * grid_for(xrows, kBlock), kBlock, 0, st>>>(
+                        n, xrows, j, V, w, nsum, sums, c->gs, eps_dot);
             });
         }
         // the second pass of the last vector completes the last column
