@@ -26,7 +26,10 @@
  *   - Newton sign convention: K * Delta = -R.
  *   - Every call enqueues on `stream` (NULL = default stream) and returns an
  *     int status; calls documented as synchronising wait for the stream.
- *   - No call allocates device memory except vms_create.
+ *   - No call allocates device or pinned host memory except vms_create (the
+ *     HIP runtime objects behind the GMRES cycle graphs aside: the capture
+ *     stream and the executable graphs that vms_gmres_solve creates on first
+ *     use of a restart length and keeps until vms_destroy).
  *   - Errors: negative status; vms_last_error() describes the last one.
  *     Nothing aborts the process (the paper's code aborted on solver
  *     failure, Section 6; this library returns VMS_ENOCONV_* instead).
