@@ -44,7 +44,10 @@ def test_invariant_krylov_space_on_a_large_grid(vms_lib, precision):
     bc = cavity_bc(m)
     print(f"invariant-space regression: cavity 64^3 mesh, {m.n_nodes} nodes, precision {precision}", flush=True)
     ctx = make_context(B, m, bc.dofs, precision)
-    assert 4 * ctx.n_nodes // 256 > 2048          # update launch: more than 2048 workgroups
+    # update launch: more than 2048 workgroups (from 131,072 nodes on, each XCD's eighth is the
+    # rows of the dots' 8 of 64 chunks, two rows per thread)
+    rows_per_xcd = 4 * -(-ctx.n_nodes // 64) * 8
+    assert 8 * -(-rows_per_xcd // 512) > 2048
     vals, b, x_ref = _block_diagonal_system(ctx, seed=11 + precision)
     x = ctx.new_vec()
     rc, info = B.vms_gmres_solve(ctx, vals, to_dev(b), x, B.solve_opts(restart=50, rtol=1e-10, max_iters=400))
