@@ -255,8 +255,8 @@ def main():
                                            lin=B.solve_opts(restart=50, rtol=1e-4, max_iters=60000), per_step=48)
         train += d[:-1]
         val.append((d[-1][0], d[-1][1][0].contiguous()))
-    weights, train_report = learned.train_select(ctx, train or [v for v in val], val, seeds=(1, 2, 3), steps=200,
-                                                 lr=3e-4)
+    weights, train_report = learned.train_select(ctx, train or [v for v in val], val, seeds=(1, 2, 3), steps=300,
+                                                 lr=3e-4, lr_decay="cosine", check_every=10)
     train_report["seconds"] = time.perf_counter() - t0
     train_report["training_systems"] = (f"cavity32 mixed Newton solves at Re {', '.join(f'{r:g}' for r in TRAIN_RE)}: "
                                         f"{len(train)} systems for training, the last system of each solve "

@@ -6,6 +6,7 @@ runs in the library's kernels (vms_pc_train_step).
 """
 from __future__ import annotations
 
+import math
 import numpy as np
 import torch
 
@@ -96,14 +97,17 @@ def gmres_iterations(ctx: B.Context, A, b, weights, rtol=1e-4, max_iters=20000, 
 
 
 def train_validated(ctx: B.Context, data, val, steps=200, lr=3e-4, batch=8, seed=1, check_every=20,
-                    val_rtol=1e-4, val_restart=50, val_max_iters=20000, min_gain=0.2):
+                    val_rtol=1e-4, val_restart=50, val_max_iters=20000, min_gain=0.2, lr_decay="none"):
     """Trains on `data` and keeps the checkpoint with the fewest GMRES iterations on the
     held-out systems `val` (list of (bsr_vals, rhs)); plain block-Jacobi (the zero output
     layer) is one of the candidates, so the result is never worse on the validation set.
     A checkpoint replaces block-Jacobi only if it saves at least min_gain of its validation
     iterations: restarted GMRES counts scatter widely under small perturbations of the
     operator, so a smaller gain is not evidence that the correction helps.
+    lr_decay: "none" keeps lr; "cosine" scales it by (1 + cos(pi (step - 1) / steps)) / 2.
     Returns (weights or None for block-Jacobi, report)."""
+    if lr_decay not in ("none", "cosine"):
+        raise ValueError(f"lr_decay must be 'none' or 'cosine', not {lr_decay!r}")
     def score(w, cap=val_max_iters):
         return sum(gmres_iterations(ctx, A, b, w, rtol=val_rtol, max_iters=cap, restart=val_restart) for A, b in val)
 
@@ -119,7 +123,8 @@ def train_validated(ctx: B.Context, data, val, steps=200, lr=3e-4, batch=8, seed
         A, S = data[rng.integers(len(data))]
         k = min(batch, S.shape[0])
         idx = torch.from_numpy(rng.choice(S.shape[0], size=k, replace=False)).to(ctx.device)
-        B.vms_pc_train_step(ctx, A, S.index_select(0, idx).contiguous(), w, state, step, lr, None, loss)
+        lr_t = lr * (0.5 * (1.0 + math.cos(math.pi * (step - 1) / steps)) if lr_decay == "cosine" else 1.0)
+        B.vms_pc_train_step(ctx, A, S.index_select(0, idx).contiguous(), w, state, step, lr_t, None, loss)
         if step % check_every == 0:
             s = score(w, cap)
             report["checkpoints"].append({"step": step, "loss": float(loss.item()), "val_iters": s})
