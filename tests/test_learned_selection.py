@@ -1,5 +1,7 @@
-"""Checkpoint selection of the learned correction (host logic, not gpu): the GMRES iteration
-counts and the training step are replaced by scripted stand-ins, so only the rule is tested."""
+"""Checkpoint selection and learning-rate schedule of the learned correction (host logic, not
+gpu): the GMRES iteration counts and the training step are replaced by scripted stand-ins, so
+only the rules are tested."""
+import pytest
 import torch
 
 from paper_0809_4802_amd import binding as B
@@ -34,3 +36,30 @@ def test_small_gains_keep_block_jacobi(monkeypatch):
 def test_min_gain_zero_takes_any_improvement(monkeypatch):
     w, rep = _select(monkeypatch, [1000, 999, 1200], min_gain=0.0)
     assert rep["selected"] == "learned" and rep["val_iters_selected"] == 999
+
+
+def _rates(monkeypatch, steps, **kw):
+    """The learning rate handed to each training step."""
+    seen = []
+    monkeypatch.setattr(learned, "gmres_iterations", lambda ctx, A, b, w, **k: 1000)
+    monkeypatch.setattr(B, "vms_pc_train_step", lambda ctx, A, S, w, state, step, lr, *a: seen.append((step, lr)))
+    data = [(None, torch.zeros((4, 3, 4)))]
+    learned.train_validated(_Ctx(), data, [(None, None)], steps=steps, check_every=steps, lr=1e-3, **kw)
+    return seen
+
+
+def test_cosine_decay_of_the_learning_rate(monkeypatch):
+    steps = 100
+    seen = _rates(monkeypatch, steps, lr_decay="cosine")
+    assert [s for s, _ in seen] == list(range(1, steps + 1))
+    lrs = [lr for _, lr in seen]
+    assert lrs[0] == 1e-3                                   # full rate at the first step
+    assert abs(lrs[steps // 2] - 0.5e-3) < 1e-12            # half way (step 51: cos(pi / 2) = 0)
+    assert 0.0 < lrs[-1] < 1e-6                             # close to zero at the last step
+    assert all(a >= b for a, b in zip(lrs, lrs[1:]))        # never rises
+
+
+def test_constant_rate_without_decay_and_unknown_decay_rejected(monkeypatch):
+    assert {lr for _, lr in _rates(monkeypatch, 10)} == {1e-3}
+    with pytest.raises(ValueError):
+        _rates(monkeypatch, 10, lr_decay="linear")
