@@ -147,7 +147,6 @@ struct GmresState {
 constexpr size_t kDrStateBytes = (sizeof(GmresState) + 255) & ~size_t(255);
 constexpr size_t kDrStagingBytes = kDrStateBytes + sizeof(double) * kDrUpload;
 
-
 // Grid-wide reduction scratch.
 struct RedScratch {
     double partial[kRedBlocks * (kMaxRestart + 1)];
