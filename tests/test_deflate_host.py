@@ -142,3 +142,89 @@ def test_singular_leading_block_keeps_nothing(lib):
     H[np.arange(1, m + 1), np.arange(m)] = 1.0          # H_m is singular (zero first row)
     kk, *_ = _call(lib, H, np.ones(m + 1), 3)
     assert kk == 0
+
+
+# ---- the Francis double-shift QR itself (eigenvalues of an upper Hessenberg matrix) ----------
+EIG_SHIM = r"""
+#include "deflate.cpp"
+extern "C" int hess_eig_c(int n, const double* a, double* re, double* im) {
+    std::vector<double> w(a, a + (size_t)n * n);
+    std::vector<std::complex<double>> ev;
+    if (!vms::hessenberg_eigenvalues(n, w, ev)) return 0;
+    for (int i = 0; i < (int)ev.size(); ++i) {
+        re[i] = ev[i].real();
+        im[i] = ev[i].imag();
+    }
+    return (int)ev.size();
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def eig_lib(tmp_path_factory):
+    d = tmp_path_factory.mktemp("hess_eig")
+    shim = d / "eig_shim.cpp"
+    shim.write_text(EIG_SHIM)
+    so = d / "libhess_eig.so"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I", CSRC, str(shim), "-o", str(so)])
+    L = ctypes.CDLL(str(so))
+    L.hess_eig_c.restype = ctypes.c_int
+    return L
+
+
+def _eig(L, H):
+    n = H.shape[0]
+    a = np.ascontiguousarray(H, dtype=np.float64)         # row-major, as the routine takes it
+    re, im = np.zeros(n), np.zeros(n)
+    ptr = lambda v: v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    got = L.hess_eig_c(n, ptr(a), ptr(re), ptr(im))
+    assert got == n
+    return re + 1j * im
+
+
+def _same_spectrum(ev, ref, tol):
+    """Each computed eigenvalue matched to a distinct reference one (greedy on distance)."""
+    ref = list(ref)
+    for z in ev:
+        k = int(np.argmin([abs(z - r) for r in ref]))
+        assert abs(z - ref[k]) <= tol, (z, ref[k])
+        ref.pop(k)
+
+
+def test_cyclic_shift_needs_the_exceptional_shifts(eig_lib):
+    """The cyclic permutation (ones below the diagonal, one in the corner) is orthogonal with its
+    eigenvalues the n-th roots of unity, all of modulus 1: the standard double shifts leave it
+    unchanged, and only the exceptional shifts move the iteration."""
+    for n in (3, 8, 10, 13):
+        C = np.zeros((n, n))
+        C[np.arange(1, n), np.arange(n - 1)] = 1.0
+        C[0, n - 1] = 1.0
+        ev = _eig(eig_lib, C)
+        _same_spectrum(ev, np.exp(2j * np.pi * np.arange(n) / n), 1e-10)
+
+
+def test_prescribed_spectrum_with_pairs_and_repeats(eig_lib):
+    """A Hessenberg matrix similar to a block-diagonal one with chosen eigenvalues: real ones
+    (one repeated), complex pairs, and values of equal modulus."""
+    import scipy.linalg as sl
+    rng = np.random.default_rng(21)
+    real = [0.5, -1.25, 2.0, 2.0, 3.5, -0.75]
+    pairs = [(1.0, 2.0), (-0.5, 0.75), (0.0, 3.0), (2.0, 0.0001)]
+    blocks = [np.array([[x]]) for x in real] + [np.array([[a, b], [-b, a]]) for a, b in pairs]
+    T = sl.block_diag(*blocks)
+    n = T.shape[0]
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    H = sl.hessenberg(Q @ T @ Q.T)
+    ref = real + [complex(a, s * b) for a, b in pairs for s in (1, -1)]
+    _same_spectrum(_eig(eig_lib, H), ref, 1e-8 * np.abs(ref).max())
+
+
+def test_split_and_small_matrices(eig_lib):
+    """A zero subdiagonal entry splits the problem; 1x1 and 2x2 blocks are solved directly."""
+    rng = np.random.default_rng(5)
+    H = np.triu(rng.standard_normal((9, 9)), -1)
+    H[4, 3] = 0.0
+    _same_spectrum(_eig(eig_lib, H), np.linalg.eigvals(H), 1e-10 * np.abs(H).max() * 9)
+    _same_spectrum(_eig(eig_lib, np.array([[2.5]])), [2.5], 0.0)
+    for M in (np.array([[1.0, 2.0], [-3.0, 1.0]]), np.array([[4.0, 1.0], [2.0, 3.0]])):
+        _same_spectrum(_eig(eig_lib, M), np.linalg.eigvals(M), 1e-13)
